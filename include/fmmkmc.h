@@ -1,0 +1,146 @@
+/*
+ * fmmkmc: FMM electrostatics for kinetic Monte Carlo on AMD MI355X (gfx950).
+ *
+ * Implements the method of Saunders, Grant, Mueller and Thompson, "Fast
+ * electrostatic solvers for kinetic Monte Carlo simulations" (arXiv:1905.04065):
+ * the energy change dU of every proposed single-charge hop (Sec. 3,
+ * Eq. (proposed_energy); periodic boxes Sec. 3.1, Eq. (proposed_energy_sr) plus
+ * the far-field terms of Sec. 3.1) and the incremental update of the expansions
+ * once a hop is accepted (Sec. 3 "Accept move", Sec. 3.1 "Accept move").
+ *
+ * Units: Coulomb constant 1, so the energy of charges q_i, q_j at distance r is
+ * q_i q_j / r.  Positions are in the box [0, a)^3.
+ *
+ * Calling conventions (all entry points):
+ *   - Return FMMKMC_OK (0) or a positive error code below; on error the
+ *     context is unchanged and fmmkmc_last_error() describes the failure.
+ *   - Bulk arrays are DEVICE pointers (HIP global memory on the context's
+ *     device) unless the parameter says "host".  The caller owns every array it
+ *     passes; the library never keeps a pointer to it after the call returns.
+ *   - Work is issued on the context's stream.  fmmkmc_propose_lattice() is
+ *     asynchronous (synchronise the stream before reading dU); every other
+ *     call returns after its results are complete.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef FMMKMC_H
+#define FMMKMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fmmkmc_status {
+    FMMKMC_OK = 0,
+    FMMKMC_EINVAL = 1,      /* bad argument (size, level count, order, index, non-neutral periodic box) */
+    FMMKMC_EDOMAIN = 2,     /* a position outside the box (free space) or off the lattice (lattice mode) */
+    FMMKMC_ECOINCIDENT = 3, /* two charges at one point, or a target on an occupied point */
+    FMMKMC_ECAPACITY = 4,   /* a fine cell holds more charges than cell_capacity */
+    FMMKMC_ESTATE = 5,      /* call out of order (e.g. propose before initialise) */
+    FMMKMC_EHIP = 6,        /* a HIP runtime call failed */
+    FMMKMC_ENOMEM = 7       /* device allocation failed */
+};
+
+enum fmmkmc_bc { FMMKMC_FREE = 0, FMMKMC_PERIODIC = 1 };
+enum fmmkmc_precision { FMMKMC_FP64 = 0, FMMKMC_MIXED = 1 };
+
+typedef struct fmmkmc_ctx fmmkmc_ctx;
+
+/* Solver parameters (Sec. 5.2: the KMCFMM constructor's levels and terms,
+ * Sec. 2.2.1 for the boundary condition). */
+typedef struct fmmkmc_params {
+    double a;          /* box side, > 0 */
+    int bc;            /* FMMKMC_FREE or FMMKMC_PERIODIC (periodic: sum of charges must be 0) */
+    int levels;        /* octree levels L, root = level 1, fine level has 8^(L-1) cells;
+                          free space L >= 2, periodic L >= 3, L <= 10 */
+    int order;         /* expansion order p, 1 <= p <= 16: (p+1)^2 coefficients per expansion */
+    int precision;     /* FMMKMC_FP64, or FMMKMC_MIXED: FP32 fine-level local expansions
+                          (constant term kept in FP64), FP32 near field and L2P with FP32
+                          accumulation; dU subtraction, far field, and all accept-step
+                          updates in FP64 */
+    int lattice_n;     /* 0, or n > 0: every charge sits on a site ((i+1/2)h, (j+1/2)h, (k+1/2)h)
+                          of the n^3 lattice with h = a/n; enables fmmkmc_propose_lattice() */
+    int cell_capacity; /* charge slots per fine cell; 0 picks sites-per-cell (lattice mode)
+                          or 4 x the largest initial occupancy (otherwise) */
+    int device;        /* HIP device ordinal */
+    void *stream;      /* hipStream_t for all work, NULL for the null stream */
+} fmmkmc_params;
+
+/* Create a context for n charges (KMCFMM(positions, charges, r, l), Sec. 5.2).
+ * xyz: n x 3 positions, q: n charges; both HOST arrays, copied.
+ * Errors: EINVAL, EDOMAIN, ECOINCIDENT, ECAPACITY, EHIP, ENOMEM. */
+int fmmkmc_create(const fmmkmc_params *prm, int64_t n, const double *xyz, const double *q,
+                  fmmkmc_ctx **out);
+
+/* Build the octree expansions (Alg. "fmm", App. A; periodic: wrapped
+ * interaction lists and the lattice-sum far field of Sec. 3.1 with the dipole
+ * correction of Sec. 2.2.2 / App. B) and return the total energy (Alg.
+ * "fmm_evaluation" plus the far-field energy) in *U_out (host).  Must precede
+ * every propose / accept call. */
+int fmmkmc_initialise(fmmkmc_ctx *c, double *U_out);
+
+/* propose(P), Sec. 5.2.1: n_groups groups; group g moves charge idx[g] to each
+ * of the targets offs[g] .. offs[g+1]-1 (CSR, offs has n_groups+1 entries,
+ * offs[0] = 0).  targets: offs[n_groups] x 3, dU: offs[n_groups] outputs.
+ * idx, offs, targets, dU are device arrays.  Periodic targets are wrapped into
+ * the box.  A slot whose target lies outside the box (free space) gets NaN and
+ * the call returns EDOMAIN; a target on an occupied point gets NaN and the call
+ * returns ECOINCIDENT (other slots are still valid). */
+int fmmkmc_propose(fmmkmc_ctx *c, int64_t n_groups, const int64_t *idx, const int64_t *offs,
+                   const double *targets, double *dU);
+
+/* propose_with_dats(C, T, R, M, U), App. C: every charge i has type T[i] in
+ * [0, n_types) and may hop to the first C[T[i]] of its K candidate targets
+ * R[i][0..K-1] (N x 3K doubles); M[i][k] = 1 allows the hop, 0 forbids it.
+ * U[i][k] (N x K) receives dU; forbidden entries and entries with
+ * k >= C[T[i]] are "undefined" in the paper and are written as NaN here.
+ * C (n_types entries) is a HOST array; T, R, M, U are device arrays. */
+int fmmkmc_propose_dats(fmmkmc_ctx *c, int K, const int32_t *C, int n_types, const int32_t *T,
+                        const double *R, const uint8_t *M, double *U);
+
+/* Lattice fast path (requires lattice_n > 0): for every charge i and hop k the
+ * target is the site at lattice offset offsets[k] (K x 3 HOST ints, |entries| <= 1)
+ * from the charge's site, wrapped in periodic boxes.  dU (N x K, device) gets
+ * the energy change; slots whose target is occupied or (free space) off the
+ * lattice are masked: dU = NaN and mask[i][k] = 0 (mask is an optional N x K
+ * device array, valid slots 1).  Asynchronous on the context's stream. */
+int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double *dU, uint8_t *mask);
+
+/* accept((i, r')), Sec. 5.2.2: move charge i to new_xyz (HOST, 3 doubles;
+ * wrapped in periodic boxes).  dU is recomputed for the move (footnote to
+ * Sec. 3.1) and returned in *dU_out (host); then every fine-level local
+ * expansion, the multipole expansions of the moved charge's cells on every
+ * level, and the far-field coefficients are updated, and U += dU.
+ * Errors: EINVAL (bad i), EDOMAIN, ECOINCIDENT (target occupied), ECAPACITY. */
+int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_out);
+
+/* Current total energy (initial energy plus the accepted dU's), host. */
+int fmmkmc_energy(fmmkmc_ctx *c, double *U);
+
+/* Current positions, n x 3 device array. */
+int fmmkmc_positions(fmmkmc_ctx *c, double *xyz);
+
+/* Electrostatic potential at m points (device m x 3 array) from every charge
+ * except exclude[j] (device, -1 for none): local expansion + near field (+ far
+ * field in periodic boxes); out: m device doubles.  Used to check the
+ * expansions and the energy. */
+int fmmkmc_potential(fmmkmc_ctx *c, int64_t m, const double *xyz, const int64_t *exclude, double *out);
+
+/* Per-kernel timing: when on, every kernel launch is bracketed by HIP events
+ * on the context's stream.  fmmkmc_kernel_time() returns the accumulated time
+ * (ms) and launch count of the named kernel since profiling was switched on. */
+int fmmkmc_set_profiling(fmmkmc_ctx *c, int on);
+int fmmkmc_kernel_time(fmmkmc_ctx *c, const char *name, double *ms, int64_t *launches);
+
+/* Text of the last error on this context (static storage owned by it). */
+const char *fmmkmc_last_error(fmmkmc_ctx *c);
+
+/* Free the context and all its device memory. */
+int fmmkmc_destroy(fmmkmc_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,888 @@
+// C-ABI of the fmmkmc library (declared in include/fmmkmc.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace fmmkmc;
+
+namespace {
+
+struct HipError {
+    std::string what;
+};
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+int fail(fmmkmc_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+template <typename T>
+T *dalloc(size_t count)
+{
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(T) * count);
+    if (e != hipSuccess) throw std::bad_alloc();
+    return (T *)p;
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+template <typename T>
+void upload(T *dst, const T *src, size_t count, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s));
+}
+
+// scratch buffer of at least `bytes`
+void *scratch(fmmkmc_ctx *c, size_t bytes)
+{
+    if (c->scr_bytes < bytes) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        dfree(c->scr);
+        c->scr = dalloc<double>((bytes + 7) / 8);
+        c->scr_bytes = ((bytes + 7) / 8) * 8;
+    }
+    return c->scr;
+}
+
+double lattice_h(const fmmkmc_ctx *c) { return c->a / c->lat_n; }
+
+// lattice index of a position, -1 if it is not a site
+int64_t site_of(const fmmkmc_ctx *c, const double *p)
+{
+    const int n = c->lat_n;
+    const double h = lattice_h(c);
+    int idx[3];
+    for (int d = 0; d < 3; ++d) {
+        const double u = p[d] / h - 0.5;
+        const double r = std::nearbyint(u);
+        if (r < 0 || r >= n) return -1;
+        if ((r + 0.5) * h != p[d]) return -1;
+        idx[d] = (int)r;
+    }
+    return ((int64_t)idx[0] * n + idx[1]) * n + idx[2];
+}
+
+void fine_of(const fmmkmc_ctx *c, const double *p, int g[3])
+{
+    const double w = c->a / c->nc;
+    for (int d = 0; d < 3; ++d) g[d] = fine_coord(p[d], w, c->nc);
+}
+
+void release(fmmkmc_ctx *c)
+{
+    dfree(c->x);
+    dfree(c->y);
+    dfree(c->z);
+    dfree(c->q);
+    dfree(c->cell);
+    dfree(c->slot);
+    dfree(c->site);
+    dfree(c->cell_cnt);
+    dfree(c->cell_slots);
+    dfree(c->site_charge);
+    dfree(c->qsite);
+    dfree(c->qsite32);
+    for (auto &p : c->phi_lv) dfree(p);
+    for (auto &p : c->psi_lv) dfree(p);
+    dfree(c->d_phi_ptrs);
+    dfree(c->psi32);
+    dfree(c->phisite);
+    for (auto &p : c->m2m) dfree(p);
+    for (auto &p : c->l2l) dfree(p);
+    dfree(c->m2l);
+    dfree(c->m2l_index);
+    dfree(c->scale);
+    dfree(c->Y2);
+    dfree(c->T2);
+    dfree(c->Y2f);
+    dfree(c->T2f);
+    dfree(c->far.H);
+    dfree(c->far.R);
+    dfree(c->far.G);
+    dfree(c->far.C);
+    dfree(c->far.Bz);
+    dfree(c->far.Tax);
+    dfree(c->far.sigma);
+    c->far.K = nullptr;  // alias of phi_lv[1]
+    dfree(c->F);
+    dfree(c->d_offsets);
+    dfree(c->scr);
+    dfree(c->flags);
+    dfree(c->red);
+    dfree(c->iota);
+    dfree(c->acc_buf);
+    for (auto &pd : c->prof.pending) {
+        (void)hipEventDestroy(pd.a);
+        (void)hipEventDestroy(pd.b);
+    }
+    c->prof.pending.clear();
+}
+
+void build_operators(fmmkmc_ctx *c)
+{
+    const int p = c->p, nt = c->nt, L = c->L;
+    std::vector<double> mat((size_t)nt * nt), tr((size_t)nt * nt);
+    auto transpose = [&](const double *src, double *dst) {
+        for (int k = 0; k < nt; ++k)
+            for (int n = 0; n < nt; ++n) dst[(size_t)n * nt + k] = src[(size_t)k * nt + n];
+    };
+    c->m2m.assign(L + 1, nullptr);
+    c->l2l.assign(L + 1, nullptr);
+    std::vector<double> all((size_t)8 * nt * nt);
+    for (int l = 1; l <= L; ++l) {
+        const double wc = c->a / (1 << l);  // child width (level l + 1)
+        if (l <= L - 1) {
+            for (int ch = 0; ch < 8; ++ch) {
+                const int ox = ch >> 2, oy = (ch >> 1) & 1, oz = ch & 1;
+                build_m2m(p, (ox - 0.5) * wc, (oy - 0.5) * wc, (oz - 0.5) * wc, mat.data());
+                transpose(mat.data(), all.data() + (size_t)ch * nt * nt);
+            }
+            c->m2m[l] = dalloc<double>(all.size());
+            upload(c->m2m[l], all.data(), all.size(), c->stream);
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
+        if (l >= 2) {
+            const double w = c->a / (1 << (l - 1));  // width at level l
+            for (int ch = 0; ch < 8; ++ch) {
+                const int ox = ch >> 2, oy = (ch >> 1) & 1, oz = ch & 1;
+                build_l2l(p, (ox - 0.5) * w, (oy - 0.5) * w, (oz - 0.5) * w, mat.data());
+                transpose(mat.data(), all.data() + (size_t)ch * nt * nt);
+            }
+            c->l2l[l] = dalloc<double>(all.size());
+            upload(c->l2l[l], all.data(), all.size(), c->stream);
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
+    }
+    // M2L for unit width, keyed by d = target - source in {-3..3}^3 \ {-1..1}^3
+    std::vector<int32_t> index(343, -1);
+    std::vector<double> m2l;
+    int o = 0;
+    for (int dx = -3; dx <= 3; ++dx)
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dz = -3; dz <= 3; ++dz) {
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                index[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)] = o++;
+            }
+    m2l.resize((size_t)o * nt * nt);
+    for (int dx = -3; dx <= 3; ++dx)
+        for (int dy = -3; dy <= 3; ++dy)
+            for (int dz = -3; dz <= 3; ++dz) {
+                const int id = index[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)];
+                if (id < 0) continue;
+                build_m2l(p, dx, dy, dz, mat.data());
+                transpose(mat.data(), m2l.data() + (size_t)id * nt * nt);
+            }
+    c->m2l = dalloc<double>(m2l.size());
+    upload(c->m2l, m2l.data(), m2l.size(), c->stream);
+    c->m2l_index = dalloc<int32_t>(343);
+    upload(c->m2l_index, index.data(), 343, c->stream);
+    // per-level scales of the unit-width M2L: input w^-deg(n), output w^-(deg(k)+1)
+    std::vector<double> sc((size_t)2 * (L + 1) * nt, 0.0);
+    for (int l = 1; l <= L; ++l) {
+        const double w = c->a / (1 << (l - 1));
+        for (int n = 0; n <= p; ++n)
+            for (int k = n * n; k < (n + 1) * (n + 1); ++k) {
+                sc[(size_t)(2 * l) * nt + k] = std::pow(w, -n);
+                sc[(size_t)(2 * l + 1) * nt + k] = std::pow(w, -(n + 1.0));
+            }
+    }
+    c->scale = dalloc<double>(sc.size());
+    upload(c->scale, sc.data(), sc.size(), c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+void build_far(fmmkmc_ctx *c)
+{
+    const int p = c->p, nt = c->nt, q = p + 1;
+    std::vector<double> R((size_t)nt * nt), RT((size_t)nt * nt);
+    build_far_operator(p, c->a, R.data());
+    for (int k = 0; k < nt; ++k)
+        for (int n = 0; n < nt; ++n) RT[(size_t)n * nt + k] = R[(size_t)k * nt + n];
+    c->far.R = dalloc<double>(RT.size());
+    upload(c->far.R, RT.data(), RT.size(), c->stream);
+    std::vector<double> G((size_t)q * q * q * nt);
+    build_cheb_map(p, c->a, G.data());
+    c->far.G = dalloc<double>(G.size());
+    upload(c->far.G, G.data(), G.size(), c->stream);
+    c->far.C = dalloc<double>((size_t)q * q * q);
+    c->far.H = dalloc<double>(nt);
+    c->far.K = c->phi_lv[1];
+    if (c->lat_n > 0) {
+        const int n = c->lat_n;
+        std::vector<double> Tax((size_t)n * q);
+        const double h = lattice_h(c);
+        for (int i = 0; i < n; ++i) {
+            const double xi = ((i + 0.5) * h - 0.5 * c->a) / (0.5 * c->a);
+            double t0 = 1.0, t1 = xi;
+            for (int aa = 0; aa < q; ++aa) {
+                double v = aa == 0 ? 1.0 : (aa == 1 ? xi : 2.0 * xi * t1 - t0);
+                if (aa >= 2) {
+                    t0 = t1;
+                    t1 = v;
+                }
+                Tax[(size_t)i * q + aa] = v;
+            }
+        }
+        c->far.Tax = dalloc<double>(Tax.size());
+        upload(c->far.Tax, Tax.data(), Tax.size(), c->stream);
+        c->far.Bz = dalloc<double>((size_t)n * n * q);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const double *qv, fmmkmc_ctx *c)
+{
+    if (!prm || !xyz || !qv) return fail(c, FMMKMC_EINVAL, "null argument");
+    if (!(prm->a > 0)) return fail(c, FMMKMC_EINVAL, "box side a must be > 0");
+    if (prm->bc != FMMKMC_FREE && prm->bc != FMMKMC_PERIODIC) return fail(c, FMMKMC_EINVAL, "bc must be 0 or 1");
+    const int minL = prm->bc == FMMKMC_PERIODIC ? 3 : 2;
+    if (prm->levels < minL || prm->levels > kMaxLevels)
+        return fail(c, FMMKMC_EINVAL, "levels out of range (free >= 2, periodic >= 3, <= 10)");
+    if (prm->order < 1 || prm->order > kMaxOrder) return fail(c, FMMKMC_EINVAL, "order must be in 1..16");
+    if (prm->precision != FMMKMC_FP64 && prm->precision != FMMKMC_MIXED)
+        return fail(c, FMMKMC_EINVAL, "precision must be 0 or 1");
+    if (prm->lattice_n < 0 || prm->cell_capacity < 0) return fail(c, FMMKMC_EINVAL, "negative lattice_n/capacity");
+    if (n < 1 || n > (int64_t)1 << 30) return fail(c, FMMKMC_EINVAL, "charge count out of range");
+    c->a = prm->a;
+    c->bc = prm->bc;
+    c->L = prm->levels;
+    c->p = prm->order;
+    c->nt = nterms(c->p);
+    c->prec = prm->precision;
+    c->lat_n = prm->lattice_n;
+    c->device = prm->device;
+    c->stream = (hipStream_t)prm->stream;
+    c->N = n;
+    c->nc = 1 << (c->L - 1);
+    c->M = (int64_t)c->nc * c->nc * c->nc;
+    if (c->lat_n > 0) {
+        c->h = lattice_h(c);
+        if ((int64_t)c->lat_n * c->lat_n * c->lat_n > ((int64_t)1 << 31) - 1)
+            return fail(c, FMMKMC_EINVAL, "lattice too large");
+    }
+    HIPCHK(hipSetDevice(c->device));
+    // host copies; periodic positions wrapped into the box
+    c->hx.resize(n);
+    c->hy.resize(n);
+    c->hz.resize(n);
+    c->hq.assign(qv, qv + n);
+    double qsum = 0, qabs = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double p3[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+        for (int d = 0; d < 3; ++d) {
+            if (!std::isfinite(p3[d])) return fail(c, FMMKMC_EDOMAIN, "non-finite position");
+            if (c->bc == FMMKMC_PERIODIC)
+                p3[d] = wrap_coord(p3[d], c->a);
+            else if (!(p3[d] >= 0.0 && p3[d] < c->a))
+                return fail(c, FMMKMC_EDOMAIN, "charge " + std::to_string(i) + " outside the box");
+        }
+        if (!std::isfinite(qv[i])) return fail(c, FMMKMC_EINVAL, "non-finite charge");
+        c->hx[i] = p3[0];
+        c->hy[i] = p3[1];
+        c->hz[i] = p3[2];
+        qsum += qv[i];
+        qabs += std::fabs(qv[i]);
+    }
+    if (c->bc == FMMKMC_PERIODIC && std::fabs(qsum) > 1e-12 * std::max(1.0, qabs))
+        return fail(c, FMMKMC_EINVAL, "periodic box must be neutral");
+    // cells, sites, capacity
+    c->hcell.resize(n);
+    c->hsite.assign(n, -1);
+    std::vector<int32_t> count(c->M, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        double p3[3] = {c->hx[i], c->hy[i], c->hz[i]};
+        int g[3];
+        fine_of(c, p3, g);
+        c->hcell[i] = (int32_t)cell_id(c->nc, g[0], g[1], g[2]);
+        count[c->hcell[i]]++;
+    }
+    if (c->lat_n > 0) {
+        const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+        c->hsite_charge.assign(ns, -1);
+        for (int64_t i = 0; i < n; ++i) {
+            double p3[3] = {c->hx[i], c->hy[i], c->hz[i]};
+            const int64_t s = site_of(c, p3);
+            if (s < 0) return fail(c, FMMKMC_EDOMAIN, "charge " + std::to_string(i) + " is not on a lattice site");
+            if (c->hsite_charge[s] >= 0) return fail(c, FMMKMC_ECOINCIDENT, "two charges on one site");
+            c->hsite_charge[s] = (int32_t)i;
+            c->hsite[i] = (int32_t)s;
+        }
+        // sites per cell along one axis
+        std::vector<int> per(c->nc, 0);
+        const double w = c->a / c->nc;
+        for (int i = 0; i < c->lat_n; ++i) per[fine_coord((i + 0.5) * c->h, w, c->nc)]++;
+        const int mx = *std::max_element(per.begin(), per.end());
+        c->cap = prm->cell_capacity > 0 ? prm->cell_capacity : mx * mx * mx;
+        c->s2 = (c->lat_n == 2 * c->nc);
+    } else {
+        const int mx = *std::max_element(count.begin(), count.end());
+        c->cap = prm->cell_capacity > 0 ? prm->cell_capacity : std::max(8, 4 * mx);
+    }
+    int mxc = *std::max_element(count.begin(), count.end());
+    if (mxc > c->cap) return fail(c, FMMKMC_ECAPACITY, "a fine cell holds more charges than cell_capacity");
+    c->hcnt.assign(c->M, 0);
+    c->hslots.assign((size_t)c->M * c->cap, -1);
+    c->hslot.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t cl = c->hcell[i];
+        c->hslot[i] = c->hcnt[cl];
+        c->hslots[(size_t)cl * c->cap + c->hcnt[cl]] = (int32_t)i;
+        c->hcnt[cl]++;
+    }
+    if (c->lat_n == 0) {
+        // exact coincidences within a cell
+        for (int64_t cl = 0; cl < c->M; ++cl)
+            for (int a = 0; a < c->hcnt[cl]; ++a)
+                for (int b = a + 1; b < c->hcnt[cl]; ++b) {
+                    const int i = c->hslots[cl * c->cap + a], j = c->hslots[cl * c->cap + b];
+                    if (c->hx[i] == c->hx[j] && c->hy[i] == c->hy[j] && c->hz[i] == c->hz[j])
+                        return fail(c, FMMKMC_ECOINCIDENT, "two charges at one point");
+                }
+    }
+    // device state
+    const hipStream_t s = c->stream;
+    c->x = dalloc<double>(n);
+    c->y = dalloc<double>(n);
+    c->z = dalloc<double>(n);
+    c->q = dalloc<double>(n);
+    upload(c->x, c->hx.data(), n, s);
+    upload(c->y, c->hy.data(), n, s);
+    upload(c->z, c->hz.data(), n, s);
+    upload(c->q, c->hq.data(), n, s);
+    c->cell = dalloc<int32_t>(n);
+    c->slot = dalloc<int32_t>(n);
+    c->site = dalloc<int32_t>(n);
+    upload(c->cell, c->hcell.data(), n, s);
+    upload(c->slot, c->hslot.data(), n, s);
+    upload(c->site, c->hsite.data(), n, s);
+    c->cell_cnt = dalloc<int32_t>(c->M);
+    c->cell_slots = dalloc<int32_t>((size_t)c->M * c->cap);
+    upload(c->cell_cnt, c->hcnt.data(), c->M, s);
+    upload(c->cell_slots, c->hslots.data(), (size_t)c->M * c->cap, s);
+    {
+        std::vector<int64_t> io(n);
+        for (int64_t i = 0; i < n; ++i) io[i] = i;
+        c->iota = dalloc<int64_t>(n);
+        upload(c->iota, io.data(), n, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    c->phi_lv.assign(c->L + 1, nullptr);
+    c->psi_lv.assign(c->L + 1, nullptr);
+    for (int l = 1; l <= c->L; ++l) {
+        const int64_t ml = (int64_t)1 << (3 * (l - 1));
+        c->phi_lv[l] = dalloc<double>((size_t)ml * c->nt);
+        c->psi_lv[l] = dalloc<double>((size_t)ml * c->nt);
+        HIPCHK(hipMemsetAsync(c->psi_lv[l], 0, sizeof(double) * ml * c->nt, s));
+    }
+    c->d_phi_ptrs = dalloc<double *>(c->L + 1);
+    upload(c->d_phi_ptrs, c->phi_lv.data(), c->L + 1, s);
+    if (c->prec == FMMKMC_MIXED) c->psi32 = dalloc<float>((size_t)c->M * c->nt);
+    if (c->lat_n > 0) {
+        const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+        c->site_charge = dalloc<int32_t>(ns);
+        upload(c->site_charge, c->hsite_charge.data(), ns, s);
+        c->phisite = dalloc<double>(ns);
+        if (c->s2) {
+            std::vector<double> qs(ns, 0.0);
+            std::vector<float> qs32(ns, 0.0f);
+            for (int64_t i = 0; i < n; ++i) {
+                const int64_t st = c->hsite[i];
+                const int si = (int)(st / ((int64_t)c->lat_n * c->lat_n)), sj = (int)((st / c->lat_n) % c->lat_n),
+                          sk = (int)(st % c->lat_n);
+                const int64_t cm = s2_site(c->nc, si, sj, sk);
+                qs[cm] = c->hq[i];
+                qs32[cm] = (float)c->hq[i];
+            }
+            c->qsite = dalloc<double>(ns);
+            upload(c->qsite, qs.data(), ns, s);
+            if (c->prec == FMMKMC_MIXED) {
+                c->qsite32 = dalloc<float>(ns);
+                upload(c->qsite32, qs32.data(), ns, s);
+            }
+            std::vector<double> Y2((size_t)8 * c->nt), T2(8 * 216);
+            build_s2_tables(c->p, c->h, Y2.data(), T2.data());
+            c->Y2 = dalloc<double>(Y2.size());
+            c->T2 = dalloc<double>(T2.size());
+            upload(c->Y2, Y2.data(), Y2.size(), s);
+            upload(c->T2, T2.data(), T2.size(), s);
+            std::vector<float> Yf(Y2.begin(), Y2.end()), Tf(T2.begin(), T2.end());
+            c->Y2f = dalloc<float>(Yf.size());
+            c->T2f = dalloc<float>(Tf.size());
+            upload(c->Y2f, Yf.data(), Yf.size(), s);
+            upload(c->T2f, Tf.data(), Tf.size(), s);
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    c->flags = dalloc<int32_t>(4);
+    c->red = dalloc<double>(4096);
+    c->acc_buf = dalloc<double>(32);
+    build_operators(c);
+    if (c->bc == FMMKMC_PERIODIC) build_far(c);
+    HIPCHK(hipStreamSynchronize(s));
+    return FMMKMC_OK;
+}
+
+// energy partial sums of 1/2 q_i phi_i per block
+__global__ void k_energy_partials(int64_t n, const double *__restrict__ q, const double *__restrict__ phi,
+                                  double *__restrict__ partials)
+{
+    __shared__ double sm[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += 0.5 * q[i] * phi[i];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+}
+
+__global__ void k_interleave(int64_t n, const double *x, const double *y, const double *z, double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[3 * i] = x[i];
+    out[3 * i + 1] = y[i];
+    out[3 * i + 2] = z[i];
+}
+
+// message of the last failed fmmkmc_create on this thread
+std::string &create_error()
+{
+    static thread_local std::string msg;
+    return msg;
+}
+
+int read_flags(fmmkmc_ctx *c, int32_t *out)
+{
+    HIPCHK(hipMemcpyAsync(out, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+void clear_flags(fmmkmc_ctx *c) { HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int32_t) * 4, c->stream)); }
+
+}  // namespace
+
+namespace fmmkmc {
+
+Geo make_geo(const fmmkmc_ctx *c)
+{
+    Geo g;
+    g.a = c->a;
+    g.w = c->a / c->nc;
+    g.h = c->h;
+    g.nc = c->nc;
+    g.n = c->lat_n;
+    g.periodic = c->bc == FMMKMC_PERIODIC ? 1 : 0;
+    g.cap = c->cap;
+    return g;
+}
+
+void Profiler::resolve()
+{
+    for (auto &pd : pending) {
+        (void)hipEventSynchronize(pd.b);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, pd.a, pd.b);
+        auto &t = total[pd.name];
+        t.first += ms;
+        t.second += 1;
+        (void)hipEventDestroy(pd.a);
+        (void)hipEventDestroy(pd.b);
+    }
+    pending.clear();
+}
+
+}  // namespace fmmkmc
+
+#define API_GUARD(c, ...)                                            \
+    try {                                                            \
+        __VA_ARGS__                                                  \
+    } catch (const HipError &e) {                                    \
+        return fail(c, FMMKMC_EHIP, e.what);                         \
+    } catch (const std::bad_alloc &) {                               \
+        return fail(c, FMMKMC_ENOMEM, "device or host allocation failed"); \
+    }
+
+extern "C" {
+
+int fmmkmc_create(const fmmkmc_params *prm, int64_t n, const double *xyz, const double *q, fmmkmc_ctx **out)
+{
+    if (!out) return FMMKMC_EINVAL;
+    *out = nullptr;
+    fmmkmc_ctx *c = new (std::nothrow) fmmkmc_ctx();
+    if (!c) return FMMKMC_ENOMEM;
+    int rc;
+    try {
+        rc = create_impl(prm, n, xyz, q, c);
+    } catch (const HipError &e) {
+        rc = fail(c, FMMKMC_EHIP, e.what);
+    } catch (const std::bad_alloc &) {
+        rc = fail(c, FMMKMC_ENOMEM, "device or host allocation failed");
+    }
+    if (rc != FMMKMC_OK) {
+        create_error() = c->err;
+        release(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return FMMKMC_OK;
+}
+
+int fmmkmc_initialise(fmmkmc_ctx *c, double *U_out)
+{
+    if (!c) return FMMKMC_EINVAL;
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        const Geo g = make_geo(c);
+        launch_p2m(c, g);
+        launch_upward(c);
+        launch_downward(c);
+        if (c->prec == FMMKMC_MIXED) launch_shadow(c);
+        if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c);
+        double *phi = (double *)scratch(c, sizeof(double) * c->N);
+        launch_point_phi(c, g, c->N, nullptr, c->iota, c->iota, c->bc == FMMKMC_PERIODIC ? 1 : 0, phi,
+                         "point_phi_energy");
+        const int nb = 1024;
+        launch(c, "energy_partials", k_energy_partials, dim3(nb), dim3(256), c->N, c->q, phi, c->red);
+        std::vector<double> part(nb);
+        HIPCHK(hipMemcpyAsync(part.data(), c->red, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double U = 0.0;
+        for (double v : part) U += v;
+        c->U = U;
+        c->initialised = true;
+        c->F_offsets.clear();
+        if (U_out) *U_out = U;
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_propose(fmmkmc_ctx *c, int64_t n_groups, const int64_t *idx, const int64_t *offs, const double *targets,
+                   double *dU)
+{
+    if (!c) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "propose before initialise");
+    if (n_groups < 0 || (n_groups > 0 && (!idx || !offs || !targets || !dU)))
+        return fail(c, FMMKMC_EINVAL, "bad propose arguments");
+    if (n_groups == 0) return FMMKMC_OK;
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        // the CSR drives device writes: check it on the host first
+        std::vector<int64_t> hoffs(n_groups + 1);
+        HIPCHK(hipMemcpyAsync(hoffs.data(), offs, sizeof(int64_t) * (n_groups + 1), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (hoffs[0] != 0) return fail(c, FMMKMC_EINVAL, "offs[0] must be 0");
+        for (int64_t g2 = 0; g2 < n_groups; ++g2)
+            if (hoffs[g2 + 1] < hoffs[g2]) return fail(c, FMMKMC_EINVAL, "offs must be non-decreasing");
+        const int64_t S = hoffs[n_groups];
+        if (S == 0) return FMMKMC_OK;
+        std::vector<int64_t> hidx(n_groups);
+        HIPCHK(hipMemcpyAsync(hidx.data(), idx, sizeof(int64_t) * n_groups, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int64_t v : hidx)
+            if (v < 0 || v >= c->N) return fail(c, FMMKMC_EINVAL, "charge index out of range");
+        const size_t bytes = sizeof(double) * 8 * S + sizeof(int64_t) * S;
+        double *work = (double *)scratch(c, bytes);
+        int64_t *charge = (int64_t *)(work + 8 * S);
+        clear_flags(c);
+        const Geo g = make_geo(c);
+        launch_expand_groups(c, n_groups, idx, offs, charge);
+        launch_generic(c, g, S, targets, charge, dU, work);
+        int32_t fl = 0;
+        read_flags(c, &fl);
+        if (fl & 1) return fail(c, FMMKMC_EDOMAIN, "a target lies outside the box (NaN written)");
+        if (fl & 2) return fail(c, FMMKMC_ECOINCIDENT, "a target coincides with a charge (NaN written)");
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_propose_dats(fmmkmc_ctx *c, int K, const int32_t *C, int n_types, const int32_t *T, const double *R,
+                        const uint8_t *Mk, double *U)
+{
+    if (!c) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "propose before initialise");
+    if (K < 0 || n_types < 1 || !C || !T || !R || !Mk || !U) return fail(c, FMMKMC_EINVAL, "bad dats arguments");
+    for (int t = 0; t < n_types; ++t)
+        if (C[t] < 0 || C[t] > K) return fail(c, FMMKMC_EINVAL, "C[t] must be in 0..K");
+    if (K == 0) return FMMKMC_OK;
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        const int64_t S = c->N * K;
+        const size_t bytes = sizeof(double) * 8 * S + sizeof(int64_t) * S + sizeof(int32_t) * (S + n_types);
+        double *work = (double *)scratch(c, bytes);
+        int64_t *charge = (int64_t *)(work + 8 * S);
+        int32_t *use = (int32_t *)(charge + S);
+        int32_t *dC = use + S;
+        upload(dC, C, n_types, c->stream);
+        clear_flags(c);
+        const Geo g = make_geo(c);
+        launch_dats_select(c, c->N, K, dC, n_types, T, Mk, use);
+        // every slot (i, k) is a proposal of charge i; unused slots come out as NaN
+        launch_div_index(c, S, K, charge);
+        launch_generic(c, g, S, R, charge, U, work, use);
+        int32_t fl = 0;
+        read_flags(c, &fl);
+        if (fl & 4) return fail(c, FMMKMC_EINVAL, "a particle type is out of range");
+        if (fl & 1) return fail(c, FMMKMC_EDOMAIN, "an allowed target lies outside the box (NaN written)");
+        if (fl & 2) return fail(c, FMMKMC_ECOINCIDENT, "an allowed target coincides with a charge (NaN written)");
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double *dU, uint8_t *mask)
+{
+    if (!c) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "propose before initialise");
+    if (c->lat_n <= 0) return fail(c, FMMKMC_ESTATE, "context was not created in lattice mode");
+    if (K < 1 || !offsets || !dU) return fail(c, FMMKMC_EINVAL, "bad lattice proposal arguments");
+    for (int k = 0; k < 3 * K; ++k)
+        if (offsets[k] < -1 || offsets[k] > 1) return fail(c, FMMKMC_EINVAL, "hop offsets must be in -1..1");
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        const Geo g = make_geo(c);
+        std::vector<int32_t> off(offsets, offsets + 3 * K);
+        if (off != c->F_offsets) {
+            dfree(c->d_offsets);
+            c->d_offsets = dalloc<int32_t>(3 * K);
+            upload(c->d_offsets, off.data(), 3 * K, c->stream);
+            c->d_offsets_K = K;
+            if (c->bc == FMMKMC_PERIODIC) {
+                if (!c->far.sigma) {
+                    const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+                    c->far.sigma = dalloc<double>(ns);
+                    launch_sigma(c, g);
+                }
+                dfree(c->F);
+                c->F = dalloc<double>((size_t)c->N * K);
+                launch_f_rows(c, g, c->N, nullptr, K);
+            }
+            c->F_offsets = off;
+        }
+        launch_site_phi(c, g);
+        launch_slot_lattice(c, g, K, dU, mask);
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_out)
+{
+    if (!c) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "accept before initialise");
+    if (i < 0 || i >= c->N || !new_xyz) return fail(c, FMMKMC_EINVAL, "bad charge index or position");
+    double np[3];
+    for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(new_xyz[d])) return fail(c, FMMKMC_EDOMAIN, "non-finite position");
+        if (c->bc == FMMKMC_PERIODIC)
+            np[d] = wrap_coord(new_xyz[d], c->a);
+        else if (!(new_xyz[d] >= 0.0 && new_xyz[d] < c->a))
+            return fail(c, FMMKMC_EDOMAIN, "new position outside the box");
+        else
+            np[d] = new_xyz[d];
+    }
+    const double op[3] = {c->hx[i], c->hy[i], c->hz[i]};
+    int og[3], ng[3];
+    fine_of(c, op, og);
+    fine_of(c, np, ng);
+    const int64_t old_cell = c->hcell[i], new_cell = cell_id(c->nc, ng[0], ng[1], ng[2]);
+    int64_t old_site = -1, new_site = -1;
+    if (c->lat_n > 0) {
+        old_site = c->hsite[i];
+        new_site = site_of(c, np);
+        if (new_site < 0) return fail(c, FMMKMC_EDOMAIN, "new position is not a lattice site");
+        if (c->hsite_charge[new_site] >= 0) return fail(c, FMMKMC_ECOINCIDENT, "target site is occupied");
+    } else {
+        for (int k = 0; k < c->hcnt[new_cell]; ++k) {
+            const int j = c->hslots[(size_t)new_cell * c->cap + k];
+            if (c->hx[j] == np[0] && c->hy[j] == np[1] && c->hz[j] == np[2])
+                return fail(c, FMMKMC_ECOINCIDENT, "target coincides with a charge");
+        }
+    }
+    if (new_cell != old_cell && c->hcnt[new_cell] >= c->cap)
+        return fail(c, FMMKMC_ECAPACITY, "target cell is full");
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        const Geo g = make_geo(c);
+        // C1: dU of the move (footnote to Sec. 3.1); acc_buf holds the generic
+        // pipeline's work area (8 doubles), dU, the charge index and the target
+        double *work = c->acc_buf;
+        double *dUd = work + 8;
+        int64_t *charge = (int64_t *)(work + 9);
+        double *tgt = work + 10;
+        {
+            double hbuf[3] = {np[0], np[1], np[2]};
+            int64_t hi = i;
+            HIPCHK(hipMemcpyAsync(tgt, hbuf, sizeof(hbuf), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(charge, &hi, sizeof(hi), hipMemcpyHostToDevice, c->stream));
+            clear_flags(c);
+            launch_generic(c, g, 1, tgt, charge, dUd, work);
+            double dUh = 0;
+            HIPCHK(hipMemcpyAsync(&dUh, dUd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if (!std::isfinite(dUh)) return fail(c, FMMKMC_ECOINCIDENT, "singular move");
+            if (dU_out) *dU_out = dUh;
+            c->U += dUh;
+        }
+        // C2 + C3
+        CommitArgs a;
+        a.i = i;
+        std::memcpy(a.old_pos, op, sizeof(op));
+        std::memcpy(a.new_pos, np, sizeof(np));
+        a.q = c->hq[i];
+        std::memcpy(a.old_g, og, sizeof(og));
+        std::memcpy(a.new_g, ng, sizeof(ng));
+        a.old_cell = old_cell;
+        a.new_cell = new_cell;
+        a.old_slot = c->hslot[i];
+        a.moved_j = -1;
+        a.new_slot = c->hslot[i];
+        a.old_cnt = c->hcnt[old_cell];
+        a.new_cnt = c->hcnt[new_cell];
+        if (new_cell != old_cell) {
+            const int last = c->hcnt[old_cell] - 1;
+            const int jlast = c->hslots[(size_t)old_cell * c->cap + last];
+            a.moved_j = (jlast != i) ? jlast : -1;
+            a.old_cnt = last;
+            a.new_slot = c->hcnt[new_cell];
+            a.new_cnt = c->hcnt[new_cell] + 1;
+        }
+        a.old_site = old_site;
+        a.new_site = new_site;
+        a.old_site_s2 = a.new_site_s2 = -1;
+        if (c->s2) {
+            const int n = c->lat_n;
+            a.old_site_s2 = s2_site(c->nc, (int)(old_site / ((int64_t)n * n)), (int)((old_site / n) % n),
+                                    (int)(old_site % n));
+            a.new_site_s2 = s2_site(c->nc, (int)(new_site / ((int64_t)n * n)), (int)((new_site / n) % n),
+                                    (int)(new_site % n));
+        }
+        launch_commit(c, g, a);
+        if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c);
+        // host mirrors
+        c->hx[i] = np[0];
+        c->hy[i] = np[1];
+        c->hz[i] = np[2];
+        if (new_cell != old_cell) {
+            if (a.moved_j >= 0) {
+                c->hslots[(size_t)old_cell * c->cap + a.old_slot] = a.moved_j;
+                c->hslot[a.moved_j] = a.old_slot;
+            }
+            c->hslots[(size_t)old_cell * c->cap + a.old_cnt] = -1;
+            c->hcnt[old_cell] = a.old_cnt;
+            c->hslots[(size_t)new_cell * c->cap + a.new_slot] = (int32_t)i;
+            c->hcnt[new_cell] = a.new_cnt;
+            c->hcell[i] = (int32_t)new_cell;
+            c->hslot[i] = a.new_slot;
+        }
+        if (c->lat_n > 0) {
+            c->hsite_charge[old_site] = -1;
+            c->hsite_charge[new_site] = (int32_t)i;
+            c->hsite[i] = (int32_t)new_site;
+        }
+        // lattice proposal table row of the moved charge
+        if (c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty()) {
+            HIPCHK(hipMemcpyAsync(charge, &i, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+            launch_f_rows(c, g, 1, charge, (int)c->F_offsets.size() / 3);
+        }
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_energy(fmmkmc_ctx *c, double *U)
+{
+    if (!c || !U) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "energy before initialise");
+    *U = c->U;
+    return FMMKMC_OK;
+}
+
+int fmmkmc_positions(fmmkmc_ctx *c, double *xyz)
+{
+    if (!c || !xyz) return FMMKMC_EINVAL;
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        launch(c, "interleave", k_interleave, dim3((unsigned)((c->N + 255) / 256)), dim3(256), c->N, c->x, c->y,
+               c->z, xyz);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_potential(fmmkmc_ctx *c, int64_t m, const double *xyz, const int64_t *exclude, double *out)
+{
+    if (!c || m < 0 || (m > 0 && (!xyz || !out))) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "potential before initialise");
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        launch_point_phi(c, make_geo(c), m, xyz, nullptr, exclude, c->bc == FMMKMC_PERIODIC ? 1 : 0, out,
+                         "point_phi");
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_set_profiling(fmmkmc_ctx *c, int on)
+{
+    if (!c) return FMMKMC_EINVAL;
+    API_GUARD(c, {
+        c->prof.resolve();
+        c->prof.total.clear();
+        c->prof.on = on != 0;
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_kernel_time(fmmkmc_ctx *c, const char *name, double *ms, int64_t *launches)
+{
+    if (!c || !name) return FMMKMC_EINVAL;
+    c->prof.resolve();
+    auto it = c->prof.total.find(name);
+    if (ms) *ms = it == c->prof.total.end() ? 0.0 : it->second.first;
+    if (launches) *launches = it == c->prof.total.end() ? 0 : it->second.second;
+    return FMMKMC_OK;
+}
+
+const char *fmmkmc_last_error(fmmkmc_ctx *c)
+{
+    if (!c) return create_error().c_str();
+    return c->err.c_str();
+}
+
+int fmmkmc_destroy(fmmkmc_ctx *c)
+{
+    if (!c) return FMMKMC_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+    return FMMKMC_OK;
+}
+
+}  // extern "C"

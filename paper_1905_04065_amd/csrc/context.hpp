@@ -1,0 +1,109 @@
+// Library context: device state of one FMM-KMC system and host mirrors of the
+// bookkeeping needed to validate an accepted move without a device round trip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmkmc.h"
+
+namespace fmmkmc {
+
+constexpr int kMaxOrder = 16;
+constexpr int kMaxLevels = 10;
+
+// geometry passed by value to kernels
+struct Geo {
+    double a;      // box side
+    double w;      // fine cell width
+    double h;      // lattice spacing (lattice mode), else 0
+    int nc;        // fine cells per axis, 2^(L-1)
+    int n;         // lattice sites per axis (lattice mode), else 0
+    int periodic;  // 1 periodic, 0 free space
+    int cap;       // slots per fine cell
+};
+
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::map<std::string, std::pair<double, int64_t>> total;  // ms, launches
+    void resolve();
+};
+
+struct FarField {
+    double *K = nullptr;      // multipole of the box about its centre (nt)
+    double *H = nullptr;      // local expansion of the copies in V_inf (nt)
+    double *R = nullptr;      // far operator, [k][n] (nt x nt)
+    double *G = nullptr;      // Chebyshev map [(p+1)^3][nt]
+    double *C = nullptr;      // Chebyshev coefficients (p+1)^3
+    double *Bz = nullptr;     // lattice: [n][n][p+1] partial sums over x and y
+    double *Tax = nullptr;    // lattice: T_c(xi) at the n lattice coordinates [n][p+1]
+    double *sigma = nullptr;  // lattice: V_inf self-energy factor per site [n^3]
+};
+
+}  // namespace fmmkmc
+
+struct fmmkmc_ctx {
+    // parameters
+    double a = 0, h = 0;
+    int bc = 0, L = 0, p = 0, nt = 0, prec = 0, lat_n = 0, cap = 0, device = 0;
+    hipStream_t stream = nullptr;
+    int64_t N = 0;
+    int nc = 0;
+    int64_t M = 0;        // fine cells
+    bool s2 = false;      // lattice with 2x2x2 sites per fine cell
+    bool initialised = false;
+    double U = 0;
+    std::string err;
+    fmmkmc::Profiler prof;
+
+    // charges (device)
+    double *x = nullptr, *y = nullptr, *z = nullptr, *q = nullptr;
+    int32_t *cell = nullptr, *slot = nullptr, *site = nullptr;
+    int32_t *cell_cnt = nullptr, *cell_slots = nullptr;
+    int32_t *site_charge = nullptr;  // lattice: charge on each site (lattice order) or -1
+    double *qsite = nullptr;         // 2x2x2 lattice: charge per site, cell-major order
+    float *qsite32 = nullptr;
+
+    // expansions (device), coefficient-major [k][cells]
+    std::vector<double *> phi_lv, psi_lv;  // index = level 1..L
+    double **d_phi_ptrs = nullptr;         // device copy of phi_lv
+    float *psi32 = nullptr;                // mixed: FP32 copy of psi_lv[L]
+    double *phisite = nullptr;             // lattice: potential per site
+
+    // operators (device)
+    std::vector<double *> m2m;   // [level] 8 matrices [c][n][k] (parent level 1..L-1)
+    std::vector<double *> l2l;   // [level] 8 matrices [c][n][k] (child level 2..L)
+    double *m2l = nullptr;       // 316 unit-width matrices [o][n][k]
+    int32_t *m2l_index = nullptr;  // 343 entries: (dx+3)*49 + (dy+3)*7 + (dz+3) -> o or -1
+    double *scale = nullptr;     // [level][2][nt]: w^-deg(n) and w^-(deg(k)+1)
+    double *Y2 = nullptr, *T2 = nullptr;   // 2x2x2 lattice tables
+    float *Y2f = nullptr, *T2f = nullptr;
+    fmmkmc::FarField far;
+
+    // lattice proposal table (periodic): F[i][k] per charge and hop
+    double *F = nullptr;
+    std::vector<int32_t> F_offsets;   // 3K ints the table was built for
+    int32_t *d_offsets = nullptr;     // device copy of the current hop offsets
+    int d_offsets_K = 0;
+
+    // scratch
+    double *scr = nullptr;
+    size_t scr_bytes = 0;
+    int32_t *flags = nullptr;   // device error flags
+    int64_t *iota = nullptr;    // 0..N-1
+    double *acc_buf = nullptr;  // accept: target, charge index, dU (32 doubles)
+    double *red = nullptr;      // reduction partials
+
+    // host mirrors
+    std::vector<double> hx, hy, hz, hq;
+    std::vector<int32_t> hcell, hslot, hsite, hcnt, hslots, hsite_charge;
+};

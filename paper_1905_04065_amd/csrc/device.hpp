@@ -1,0 +1,163 @@
+// Device helpers shared by the kernels: cell indexing, neighbour wrapping,
+// compile-time dispatch over the expansion order, and per-point harmonics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+#include "context.hpp"
+#include "solid.hpp"
+
+namespace fmmkmc {
+
+__host__ __device__ inline int64_t cell_id(int nc, int cx, int cy, int cz)
+{
+    return ((int64_t)cx * nc + cy) * nc + cz;
+}
+
+__host__ __device__ inline int posmod(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+__host__ __device__ inline int floordiv(int v, int n) { return v >= 0 ? v / n : -((-v + n - 1) / n); }
+
+// fine-cell coordinate of a position component: floor(x / w), clamped to [0, nc)
+__host__ __device__ inline int fine_coord(double v, double w, int nc)
+{
+    int c = (int)floor(v / w);
+    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
+// wrap a periodic coordinate into [0, a)
+__host__ __device__ inline double wrap_coord(double v, double a)
+{
+    double t = v - a * floor(v / a);
+    return t >= a ? t - a : t;
+}
+
+// lattice site of the 2x2x2 fast path in cell-major order
+__host__ __device__ inline int64_t s2_site(int nc, int i, int j, int k)
+{
+    return cell_id(nc, i >> 1, j >> 1, k >> 1) * 8 + ((i & 1) * 4 + (j & 1) * 2 + (k & 1));
+}
+
+// Real-stored multipole of a unit charge at offset d (Km[k] = conj(R_k(d))) and
+// the L2P weights at d (Wt[k], Psi(d) = sum L_k Wt[k]), written with stride s.
+__device__ inline void unit_multipole_and_weights(int p, double x, double y, double z, double *Km, double *Wt,
+                                                  int s = 1)
+{
+    const double r2 = x * x + y * y + z * z;
+    double cm2 = 1.0, cm1 = z;
+    Km[0] = 1.0;
+    Wt[0] = 1.0;
+    if (p >= 1) {
+        Km[slot0(1) * s] = z;
+        Wt[slot0(1) * s] = z;
+    }
+    for (int n = 2; n <= p; ++n) {
+        double c = ((2 * n - 1) * z * cm1 - r2 * cm2) * rinv(n, 0);
+        Km[slot0(n) * s] = c;
+        Wt[slot0(n) * s] = c;
+        cm2 = cm1;
+        cm1 = c;
+    }
+    double dr = 1.0, di = 0.0;
+    for (int m = 1; m <= p; ++m) {
+        const double f = -0.5 / m;
+        double ndr = f * (x * dr - y * di), ndi = f * (x * di + y * dr);
+        dr = ndr;
+        di = ndi;
+        double ar = dr, ai = di, br = 0, bi = 0;
+        for (int n = m; n <= p; ++n) {
+            double cr, ci;
+            if (n == m) {
+                cr = ar;
+                ci = ai;
+            } else if (n == m + 1) {
+                cr = z * ar;
+                ci = z * ai;
+                br = cr;
+                bi = ci;
+            } else {
+                const double w = rinv(n, m);
+                cr = ((2 * n - 1) * z * br - r2 * ar) * w;
+                ci = ((2 * n - 1) * z * bi - r2 * ai) * w;
+                ar = br;
+                ai = bi;
+                br = cr;
+                bi = ci;
+            }
+            Km[slot_re(n, m) * s] = cr;
+            Km[slot_im(n, m) * s] = -ci;
+            Wt[slot_re(n, m) * s] = 2.0 * cr;
+            Wt[slot_im(n, m) * s] = 2.0 * ci;
+        }
+    }
+}
+
+// Evaluate a real-stored local expansion given on the device at offset d
+// (runtime order; used off the hot path).
+__device__ inline double l2p_runtime(int p, const double *L, long stride, double x, double y, double z)
+{
+    const double r2 = x * x + y * y + z * z;
+    double acc0 = L[0], acc1 = 0.0;
+    double cm2 = 1.0, cm1 = z;
+    if (p >= 1) acc0 += L[slot0(1) * stride] * z;
+    for (int n = 2; n <= p; ++n) {
+        double c = ((2 * n - 1) * z * cm1 - r2 * cm2) * rinv(n, 0);
+        acc0 += L[slot0(n) * stride] * c;
+        cm2 = cm1;
+        cm1 = c;
+    }
+    double dr = 1.0, di = 0.0;
+    for (int m = 1; m <= p; ++m) {
+        const double f = -0.5 / m;
+        double ndr = f * (x * dr - y * di), ndi = f * (x * di + y * dr);
+        dr = ndr;
+        di = ndi;
+        double ar = dr, ai = di;
+        acc1 += L[slot_re(m, m) * stride] * ar + L[slot_im(m, m) * stride] * ai;
+        if (m + 1 > p) continue;
+        double br = z * ar, bi = z * ai;
+        acc1 += L[slot_re(m + 1, m) * stride] * br + L[slot_im(m + 1, m) * stride] * bi;
+        for (int n = m + 2; n <= p; ++n) {
+            const double w = rinv(n, m);
+            double cr = ((2 * n - 1) * z * br - r2 * ar) * w;
+            double ci = ((2 * n - 1) * z * bi - r2 * ai) * w;
+            acc1 += L[slot_re(n, m) * stride] * cr + L[slot_im(n, m) * stride] * ci;
+            ar = br;
+            ai = bi;
+            br = cr;
+            bi = ci;
+        }
+    }
+    return acc0 + 2.0 * acc1;
+}
+
+}  // namespace fmmkmc
+
+// Expand a runtime order p (1..16) into a call of F<P>.
+#define FMMKMC_DISPATCH_P(p, CALL)                                 \
+    switch (p) {                                                   \
+    case 1: { constexpr int P_ = 1; CALL; } break;                 \
+    case 2: { constexpr int P_ = 2; CALL; } break;                 \
+    case 3: { constexpr int P_ = 3; CALL; } break;                 \
+    case 4: { constexpr int P_ = 4; CALL; } break;                 \
+    case 5: { constexpr int P_ = 5; CALL; } break;                 \
+    case 6: { constexpr int P_ = 6; CALL; } break;                 \
+    case 7: { constexpr int P_ = 7; CALL; } break;                 \
+    case 8: { constexpr int P_ = 8; CALL; } break;                 \
+    case 9: { constexpr int P_ = 9; CALL; } break;                 \
+    case 10: { constexpr int P_ = 10; CALL; } break;               \
+    case 11: { constexpr int P_ = 11; CALL; } break;               \
+    case 12: { constexpr int P_ = 12; CALL; } break;               \
+    case 13: { constexpr int P_ = 13; CALL; } break;               \
+    case 14: { constexpr int P_ = 14; CALL; } break;               \
+    case 15: { constexpr int P_ = 15; CALL; } break;               \
+    case 16: { constexpr int P_ = 16; CALL; } break;               \
+    default: break;                                                \
+    }

@@ -1,0 +1,71 @@
+// Kernel launchers shared by the C-ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "context.hpp"
+#include "device.hpp"
+
+namespace fmmkmc {
+
+// Launch on the context's stream; with profiling on, bracket with HIP events.
+template <typename Kern, typename... Args>
+inline void launch_shm(fmmkmc_ctx *c, const char *name, Kern k, dim3 grid, dim3 block, size_t shm, Args... args)
+{
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0) return;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->prof.on) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, c->stream);
+    }
+    hipLaunchKernelGGL(k, grid, block, shm, c->stream, args...);
+    if (c->prof.on) {
+        (void)hipEventRecord(b, c->stream);
+        c->prof.pending.push_back({name, a, b});
+    }
+}
+
+template <typename Kern, typename... Args>
+inline void launch(fmmkmc_ctx *c, const char *name, Kern k, dim3 grid, dim3 block, Args... args)
+{
+    launch_shm(c, name, k, grid, block, 0, args...);
+}
+
+struct CommitArgs {
+    int64_t i;
+    double old_pos[3], new_pos[3], q;
+    int old_g[3], new_g[3];
+    int64_t old_cell, new_cell;
+    int old_slot, new_slot, moved_j, old_cnt, new_cnt;
+    int64_t old_site, new_site, old_site_s2, new_site_s2;
+};
+
+Geo make_geo(const fmmkmc_ctx *c);
+
+// setup
+void launch_p2m(fmmkmc_ctx *c, const Geo &g);
+void launch_upward(fmmkmc_ctx *c);
+void launch_downward(fmmkmc_ctx *c);
+void launch_far_refresh(fmmkmc_ctx *c);
+void launch_shadow(fmmkmc_ctx *c);
+// propose
+void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz, const int64_t *pidx,
+                      const int64_t *exclude, int with_far, double *out, const char *name);
+void launch_site_phi(fmmkmc_ctx *c, const Geo &g);
+void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask);
+void launch_sigma(fmmkmc_ctx *c, const Geo &g);
+void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K);
+// work: at least 8 S doubles; use: optional per-slot flag (0 = skip, NaN out)
+void launch_generic(fmmkmc_ctx *c, const Geo &g, int64_t S, const double *tgt, const int64_t *charge, double *dU,
+                    double *work, const int32_t *use = nullptr);
+void launch_div_index(fmmkmc_ctx *c, int64_t S, int K, int64_t *charge);
+void launch_expand_groups(fmmkmc_ctx *c, int64_t G, const int64_t *idx, const int64_t *offs, int64_t *charge);
+void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int ntypes, const int32_t *T,
+                        const uint8_t *Mk, int32_t *use);
+// accept
+void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a);
+
+}  // namespace fmmkmc

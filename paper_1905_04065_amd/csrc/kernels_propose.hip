@@ -1,0 +1,640 @@
+// Proposal kernels: the energy change of a hop r -> r' of charge q,
+//   free space (Eq. (proposed_energy)):
+//     dU = q phi(r') - q phi_occ(r) - q^2 / |r' - r|
+//   periodic (Eq. (proposed_energy_sr) plus the far field of Sec. 3.1):
+//     dU = q phi(r') - q phi_occ(r) - q^2 sum_{nu in V_box} 1/|r' - r - a nu|
+//          + q^2 (6 + 8/sqrt3 + 12/sqrt2)/a + dU_far,
+// where phi(x) = Psi_{L,cell(x)}(x) + sum over the 27 (wrapped) neighbour cells
+// of q_j/|x - r_j| is the potential of all charges (phi_occ leaves out the
+// moving charge itself), and
+//     dU_far = q (phi_inf(r') - phi_inf(r)) + 1/2 q (dphi(r') - dphi(r)),
+// phi_inf the local expansion H of the copies in V_inf and dphi the change of
+// that expansion when the charge moves (H -> H + R dK), i.e. the paper's
+// U_inf(r') - U_inf(r) with U_inf = 1/2 E.H.
+//
+// On a lattice phi is evaluated once per site (every hop to a site shares it)
+// and the per-slot kernel only gathers; the hop-dependent but
+// charge-configuration-independent terms (self terms and the quadratic far-field
+// term) are tabulated per charge and hop in F.
+#include "kernels.hpp"
+
+namespace fmmkmc {
+
+// ---- generic points ------------------------------------------------------
+
+// potential at arbitrary points: local expansion + near field (+ far field);
+// points are xyz[3j..3j+2] or, with pidx, the current positions of charges.
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_point_phi(Geo g, int64_t M, int64_t m, const double *__restrict__ xyz,
+                                                   const int64_t *__restrict__ pidx,
+                                                   const int64_t *__restrict__ exclude,
+                                                   const double *__restrict__ psi, const float *__restrict__ psi32,
+                                                   const double *__restrict__ H, int with_far,
+                                                   const double *__restrict__ x, const double *__restrict__ y,
+                                                   const double *__restrict__ z, const double *__restrict__ q,
+                                                   const int32_t *__restrict__ cnt,
+                                                   const int32_t *__restrict__ slots, double *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    double px, py, pz;
+    if (pidx) {
+        const int64_t i = pidx[t];
+        px = x[i];
+        py = y[i];
+        pz = z[i];
+    } else {
+        px = xyz[3 * t];
+        py = xyz[3 * t + 1];
+        pz = xyz[3 * t + 2];
+    }
+    const int64_t ex = exclude ? exclude[t] : -1;
+    const int cx = fine_coord(px, g.w, g.nc), cy = fine_coord(py, g.w, g.nc), cz = fine_coord(pz, g.w, g.nc);
+    const int64_t cell = cell_id(g.nc, cx, cy, cz);
+    const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
+    double phi;
+    if (MIXED) {
+        phi = psi[cell] + (double)l2p<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
+    } else {
+        phi = l2p<P, double>(psi + cell, M, ux, uy, uz);
+    }
+    // near field over the 27 neighbour cells
+    double nearv = 0.0;
+    float nearf = 0.0f;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                int ax = cx + dx, ay = cy + dy, az = cz + dz;
+                double shx = 0, shy = 0, shz = 0;
+                if (ax < 0 || ax >= g.nc || ay < 0 || ay >= g.nc || az < 0 || az >= g.nc) {
+                    if (!g.periodic) continue;
+                    shx = g.a * floordiv(ax, g.nc);
+                    shy = g.a * floordiv(ay, g.nc);
+                    shz = g.a * floordiv(az, g.nc);
+                    ax = posmod(ax, g.nc);
+                    ay = posmod(ay, g.nc);
+                    az = posmod(az, g.nc);
+                }
+                const int64_t nb = cell_id(g.nc, ax, ay, az);
+                const bool unshifted = (shx == 0 && shy == 0 && shz == 0);
+                const int cn = cnt[nb];
+                for (int s = 0; s < cn; ++s) {
+                    const int j = slots[nb * g.cap + s];
+                    if (j == ex && unshifted) continue;
+                    const double ex_ = px - (x[j] + shx), ey_ = py - (y[j] + shy), ez_ = pz - (z[j] + shz);
+                    if (MIXED) {
+                        const float fx = (float)ex_, fy = (float)ey_, fz = (float)ez_;
+                        nearf += (float)q[j] * __frsqrt_rn(fx * fx + fy * fy + fz * fz);
+                    } else {
+                        nearv += q[j] / sqrt(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
+                    }
+                }
+            }
+    phi += MIXED ? (double)nearf : nearv;
+    if (with_far) {
+        const double hx = px - 0.5 * g.a, hy = py - 0.5 * g.a, hz = pz - 0.5 * g.a;
+        phi += l2p<P, double>(H, 1, hx, hy, hz);
+    }
+    out[t] = phi;
+}
+
+void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz, const int64_t *pidx,
+                      const int64_t *exclude, int with_far, double *out, const char *name)
+{
+    if (m <= 0) return;
+    dim3 grid((unsigned)((m + 255) / 256));
+    if (c->prec == FMMKMC_MIXED) {
+        FMMKMC_DISPATCH_P(c->p, launch(c, name, k_point_phi<P_, true>, grid, dim3(256), g, c->M, m, xyz, pidx,
+                                       exclude, c->psi_lv[c->L], c->psi32, c->far.H, with_far, c->x, c->y, c->z,
+                                       c->q, c->cell_cnt, c->cell_slots, out));
+    } else {
+        FMMKMC_DISPATCH_P(c->p, launch(c, name, k_point_phi<P_, false>, grid, dim3(256), g, c->M, m, xyz, pidx,
+                                       exclude, c->psi_lv[c->L], c->psi32, c->far.H, with_far, c->x, c->y, c->z,
+                                       c->q, c->cell_cnt, c->cell_slots, out));
+    }
+}
+
+// ---- lattice sites, any cell geometry --------------------------------------
+
+// far-field potential at lattice site (i, j, k) from the Chebyshev columns
+template <int P>
+__device__ inline double far_site(int n, int i, int j, int k, const double *__restrict__ Bz,
+                                  const double *__restrict__ Tax)
+{
+    const double *b = Bz + ((int64_t)i * n + j) * (P + 1);
+    const double *t = Tax + (int64_t)k * (P + 1);
+    double acc = 0.0;
+#pragma unroll
+    for (int cc = 0; cc <= P; ++cc) acc += b[cc] * t[cc];
+    return acc;
+}
+
+// one lane per lattice site (lattice order); the occupant of a site, if any,
+// is left out of its own potential, so occupied sites get phi_occ.
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, const double *__restrict__ psi,
+                                                          const float *__restrict__ psi32,
+                                                          const double *__restrict__ Bz,
+                                                          const double *__restrict__ Tax,
+                                                          const double *__restrict__ x, const double *__restrict__ y,
+                                                          const double *__restrict__ z, const double *__restrict__ q,
+                                                          const int32_t *__restrict__ cnt,
+                                                          const int32_t *__restrict__ slots,
+                                                          const int32_t *__restrict__ site_charge,
+                                                          double *__restrict__ phisite)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = g.n;
+    if (s >= (int64_t)n * n * n) return;
+    const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
+    const double px = (si + 0.5) * g.h, py = (sj + 0.5) * g.h, pz = (sk + 0.5) * g.h;
+    const int ex = site_charge[s];
+    const int cx = fine_coord(px, g.w, g.nc), cy = fine_coord(py, g.w, g.nc), cz = fine_coord(pz, g.w, g.nc);
+    const int64_t cell = cell_id(g.nc, cx, cy, cz);
+    const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
+    double phi;
+    if (MIXED)
+        phi = psi[cell] + (double)l2p<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
+    else
+        phi = l2p<P, double>(psi + cell, M, ux, uy, uz);
+    double nearv = 0.0;
+    float nearf = 0.0f;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                int ax = cx + dx, ay = cy + dy, az = cz + dz;
+                double shx = 0, shy = 0, shz = 0;
+                if (ax < 0 || ax >= g.nc || ay < 0 || ay >= g.nc || az < 0 || az >= g.nc) {
+                    if (!g.periodic) continue;
+                    shx = g.a * floordiv(ax, g.nc);
+                    shy = g.a * floordiv(ay, g.nc);
+                    shz = g.a * floordiv(az, g.nc);
+                    ax = posmod(ax, g.nc);
+                    ay = posmod(ay, g.nc);
+                    az = posmod(az, g.nc);
+                }
+                const int64_t nb = cell_id(g.nc, ax, ay, az);
+                const int cn = cnt[nb];
+                for (int t = 0; t < cn; ++t) {
+                    const int j = slots[nb * g.cap + t];
+                    if (j == ex) continue;  // a site's occupant has no copy among its 27 neighbour cells
+                    const double ex_ = px - (x[j] + shx), ey_ = py - (y[j] + shy), ez_ = pz - (z[j] + shz);
+                    if (MIXED) {
+                        const float fx = (float)ex_, fy = (float)ey_, fz = (float)ez_;
+                        nearf += (float)q[j] * __frsqrt_rn(fx * fx + fy * fy + fz * fz);
+                    } else {
+                        nearv += q[j] / sqrt(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
+                    }
+                }
+            }
+    phi += MIXED ? (double)nearf : nearv;
+    if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
+    phisite[s] = phi;
+}
+
+// ---- lattice with 2 x 2 x 2 sites per fine cell ----------------------------
+// One lane per fine cell, 8 sites.  The site offsets inside a cell are the same
+// for every cell, so the L2P weights (Y2) and the near-field 1/r weights (T2)
+// are fixed tables read with wavefront-uniform addresses.
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const double *__restrict__ psi,
+                                                     const float *__restrict__ psi32, const double *__restrict__ Y2,
+                                                     const double *__restrict__ T2, const float *__restrict__ Y2f,
+                                                     const float *__restrict__ T2f,
+                                                     const double *__restrict__ qsite,
+                                                     const float *__restrict__ qsite32,
+                                                     const double *__restrict__ Bz, const double *__restrict__ Tax,
+                                                     double *__restrict__ phisite)
+{
+    constexpr int NT = nterms(P);
+    using Real = typename std::conditional<MIXED, float, double>::type;
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= M) return;
+    const int nc = g.nc;
+    const int cx = (int)(cell / ((int64_t)nc * nc)), cy = (int)((cell / nc) % nc), cz = (int)(cell % nc);
+    const Real *Yt = MIXED ? (const Real *)Y2f : (const Real *)Y2;
+    const Real *Tt = MIXED ? (const Real *)T2f : (const Real *)T2;
+    Real far_[8], near_[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) far_[u] = near_[u] = Real(0);
+    // L2P at the 8 sites
+#pragma unroll 4
+    for (int k = MIXED ? 1 : 0; k < NT; ++k) {
+        const Real v = MIXED ? (Real)psi32[(int64_t)k * M + cell] : (Real)psi[(int64_t)k * M + cell];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) far_[u] += Yt[u * NT + k] * v;
+    }
+    // near field: the 27 neighbour cells' 8 sites each
+    for (int nb = 0; nb < 27; ++nb) {
+        int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
+        if (ax < 0 || ax >= nc || ay < 0 || ay >= nc || az < 0 || az >= nc) {
+            if (!g.periodic) continue;
+            ax = posmod(ax, nc);
+            ay = posmod(ay, nc);
+            az = posmod(az, nc);
+        }
+        const int64_t base = cell_id(nc, ax, ay, az) * 8;
+        Real qv[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) qv[v] = MIXED ? (Real)qsite32[base + v] : (Real)qsite[base + v];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) near_[u] += Tt[u * 216 + nb * 8 + v] * qv[v];
+    }
+    const double l00 = MIXED ? psi[cell] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = 2 * cx + (u >> 2), j = 2 * cy + ((u >> 1) & 1), k = 2 * cz + (u & 1);
+        double phi = l00 + (double)far_[u] + (double)near_[u];
+        if (g.periodic) phi += far_site<P>(g.n, i, j, k, Bz, Tax);
+        phisite[cell * 8 + u] = phi;
+    }
+}
+
+void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
+{
+    const bool mixed = c->prec == FMMKMC_MIXED;
+    if (c->s2) {
+        dim3 grid((unsigned)((c->M + 255) / 256));
+        if (mixed) {
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, true>, grid, dim3(256), g, c->M,
+                                           c->psi_lv[c->L], c->psi32, c->Y2, c->T2, c->Y2f, c->T2f, c->qsite,
+                                           c->qsite32, c->far.Bz, c->far.Tax, c->phisite));
+        } else {
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, false>, grid, dim3(256), g, c->M,
+                                           c->psi_lv[c->L], c->psi32, c->Y2, c->T2, c->Y2f, c->T2f, c->qsite,
+                                           c->qsite32, c->far.Bz, c->far.Tax, c->phisite));
+        }
+    } else {
+        const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+        dim3 grid((unsigned)((ns + 255) / 256));
+        if (mixed) {
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, true>, grid, dim3(256), g, c->M,
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->x, c->y, c->z,
+                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->phisite));
+        } else {
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, false>, grid, dim3(256), g, c->M,
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->x, c->y, c->z,
+                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->phisite));
+        }
+    }
+}
+
+// ---- per-slot gather (lattice) ---------------------------------------------
+
+__global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, int K, const int32_t *__restrict__ offs,
+                                                      const int32_t *__restrict__ site, const double *__restrict__ q,
+                                                      const int32_t *__restrict__ site_charge,
+                                                      const double *__restrict__ phisite,
+                                                      const double *__restrict__ F, int s2,
+                                                      double *__restrict__ dU, uint8_t *__restrict__ mask)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * K) return;
+    const int64_t i = t / K;
+    const int k = (int)(t - i * K);
+    const int n = g.n;
+    const int s = site[i];
+    const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
+    int ti = si + offs[3 * k], tj = sj + offs[3 * k + 1], tk = sk + offs[3 * k + 2];
+    bool valid = true;
+    if (g.periodic) {
+        ti = posmod(ti, n);
+        tj = posmod(tj, n);
+        tk = posmod(tk, n);
+    } else if (ti < 0 || ti >= n || tj < 0 || tj >= n || tk < 0 || tk >= n) {
+        valid = false;
+    }
+    double out = __builtin_nan("");
+    if (valid) {
+        const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
+        valid = site_charge[ts] < 0;
+        if (valid) {
+            const int64_t ps = s2 ? s2_site(g.nc, si, sj, sk) : (int64_t)s;
+            const int64_t pt = s2 ? s2_site(g.nc, ti, tj, tk) : ts;
+            const double qi = q[i];
+            double corr;
+            if (g.periodic) {
+                corr = F[t];
+            } else {
+                const double ox = offs[3 * k], oy = offs[3 * k + 1], oz = offs[3 * k + 2];
+                corr = -1.0 / (g.h * sqrt(ox * ox + oy * oy + oz * oz));
+            }
+            out = qi * (phisite[pt] - phisite[ps]) + qi * qi * corr;
+        }
+    }
+    dU[t] = out;
+    if (mask) mask[t] = valid ? 1 : 0;
+}
+
+void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask)
+{
+    const int64_t tot = c->N * K;
+    launch(c, "slot_lattice", k_slot_lattice, dim3((unsigned)((tot + 255) / 256)), dim3(256), g, c->N, K,
+           c->d_offsets, c->site, c->q, c->site_charge, c->phisite, c->F, c->s2 ? 1 : 0, dU, mask);
+}
+
+// ---- far-field helpers (LDS-tiled matrix-vector products with R) ----------
+
+constexpr int SB = 8;  // items per block (2 LDS rows of (p+1)^2 doubles each, <= 37 KB)
+
+// sigma(s) = B(s, s) with B(y, x) = L2P of R K1(x) at y: the V_inf field at a
+// site due to a unit charge at the same site, for every lattice site.
+__global__ __launch_bounds__(256) void k_sigma_sites(Geo g, int p, const double *__restrict__ R,
+                                                     double *__restrict__ sigma)
+{
+    const int nt = nterms(p);
+    extern __shared__ double sm[];
+    double *Kv = sm, *Wv = sm + SB * nt;
+    const int n = g.n;
+    const int64_t ns = (int64_t)n * n * n;
+    const int64_t s0 = (int64_t)blockIdx.x * SB;
+    if (threadIdx.x < SB) {
+        const int64_t s = s0 + threadIdx.x;
+        if (s < ns) {
+            const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
+            unit_multipole_and_weights(p, (si + 0.5) * g.h - 0.5 * g.a, (sj + 0.5) * g.h - 0.5 * g.a,
+                                       (sk + 0.5) * g.h - 0.5 * g.a, Kv + threadIdx.x * nt, Wv + threadIdx.x * nt);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < SB * nt; e += blockDim.x) {
+        const int b = e / nt, k = e % nt;
+        if (s0 + b >= ns) continue;
+        double acc = 0.0;
+        for (int m = 0; m < nt; ++m) acc += R[(int64_t)m * nt + k] * Kv[b * nt + m];
+        Wv[b * nt + k] *= acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < SB && s0 + threadIdx.x < ns) {
+        double acc = 0.0;
+        for (int k = 0; k < nt; ++k) acc += Wv[threadIdx.x * nt + k];
+        sigma[s0 + threadIdx.x] = acc;
+    }
+}
+
+// F[i][k] for the lattice fast path (periodic): the q^2-terms of a hop,
+//   -sum_{nu in V_box} 1/|t - r - a nu| + C_box / a + 1/2 (sigma(t) + sigma(r)) - B(t, r)
+// for charge i at site r and its wrapped target t (charges listed in `which`).
+__global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, const int64_t *__restrict__ which,
+                                                int K, const int32_t *__restrict__ offs,
+                                                const int32_t *__restrict__ site, const double *__restrict__ R,
+                                                const double *__restrict__ sigma, double *__restrict__ F)
+{
+    const int nt = nterms(p);
+    extern __shared__ double sm[];
+    double *Kv = sm, *Wv = sm + SB * nt;
+    const int n = g.n;
+    const int64_t c0 = (int64_t)blockIdx.x * SB;
+    if (threadIdx.x < SB && c0 + threadIdx.x < count) {
+        const int64_t i = which ? which[c0 + threadIdx.x] : c0 + threadIdx.x;
+        const int s = site[i];
+        const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
+        unit_multipole_and_weights(p, (si + 0.5) * g.h - 0.5 * g.a, (sj + 0.5) * g.h - 0.5 * g.a,
+                                   (sk + 0.5) * g.h - 0.5 * g.a, Kv + threadIdx.x * nt, Wv + threadIdx.x * nt);
+    }
+    __syncthreads();
+    // Wv <- R K1(r) (the V_inf local expansion of a unit charge at r)
+    for (int e = threadIdx.x; e < SB * nt; e += blockDim.x) {
+        const int b = e / nt, k = e % nt;
+        if (c0 + b >= count) continue;
+        double acc = 0.0;
+        for (int m = 0; m < nt; ++m) acc += R[(int64_t)m * nt + k] * Kv[b * nt + m];
+        Wv[b * nt + k] = acc;
+    }
+    __syncthreads();
+    const double cbox = (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
+    for (int e = threadIdx.x; e < SB * K; e += blockDim.x) {
+        const int b = e / K, k = e % K;
+        if (c0 + b >= count) continue;
+        const int64_t i = which ? which[c0 + b] : c0 + b;
+        const int s = site[i];
+        const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
+        const int ti = posmod(si + offs[3 * k], n), tj = posmod(sj + offs[3 * k + 1], n),
+                  tk = posmod(sk + offs[3 * k + 2], n);
+        const double rx = (si + 0.5) * g.h, ry = (sj + 0.5) * g.h, rz = (sk + 0.5) * g.h;
+        const double tx = (ti + 0.5) * g.h, ty = (tj + 0.5) * g.h, tz = (tk + 0.5) * g.h;
+        double self = 0.0;
+        for (int a0 = -1; a0 <= 1; ++a0)
+            for (int a1 = -1; a1 <= 1; ++a1)
+                for (int a2 = -1; a2 <= 1; ++a2) {
+                    const double d0 = tx - rx - g.a * a0, d1 = ty - ry - g.a * a1, d2 = tz - rz - g.a * a2;
+                    self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                }
+        const double B = l2p_runtime(p, Wv + b * nt, 1, tx - 0.5 * g.a, ty - 0.5 * g.a, tz - 0.5 * g.a);
+        const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
+        F[i * K + k] = -self + cbox + 0.5 * (sigma[ts] + sigma[s]) - B;
+    }
+}
+
+void launch_sigma(fmmkmc_ctx *c, const Geo &g)
+{
+    const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+    const size_t shm = sizeof(double) * 2 * SB * c->nt;
+    launch_shm(c, "sigma_sites", k_sigma_sites, dim3((unsigned)((ns + SB - 1) / SB)), dim3(256), shm, g, c->p,
+               c->far.R, c->far.sigma);
+}
+
+void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K)
+{
+    const size_t shm = sizeof(double) * 2 * SB * c->nt;
+    launch_shm(c, "f_rows", k_f_rows, dim3((unsigned)((count + SB - 1) / SB)), dim3(256), shm, g, c->p, count,
+               which, K, c->d_offsets, c->site, c->far.R, c->far.sigma, c->F);
+}
+
+// ---- generic proposals ----------------------------------------------------
+
+// wrap / validate targets; status: 0 ok, 1 outside (free), 2 coincident, 3 not used
+__global__ __launch_bounds__(256) void k_prepare_targets(Geo g, int64_t S, const double *__restrict__ tgt,
+                                                         const int32_t *__restrict__ use,
+                                                         const double *__restrict__ x, const double *__restrict__ y,
+                                                         const double *__restrict__ z,
+                                                         const int32_t *__restrict__ cnt,
+                                                         const int32_t *__restrict__ slots, double *__restrict__ tw,
+                                                         int32_t *__restrict__ status, int32_t *__restrict__ flags)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double t[3] = {tgt[3 * s], tgt[3 * s + 1], tgt[3 * s + 2]};
+    int st = (use && !use[s]) ? 3 : 0;
+    for (int d = 0; d < 3 && st == 0; ++d) {
+        if (g.periodic) {
+            t[d] = wrap_coord(t[d], g.a);
+        } else if (!(t[d] >= 0.0 && t[d] < g.a)) {
+            st = 1;
+        }
+    }
+    if (st == 0) {
+        const int64_t cell = cell_id(g.nc, fine_coord(t[0], g.w, g.nc), fine_coord(t[1], g.w, g.nc),
+                                     fine_coord(t[2], g.w, g.nc));
+        for (int k = 0; k < cnt[cell]; ++k) {
+            const int j = slots[cell * g.cap + k];
+            if (x[j] == t[0] && y[j] == t[1] && z[j] == t[2]) st = 2;
+        }
+    } else {
+        t[0] = t[1] = t[2] = 0.5 * g.a;  // harmless point for the later kernels
+    }
+    tw[3 * s] = t[0];
+    tw[3 * s + 1] = t[1];
+    tw[3 * s + 2] = t[2];
+    status[s] = st;
+    if (st == 1) atomicOr(flags, 1);
+    if (st == 2) atomicOr(flags, 2);
+}
+
+// far-field change of each proposal: q (phi_inf(t) - phi_inf(r)) + 1/2 q (dphi(t) - dphi(r))
+constexpr int SBF = 4;  // proposals per block (four LDS rows of (p+1)^2 doubles, <= 37 KB)
+
+__global__ __launch_bounds__(256) void k_generic_far(Geo g, int p, int64_t S, const double *__restrict__ tw,
+                                                     const int64_t *__restrict__ charge,
+                                                     const double *__restrict__ x, const double *__restrict__ y,
+                                                     const double *__restrict__ z, const double *__restrict__ q,
+                                                     const double *__restrict__ R, const double *__restrict__ H,
+                                                     double *__restrict__ far)
+{
+    const int nt = nterms(p);
+    extern __shared__ double sm[];
+    double *Kt = sm, *Wt = sm + SBF * nt, *Kr = sm + 2 * SBF * nt, *Wr = sm + 3 * SBF * nt;
+    const int64_t s0 = (int64_t)blockIdx.x * SBF;
+    const double c = 0.5 * g.a;
+    const int b = threadIdx.x;
+    if (b < SBF && s0 + b < S) {
+        const int64_t s = s0 + b, i = charge[s];
+        unit_multipole_and_weights(p, tw[3 * s] - c, tw[3 * s + 1] - c, tw[3 * s + 2] - c, Kt + b * nt, Wt + b * nt);
+        unit_multipole_and_weights(p, x[i] - c, y[i] - c, z[i] - c, Kr + b * nt, Wr + b * nt);
+    }
+    __syncthreads();
+    // Kt <- dK = q (K1(t) - K1(r)), Wt <- W(t) - W(r)
+    for (int e = threadIdx.x; e < SBF * nt; e += blockDim.x) {
+        const int bb = e / nt;
+        if (s0 + bb >= S) continue;
+        const double qi = q[charge[s0 + bb]];
+        Kt[e] = qi * (Kt[e] - Kr[e]);
+        Wt[e] = Wt[e] - Wr[e];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < SBF * nt; e += blockDim.x) {
+        const int bb = e / nt, k = e % nt;
+        if (s0 + bb >= S) continue;
+        double dh = 0.0;
+        for (int m = 0; m < nt; ++m) dh += R[(int64_t)m * nt + k] * Kt[bb * nt + m];
+        const double qi = q[charge[s0 + bb]];
+        Kr[e] = Wt[e] * qi * (H[k] + 0.5 * dh);
+    }
+    __syncthreads();
+    if (b < SBF && s0 + b < S) {
+        double acc = 0.0;
+        for (int k = 0; k < nt; ++k) acc += Kr[b * nt + k];
+        far[s0 + b] = acc;
+    }
+}
+
+// dU = q (phi(t) - phi_occ(r)) + self terms + far
+__global__ __launch_bounds__(256) void k_generic_combine(Geo g, int64_t S, const double *__restrict__ tw,
+                                                         const int32_t *__restrict__ status,
+                                                         const int64_t *__restrict__ charge,
+                                                         const double *__restrict__ x, const double *__restrict__ y,
+                                                         const double *__restrict__ z, const double *__restrict__ q,
+                                                         const double *__restrict__ phit,
+                                                         const double *__restrict__ phir,
+                                                         const double *__restrict__ far, double *__restrict__ dU)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (status[s] != 0) {
+        dU[s] = __builtin_nan("");
+        return;
+    }
+    const int64_t i = charge[s];
+    const double qi = q[i];
+    const double tx = tw[3 * s], ty = tw[3 * s + 1], tz = tw[3 * s + 2];
+    double d = qi * (phit[s] - phir[s]);
+    if (g.periodic) {
+        double self = 0.0;
+        for (int a0 = -1; a0 <= 1; ++a0)
+            for (int a1 = -1; a1 <= 1; ++a1)
+                for (int a2 = -1; a2 <= 1; ++a2) {
+                    const double d0 = tx - x[i] - g.a * a0, d1 = ty - y[i] - g.a * a1, d2 = tz - z[i] - g.a * a2;
+                    self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                }
+        d += -qi * qi * self + qi * qi * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a + far[s];
+    } else {
+        const double d0 = tx - x[i], d1 = ty - y[i], d2 = tz - z[i];
+        d -= qi * qi / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    dU[s] = d;
+}
+
+// slot -> charge index from the CSR groups
+__global__ void k_expand_groups(int64_t G, const int64_t *__restrict__ idx, const int64_t *__restrict__ offs,
+                                int64_t *__restrict__ charge)
+{
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= G) return;
+    for (int64_t s = offs[gi]; s < offs[gi + 1]; ++s) charge[s] = idx[gi];
+}
+
+// propose_with_dats: slots (i, k) with k < C[T[i]] and M[i][k] != 0
+__global__ void k_dats_select(int64_t N, int K, const int32_t *__restrict__ C, int ntypes,
+                              const int32_t *__restrict__ T, const uint8_t *__restrict__ Mk,
+                              int32_t *__restrict__ use, int32_t *__restrict__ flags)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * K) return;
+    const int64_t i = t / K;
+    const int k = (int)(t - i * K);
+    const int ty = T[i];
+    int u = 0;
+    if (ty < 0 || ty >= ntypes) {
+        atomicOr(flags, 4);
+    } else {
+        u = (k < C[ty] && Mk[t] != 0) ? 1 : 0;
+    }
+    use[t] = u;
+}
+
+void launch_generic(fmmkmc_ctx *c, const Geo &g, int64_t S, const double *tgt, const int64_t *charge, double *dU,
+                    double *work, const int32_t *use)
+{
+    // work layout: tw[3S] phit[S] phir[S] far[S] status[S] (int32)
+    double *tw = work, *phit = tw + 3 * S, *phir = phit + S, *far = phir + S;
+    int32_t *status = (int32_t *)(far + S);
+    dim3 grid((unsigned)((S + 255) / 256));
+    launch(c, "prepare_targets", k_prepare_targets, grid, dim3(256), g, S, tgt, use, c->x, c->y, c->z,
+           c->cell_cnt, c->cell_slots, tw, status, c->flags);
+    launch_point_phi(c, g, S, tw, nullptr, nullptr, 0, phit, "point_phi");
+    launch_point_phi(c, g, S, nullptr, charge, charge, 0, phir, "point_phi");
+    if (g.periodic) {
+        const size_t shm = sizeof(double) * 4 * SBF * c->nt;
+        launch_shm(c, "generic_far", k_generic_far, dim3((unsigned)((S + SBF - 1) / SBF)), dim3(256), shm, g, c->p,
+                   S, tw, charge, c->x, c->y, c->z, c->q, c->far.R, c->far.H, far);
+    }
+    launch(c, "generic_combine", k_generic_combine, grid, dim3(256), g, S, tw, status, charge, c->x, c->y, c->z,
+           c->q, phit, phir, far, dU);
+}
+
+__global__ void k_div_index(int64_t S, int K, int64_t *__restrict__ charge)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S) charge[s] = s / K;
+}
+
+void launch_div_index(fmmkmc_ctx *c, int64_t S, int K, int64_t *charge)
+{
+    launch(c, "div_index", k_div_index, dim3((unsigned)((S + 255) / 256)), dim3(256), S, K, charge);
+}
+
+void launch_expand_groups(fmmkmc_ctx *c, int64_t G, const int64_t *idx, const int64_t *offs, int64_t *charge)
+{
+    launch(c, "expand_groups", k_expand_groups, dim3((unsigned)((G + 255) / 256)), dim3(256), G, idx, offs, charge);
+}
+
+void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int ntypes, const int32_t *T,
+                        const uint8_t *Mk, int32_t *use)
+{
+    launch(c, "dats_select", k_dats_select, dim3((unsigned)((N * K + 255) / 256)), dim3(256), N, K, C, ntypes, T, Mk,
+           use, c->flags);
+}
+
+}  // namespace fmmkmc

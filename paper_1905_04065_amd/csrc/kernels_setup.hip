@@ -1,0 +1,301 @@
+// Setup kernels: Alg. "fmm" (App. A) of the paper on the GPU.
+//   P2M   multipole of the charges of each fine cell about its centre
+//   M2M   upward pass, child -> parent (8 fixed child offsets per level)
+//   M2L + L2L downward pass per level: Psi = T_LL Psi(parent) + sum_{IL} T_ML Phi
+//         (free space: levels 1-2 have empty interaction lists, Sec. 2.2.1;
+//          periodic: Psi_1 = 0 and wrapped interaction lists from level 2, Sec. 3.1)
+//   far   H = R K of the periodic copies in V_inf (Sec. 3.1) and its Chebyshev
+//         form for fast evaluation at lattice sites.
+// Expansions are stored coefficient-major, [k][cell], so a wavefront of
+// consecutive cells reads each coefficient row with one coalesced access.
+#include "kernels.hpp"
+
+namespace fmmkmc {
+
+// ---- P2M: one lane per (fine cell, order m) -------------------------------
+
+template <int P, int Mc>
+__device__ void p2m_column(const Geo g, int64_t M, int64_t cell, const double *__restrict__ x,
+                           const double *__restrict__ y, const double *__restrict__ z,
+                           const double *__restrict__ q, const int32_t *__restrict__ cnt,
+                           const int32_t *__restrict__ slots, double *__restrict__ phi)
+{
+    constexpr int NC = P - Mc + 1;
+    double accr[NC], acci[NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) accr[t] = acci[t] = 0.0;
+    const int cx = (int)(cell / ((int64_t)g.nc * g.nc)), cy = (int)((cell / g.nc) % g.nc), cz = (int)(cell % g.nc);
+    const double ox = (cx + 0.5) * g.w, oy = (cy + 0.5) * g.w, oz = (cz + 0.5) * g.w;
+    const int c = cnt[cell];
+    for (int s = 0; s < c; ++s) {
+        const int j = slots[cell * g.cap + s];
+        const double dx = x[j] - ox, dy = y[j] - oy, dz = z[j] - oz, qq = q[j];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double dr = 1.0, di = 0.0;
+#pragma unroll
+        for (int m = 1; m <= Mc; ++m) {
+            const double f = -0.5 / m;
+            double ndr = f * (dx * dr - dy * di), ndi = f * (dx * di + dy * dr);
+            dr = ndr;
+            di = ndi;
+        }
+        double ar = dr, ai = di, br = dz * dr, bi = dz * di;
+        accr[0] += qq * ar;
+        acci[0] -= qq * ai;
+        if (NC > 1) {
+            accr[1] += qq * br;
+            acci[1] -= qq * bi;
+        }
+#pragma unroll
+        for (int t = 2; t < NC; ++t) {
+            const int n = Mc + t;
+            const double w = rinv(n, Mc);
+            double cr = ((2 * n - 1) * dz * br - r2 * ar) * w;
+            double ci = ((2 * n - 1) * dz * bi - r2 * ai) * w;
+            accr[t] += qq * cr;
+            acci[t] -= qq * ci;
+            ar = br;
+            ai = bi;
+            br = cr;
+            bi = ci;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        const int n = Mc + t;
+        if (Mc == 0) {
+            phi[(int64_t)slot0(n) * M + cell] = accr[t];
+        } else {
+            phi[(int64_t)slot_re(n, Mc) * M + cell] = accr[t];
+            phi[(int64_t)slot_im(n, Mc) * M + cell] = acci[t];
+        }
+    }
+}
+
+template <int P, int Mc = 0>
+__device__ void p2m_dispatch(int m, const Geo g, int64_t M, int64_t cell, const double *x, const double *y,
+                             const double *z, const double *q, const int32_t *cnt, const int32_t *slots,
+                             double *phi)
+{
+    if constexpr (Mc <= P) {
+        if (m == Mc)
+            p2m_column<P, Mc>(g, M, cell, x, y, z, q, cnt, slots, phi);
+        else
+            p2m_dispatch<P, Mc + 1>(m, g, M, cell, x, y, z, q, cnt, slots, phi);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_p2m(Geo g, int64_t M, const double *__restrict__ x,
+                                             const double *__restrict__ y, const double *__restrict__ z,
+                                             const double *__restrict__ q, const int32_t *__restrict__ cnt,
+                                             const int32_t *__restrict__ slots, double *__restrict__ phi)
+{
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= M) return;
+    p2m_dispatch<P>(blockIdx.y, g, M, cell, x, y, z, q, cnt, slots, phi);
+}
+
+void launch_p2m(fmmkmc_ctx *c, const Geo &g)
+{
+    dim3 grid((unsigned)((c->M + 255) / 256), c->p + 1);
+    FMMKMC_DISPATCH_P(c->p, launch(c, "p2m", k_p2m<P_>, grid, dim3(256), g, c->M, c->x, c->y, c->z, c->q,
+                                   c->cell_cnt, c->cell_slots, c->phi_lv[c->L]));
+}
+
+// ---- matrix-vector translation kernels ------------------------------------
+// out[k][cell] = sum_n mat[n][k] * in[n][cell'] with the matrix uniform over a
+// wavefront (scalar loads) and in/out rows coalesced over consecutive cells.
+// Outputs are produced KB at a time.
+
+constexpr int KB = 16;
+
+// M2M: parent cell per lane; 8 children with level-specific matrices.
+__global__ __launch_bounds__(256) void k_m2m(int nt, int ncp, const double *__restrict__ mats,
+                                             const double *__restrict__ child, double *__restrict__ parent)
+{
+    const int64_t Mp = (int64_t)ncp * ncp * ncp, Mc = Mp * 8;
+    const int ncc = 2 * ncp;
+    const int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pc >= Mp) return;
+    const int px = (int)(pc / ((int64_t)ncp * ncp)), py = (int)((pc / ncp) % ncp), pz = (int)(pc % ncp);
+    for (int k0 = 0; k0 < nt; k0 += KB) {
+        double acc[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+        for (int ch = 0; ch < 8; ++ch) {
+            const int64_t cc = cell_id(ncc, 2 * px + (ch >> 2), 2 * py + ((ch >> 1) & 1), 2 * pz + (ch & 1));
+            const double *mat = mats + (int64_t)ch * nt * nt;
+            for (int n = 0; n < nt; ++n) {
+                const double v = child[(int64_t)n * Mc + cc];
+                const double *row = mat + (int64_t)n * nt + k0;
+#pragma unroll
+                for (int t = 0; t < KB; ++t)
+                    if (k0 + t < nt) acc[t] += row[t] * v;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KB; ++t)
+            if (k0 + t < nt) parent[(int64_t)(k0 + t) * Mp + pc] = acc[t];
+    }
+}
+
+// M2L + L2L for one level.  Lanes of a block share the parity class (the
+// position of the cell within its parent), hence the same 189 interaction-list
+// offsets.  M2L matrices are for unit cell width; per-level scaling by
+// w^-deg(n) on input and w^-(deg(k)+1) on output.
+__global__ __launch_bounds__(256) void k_m2l(int nt, int nc, int periodic, int with_parent,
+                                             const double *__restrict__ m2l, const int32_t *__restrict__ m2l_index,
+                                             const double *__restrict__ scale_in, const double *__restrict__ scale_out,
+                                             const double *__restrict__ l2l, const double *__restrict__ phi,
+                                             const double *__restrict__ psi_parent, double *__restrict__ psi)
+{
+    const int pcls = blockIdx.y;  // parity class 0..7
+    const int px = pcls >> 2, py = (pcls >> 1) & 1, pz = pcls & 1;
+    const int h = nc / 2;
+    const int64_t Mh = (int64_t)h * h * h, M = Mh * 8;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Mh) return;
+    const int ix = (int)(t / ((int64_t)h * h)), iy = (int)((t / h) % h), iz = (int)(t % h);
+    const int cx = 2 * ix + px, cy = 2 * iy + py, cz = 2 * iz + pz;
+    const int64_t cell = cell_id(nc, cx, cy, cz);
+    const int64_t Mparent = Mh;
+    const int64_t parent = cell_id(h, ix, iy, iz);
+    for (int k0 = 0; k0 < nt; k0 += KB) {
+        double acc[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) acc[u] = 0.0;
+        for (int dx = -2 - px; dx <= 3 - px; ++dx)
+            for (int dy = -2 - py; dy <= 3 - py; ++dy)
+                for (int dz = -2 - pz; dz <= 3 - pz; ++dz) {
+                    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+                    int sx = cx + dx, sy = cy + dy, sz = cz + dz;
+                    const bool outside = sx < 0 || sx >= nc || sy < 0 || sy >= nc || sz < 0 || sz >= nc;
+                    if (outside && !periodic) continue;
+                    sx = posmod(sx, nc);
+                    sy = posmod(sy, nc);
+                    sz = posmod(sz, nc);
+                    const int64_t src = cell_id(nc, sx, sy, sz);
+                    // the matrix converts source at offset -d to target: d = target - source
+                    const int o = m2l_index[(-dx + 3) * 49 + (-dy + 3) * 7 + (-dz + 3)];
+                    const double *mat = m2l + (int64_t)o * nt * nt;
+                    for (int n = 0; n < nt; ++n) {
+                        const double v = phi[(int64_t)n * M + src] * scale_in[n];
+                        const double *row = mat + (int64_t)n * nt + k0;
+#pragma unroll
+                        for (int u = 0; u < KB; ++u)
+                            if (k0 + u < nt) acc[u] += row[u] * v;
+                    }
+                }
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (k0 + u < nt) acc[u] *= scale_out[k0 + u];
+        if (with_parent) {
+            const double *mat = l2l + (int64_t)pcls * nt * nt;
+            for (int n = 0; n < nt; ++n) {
+                const double v = psi_parent[(int64_t)n * Mparent + parent];
+                const double *row = mat + (int64_t)n * nt + k0;
+#pragma unroll
+                for (int u = 0; u < KB; ++u)
+                    if (k0 + u < nt) acc[u] += row[u] * v;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (k0 + u < nt) psi[(int64_t)(k0 + u) * M + cell] = acc[u];
+    }
+}
+
+void launch_upward(fmmkmc_ctx *c)
+{
+    for (int l = c->L - 1; l >= 1; --l) {
+        const int ncp = 1 << (l - 1);
+        const int64_t Mp = (int64_t)ncp * ncp * ncp;
+        launch(c, "m2m", k_m2m, dim3((unsigned)((Mp + 255) / 256)), dim3(256), c->nt, ncp, c->m2m[l],
+               c->phi_lv[l + 1], c->phi_lv[l]);
+    }
+}
+
+void launch_downward(fmmkmc_ctx *c)
+{
+    const int start = c->bc == FMMKMC_PERIODIC ? 2 : 3;
+    for (int l = start; l <= c->L; ++l) {
+        const int nc = 1 << (l - 1);
+        const int64_t Mh = (int64_t)(nc / 2) * (nc / 2) * (nc / 2);
+        const double *sin_ = c->scale + (int64_t)(2 * l) * c->nt, *sout = c->scale + (int64_t)(2 * l + 1) * c->nt;
+        launch(c, "m2l", k_m2l, dim3((unsigned)((Mh + 255) / 256), 8), dim3(256), c->nt, nc,
+               c->bc == FMMKMC_PERIODIC ? 1 : 0, l > start ? 1 : 0, c->m2l, c->m2l_index, sin_, sout, c->l2l[l],
+               c->phi_lv[l], l > start ? c->psi_lv[l - 1] : nullptr, c->psi_lv[l]);
+    }
+}
+
+// ---- far field -----------------------------------------------------------
+
+// H = R K (R stored [n][k]) then C = G H; one block.
+__global__ __launch_bounds__(256) void k_far_refresh(int nt, int ncheb, const double *__restrict__ R,
+                                                     const double *__restrict__ K, const double *__restrict__ G,
+                                                     double *__restrict__ H, double *__restrict__ C)
+{
+    __shared__ double sH[nterms(kMaxOrder)];
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+        double acc = 0.0;
+        for (int n = 0; n < nt; ++n) acc += R[(int64_t)n * nt + k] * K[n];
+        sH[k] = acc;
+        H[k] = acc;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ncheb; t += blockDim.x) {
+        double acc = 0.0;
+        const double *row = G + (int64_t)t * nt;
+        for (int k = 0; k < nt; ++k) acc += row[k] * sH[k];
+        C[t] = acc;
+    }
+}
+
+// Bz[i][j][c] = sum_{a+b <= p-c} C[a][b][c] T_a(xi_i) T_b(xi_j)
+__global__ __launch_bounds__(256) void k_cheb_columns(int p, int n, const double *__restrict__ C,
+                                                      const double *__restrict__ Tax, double *__restrict__ Bz)
+{
+    const int q = p + 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n * q) return;
+    const int cc = (int)(t % q);
+    const int64_t ij = t / q;
+    const int i = (int)(ij / n), j = (int)(ij % n);
+    double acc = 0.0;
+    for (int a = 0; a + cc <= p; ++a) {
+        double inner = 0.0;
+        for (int b = 0; a + b + cc <= p; ++b) inner += C[(a * q + b) * q + cc] * Tax[j * q + b];
+        acc += Tax[i * q + a] * inner;
+    }
+    Bz[t] = acc;
+}
+
+void launch_far_refresh(fmmkmc_ctx *c)
+{
+    const int q = c->p + 1;
+    launch(c, "far_refresh", k_far_refresh, dim3(1), dim3(256), c->nt, q * q * q, c->far.R, c->far.K, c->far.G,
+           c->far.H, c->far.C);
+    if (c->lat_n > 0) {
+        const int64_t tot = (int64_t)c->lat_n * c->lat_n * q;
+        launch(c, "cheb_columns", k_cheb_columns, dim3((unsigned)((tot + 255) / 256)), dim3(256), c->p, c->lat_n,
+               c->far.C, c->far.Tax, c->far.Bz);
+    }
+}
+
+// ---- FP32 shadow of the fine-level local expansions ------------------------
+
+__global__ void k_to_f32(int64_t count, const double *__restrict__ in, float *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) out[t] = (float)in[t];
+}
+
+void launch_shadow(fmmkmc_ctx *c)
+{
+    const int64_t tot = (int64_t)c->nt * c->M;
+    launch(c, "shadow_f32", k_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), tot, c->psi_lv[c->L],
+           c->psi32);
+}
+
+}  // namespace fmmkmc
