@@ -64,6 +64,7 @@ struct of_ctx {
     double *log_q, *log_old, *log_new;
     cplx *Gfar, *E, *K, *H;
     double U;
+    int U_valid;
 };
 
 static int side(int l) { return 1 << (l - 1); }
@@ -367,18 +368,11 @@ of_ctx *of_create(int bc, double a, int L, int p, int n, const double *xyz, cons
         free(ym);
         free(Y);
     }
-    /* energy, Alg. "fmm_evaluation" (+ far field) */
-    {
-        int *req = (int *)malloc(sizeof(int) * n);
-        for (int i = 0; i < n; ++i) req[i] = c->cell[i];
-        ensure_psi(c, n, req);
-        free(req);
-        double U = 0.0;
-#pragma omp parallel for reduction(+ : U) schedule(dynamic, 64)
-        for (int i = 0; i < n; ++i) U += 0.5 * q[i] * of_potential(c, xyz + 3 * i, i);
-        /* of_potential includes the far-field potential; U_inf = 1/2 sum q phi_inf = 1/2 E.H */
-        c->U = U;
-    }
+    /* energy, Alg. "fmm_evaluation" (+ far field); in lazy mode only on request,
+     * since it needs the local expansion of every occupied cell */
+    c->U = NAN;
+    c->U_valid = 0;
+    if (!lazy) of_energy(c);
     return c;
 }
 
@@ -411,7 +405,28 @@ void of_destroy(of_ctx *c)
     free(c);
 }
 
-double of_energy(of_ctx *c) { return c->U; }
+static void compute_energy(of_ctx *c)
+{
+    int n = c->n;
+    int *req = (int *)malloc(sizeof(int) * n);
+    for (int i = 0; i < n; ++i) req[i] = c->cell[i];
+    ensure_psi(c, n, req);
+    free(req);
+    double U = 0.0;
+#pragma omp parallel for reduction(+ : U) schedule(dynamic, 64)
+    for (int i = 0; i < n; ++i) U += 0.5 * c->q[i] * of_potential(c, c->xyz + 3 * i, i);
+    /* of_potential includes the far-field potential: 1/2 sum q phi_inf = 1/2 E.H */
+    c->U = U;
+    c->U_valid = 1;
+}
+
+/* total energy; a lazy context computes the initial energy here if no move has
+ * been accepted yet, and reports NaN otherwise */
+double of_energy(of_ctx *c)
+{
+    if (!c->U_valid && c->nlog == 0) compute_energy(c);
+    return c->U;
+}
 int of_nterms(of_ctx *c) { return c->nt; }
 
 /* near-field sum at x over the 27 (wrapped) neighbour cells of fine cell g,

@@ -89,6 +89,21 @@ void fine_of(const fmmkmc_ctx *c, const double *p, int g[3])
     for (int d = 0; d < 3; ++d) g[d] = fine_coord(p[d], w, c->nc);
 }
 
+// index of a lattice site (lattice order) in the device's site order
+int64_t site_order(const fmmkmc_ctx *c, int64_t lat)
+{
+    if (!c->s2) return lat;
+    const int n = c->lat_n;
+    return s2_site(c->nc, (int)(lat / ((int64_t)n * n)), (int)((lat / n) % n), (int)(lat % n));
+}
+
+int32_t pack_ijk(const fmmkmc_ctx *c, int64_t lat)
+{
+    const int n = c->lat_n;
+    const int i = (int)(lat / ((int64_t)n * n)), j = (int)((lat / n) % n), k = (int)(lat % n);
+    return (int32_t)((i << 20) | (j << 10) | k);
+}
+
 void release(fmmkmc_ctx *c)
 {
     dfree(c->x);
@@ -101,6 +116,7 @@ void release(fmmkmc_ctx *c)
     dfree(c->cell_cnt);
     dfree(c->cell_slots);
     dfree(c->site_charge);
+    dfree(c->ijk);
     dfree(c->qsite);
     dfree(c->qsite32);
     for (auto &p : c->phi_lv) dfree(p);
@@ -119,7 +135,8 @@ void release(fmmkmc_ctx *c)
     dfree(c->T2f);
     dfree(c->far.H);
     dfree(c->far.R);
-    dfree(c->far.G);
+    dfree(c->far.GR);
+    dfree(c->far.A);
     dfree(c->far.C);
     dfree(c->far.Bz);
     dfree(c->far.Tax);
@@ -214,17 +231,30 @@ void build_operators(fmmkmc_ctx *c)
 
 void build_far(fmmkmc_ctx *c)
 {
-    const int p = c->p, nt = c->nt, q = p + 1;
+    const int p = c->p, nt = c->nt, q = p + 1, ncheb = q * q * q;
     std::vector<double> R((size_t)nt * nt), RT((size_t)nt * nt);
     build_far_operator(p, c->a, R.data());
     for (int k = 0; k < nt; ++k)
         for (int n = 0; n < nt; ++n) RT[(size_t)n * nt + k] = R[(size_t)k * nt + n];
     c->far.R = dalloc<double>(RT.size());
     upload(c->far.R, RT.data(), RT.size(), c->stream);
-    std::vector<double> G((size_t)q * q * q * nt);
+    // C = G H = (G R) K: fold R into the Chebyshev map once; stored [n][t]
+    std::vector<double> G((size_t)ncheb * nt), GRT((size_t)nt * ncheb, 0.0);
     build_cheb_map(p, c->a, G.data());
-    c->far.G = dalloc<double>(G.size());
-    upload(c->far.G, G.data(), G.size(), c->stream);
+    for (int t = 0; t < ncheb; ++t) {
+        const double *g = &G[(size_t)t * nt];
+        bool any = false;
+        for (int k = 0; k < nt; ++k) any |= g[k] != 0.0;
+        if (!any) continue;
+        for (int n = 0; n < nt; ++n) {
+            double s = 0.0;
+            for (int k = 0; k < nt; ++k) s += g[k] * R[(size_t)k * nt + n];
+            GRT[(size_t)n * ncheb + t] = s;
+        }
+    }
+    c->far.GR = dalloc<double>(GRT.size());
+    upload(c->far.GR, GRT.data(), GRT.size(), c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
     c->far.C = dalloc<double>((size_t)q * q * q);
     c->far.H = dalloc<double>(nt);
     c->far.K = c->phi_lv[1];
@@ -247,6 +277,7 @@ void build_far(fmmkmc_ctx *c)
         c->far.Tax = dalloc<double>(Tax.size());
         upload(c->far.Tax, Tax.data(), Tax.size(), c->stream);
         c->far.Bz = dalloc<double>((size_t)n * n * q);
+        c->far.A = dalloc<double>((size_t)n * q * q);
     }
     HIPCHK(hipStreamSynchronize(c->stream));
 }
@@ -278,8 +309,7 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
     c->M = (int64_t)c->nc * c->nc * c->nc;
     if (c->lat_n > 0) {
         c->h = lattice_h(c);
-        if ((int64_t)c->lat_n * c->lat_n * c->lat_n > ((int64_t)1 << 31) - 1)
-            return fail(c, FMMKMC_EINVAL, "lattice too large");
+        if (c->lat_n > kMaxLattice) return fail(c, FMMKMC_EINVAL, "lattice_n must be <= 1024");
     }
     HIPCHK(hipSetDevice(c->device));
     // host copies; periodic positions wrapped into the box
@@ -400,8 +430,19 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
     if (c->prec == FMMKMC_MIXED) c->psi32 = dalloc<float>((size_t)c->M * c->nt);
     if (c->lat_n > 0) {
         const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
-        c->site_charge = dalloc<int32_t>(ns);
-        upload(c->site_charge, c->hsite_charge.data(), ns, s);
+        {
+            std::vector<int32_t> sc(ns, -1), pk(n);
+            for (int64_t i = 0; i < n; ++i) {
+                const int64_t st = c->hsite[i];
+                sc[site_order(c, st)] = (int32_t)i;
+                pk[i] = pack_ijk(c, st);
+            }
+            c->site_charge = dalloc<int32_t>(ns);
+            upload(c->site_charge, sc.data(), ns, s);
+            c->ijk = dalloc<int32_t>(n);
+            upload(c->ijk, pk.data(), n, s);
+            HIPCHK(hipStreamSynchronize(s));
+        }
         c->phisite = dalloc<double>(ns);
         if (c->s2) {
             std::vector<double> qs(ns, 0.0);
@@ -661,7 +702,8 @@ int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double 
     if (!c) return FMMKMC_EINVAL;
     if (!c->initialised) return fail(c, FMMKMC_ESTATE, "propose before initialise");
     if (c->lat_n <= 0) return fail(c, FMMKMC_ESTATE, "context was not created in lattice mode");
-    if (K < 1 || !offsets || !dU) return fail(c, FMMKMC_EINVAL, "bad lattice proposal arguments");
+    if (K < 1 || K > kMaxHops || !offsets || !dU) return fail(c, FMMKMC_EINVAL, "need 1 <= K <= 64 and dU");
+    if (c->N * (int64_t)K >= ((int64_t)1 << 32)) return fail(c, FMMKMC_EINVAL, "N * K must be < 2^32");
     for (int k = 0; k < 3 * K; ++k)
         if (offsets[k] < -1 || offsets[k] > 1) return fail(c, FMMKMC_EINVAL, "hop offsets must be in -1..1");
     API_GUARD(c, {
@@ -729,26 +771,10 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
     API_GUARD(c, {
         HIPCHK(hipSetDevice(c->device));
         const Geo g = make_geo(c);
-        // C1: dU of the move (footnote to Sec. 3.1); acc_buf holds the generic
-        // pipeline's work area (8 doubles), dU, the charge index and the target
-        double *work = c->acc_buf;
-        double *dUd = work + 8;
-        int64_t *charge = (int64_t *)(work + 9);
-        double *tgt = work + 10;
-        {
-            double hbuf[3] = {np[0], np[1], np[2]};
-            int64_t hi = i;
-            HIPCHK(hipMemcpyAsync(tgt, hbuf, sizeof(hbuf), hipMemcpyHostToDevice, c->stream));
-            HIPCHK(hipMemcpyAsync(charge, &hi, sizeof(hi), hipMemcpyHostToDevice, c->stream));
-            clear_flags(c);
-            launch_generic(c, g, 1, tgt, charge, dUd, work);
-            double dUh = 0;
-            HIPCHK(hipMemcpyAsync(&dUh, dUd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipStreamSynchronize(c->stream));
-            if (!std::isfinite(dUh)) return fail(c, FMMKMC_ECOINCIDENT, "singular move");
-            if (dU_out) *dU_out = dUh;
-            c->U += dUh;
-        }
+        // C1: dU of the move (footnote to Sec. 3.1), read back after the commit
+        // kernels are queued behind it (one synchronisation per accept)
+        double *dUd = c->acc_buf;
+        launch_move_dU(c, g, i, np, dUd);
         // C2 + C3
         CommitArgs a;
         a.i = i;
@@ -774,13 +800,12 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
         }
         a.old_site = old_site;
         a.new_site = new_site;
-        a.old_site_s2 = a.new_site_s2 = -1;
-        if (c->s2) {
-            const int n = c->lat_n;
-            a.old_site_s2 = s2_site(c->nc, (int)(old_site / ((int64_t)n * n)), (int)((old_site / n) % n),
-                                    (int)(old_site % n));
-            a.new_site_s2 = s2_site(c->nc, (int)(new_site / ((int64_t)n * n)), (int)((new_site / n) % n),
-                                    (int)(new_site % n));
+        a.old_sord = a.new_sord = -1;
+        a.new_ijk = 0;
+        if (c->lat_n > 0) {
+            a.old_sord = site_order(c, old_site);
+            a.new_sord = site_order(c, new_site);
+            a.new_ijk = pack_ijk(c, new_site);
         }
         launch_commit(c, g, a);
         if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c);
@@ -806,11 +831,13 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
             c->hsite[i] = (int32_t)new_site;
         }
         // lattice proposal table row of the moved charge
-        if (c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty()) {
-            HIPCHK(hipMemcpyAsync(charge, &i, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-            launch_f_rows(c, g, 1, charge, (int)c->F_offsets.size() / 3);
-        }
+        if (c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty())
+            launch_f_rows(c, g, 1, nullptr, (int)c->F_offsets.size() / 3, i);
+        double dUh = 0;
+        HIPCHK(hipMemcpyAsync(&dUh, dUd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (dU_out) *dU_out = dUh;
+        c->U += dUh;
         return FMMKMC_OK;
     })
 }

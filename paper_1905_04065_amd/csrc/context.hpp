@@ -15,6 +15,8 @@ namespace fmmkmc {
 
 constexpr int kMaxOrder = 16;
 constexpr int kMaxLevels = 10;
+constexpr int kMaxHops = 64;       // hop offsets per lattice proposal call
+constexpr int kMaxLattice = 1024;  // lattice sites per axis (10-bit packed coordinates)
 
 // geometry passed by value to kernels
 struct Geo {
@@ -42,8 +44,9 @@ struct FarField {
     double *K = nullptr;      // multipole of the box about its centre (nt)
     double *H = nullptr;      // local expansion of the copies in V_inf (nt)
     double *R = nullptr;      // far operator, [k][n] (nt x nt)
-    double *G = nullptr;      // Chebyshev map [(p+1)^3][nt]
+    double *GR = nullptr;     // Chebyshev map times R, column-major [nt][(p+1)^3]
     double *C = nullptr;      // Chebyshev coefficients (p+1)^3
+    double *A = nullptr;      // lattice: [n][p+1][p+1] partial sums over x
     double *Bz = nullptr;     // lattice: [n][n][p+1] partial sums over x and y
     double *Tax = nullptr;    // lattice: T_c(xi) at the n lattice coordinates [n][p+1]
     double *sigma = nullptr;  // lattice: V_inf self-energy factor per site [n^3]
@@ -69,7 +72,9 @@ struct fmmkmc_ctx {
     double *x = nullptr, *y = nullptr, *z = nullptr, *q = nullptr;
     int32_t *cell = nullptr, *slot = nullptr, *site = nullptr;
     int32_t *cell_cnt = nullptr, *cell_slots = nullptr;
-    int32_t *site_charge = nullptr;  // lattice: charge on each site (lattice order) or -1
+    int32_t *site_charge = nullptr;  // lattice: charge on each site or -1, in site order
+                                     // (cell-major on the 2x2x2 path, lattice order otherwise)
+    int32_t *ijk = nullptr;          // lattice: packed site coordinates of each charge (i<<20 | j<<10 | k)
     double *qsite = nullptr;         // 2x2x2 lattice: charge per site, cell-major order
     float *qsite32 = nullptr;
 

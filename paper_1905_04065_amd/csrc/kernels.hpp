@@ -40,7 +40,9 @@ struct CommitArgs {
     int old_g[3], new_g[3];
     int64_t old_cell, new_cell;
     int old_slot, new_slot, moved_j, old_cnt, new_cnt;
-    int64_t old_site, new_site, old_site_s2, new_site_s2;
+    int64_t old_site, new_site;  // lattice order, -1 without a lattice
+    int64_t old_sord, new_sord;  // the same sites in the device's site order
+    int32_t new_ijk;             // packed coordinates of the new site
 };
 
 Geo make_geo(const fmmkmc_ctx *c);
@@ -57,7 +59,8 @@ void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz,
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g);
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask);
 void launch_sigma(fmmkmc_ctx *c, const Geo &g);
-void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K);
+// F rows of charges which[0..count) or, without which, first..first+count-1
+void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K, int64_t first = 0);
 // work: at least 8 S doubles; use: optional per-slot flag (0 = skip, NaN out)
 void launch_generic(fmmkmc_ctx *c, const Geo &g, int64_t S, const double *tgt, const int64_t *charge, double *dU,
                     double *work, const int32_t *use = nullptr);
@@ -66,6 +69,7 @@ void launch_expand_groups(fmmkmc_ctx *c, int64_t G, const int64_t *idx, const in
 void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int ntypes, const int32_t *T,
                         const uint8_t *Mk, int32_t *use);
 // accept
+void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out);
 void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a);
 
 }  // namespace fmmkmc

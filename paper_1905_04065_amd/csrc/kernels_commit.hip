@@ -23,14 +23,48 @@ struct Move {
     int ngx, ngy, ngz;   // and of the new one
 };
 
-template <int P, int Mc>
-__device__ void sweep_column(const Geo g, int64_t M, int64_t cell, const Move mv, double *__restrict__ psi,
-                             float *__restrict__ psi32)
+// Columns m of the local expansion are split into groups whose coefficients
+// fit in registers (at most kSweepBudget doubles); one lane per (cell, group).
+// The per-source work (offset, 1/r, the near test) is shared by a group's
+// columns, and the irregular diagonal I_m^m is carried across them.
+constexpr int kSweepBudget = 64;
+__host__ __device__ constexpr int col_cost(int P, int m) { return m == 0 ? P + 1 : 2 * (P - m + 1); }
+__host__ __device__ constexpr int group_end(int P, int m0)
 {
-    constexpr int NC = P - Mc + 1;
-    double accr[NC], acci[NC];
+    int acc = col_cost(P, m0), m = m0;
+    while (m + 1 <= P && acc + col_cost(P, m + 1) <= kSweepBudget) acc += col_cost(P, ++m);
+    return m;
+}
+__host__ __device__ constexpr int n_groups(int P)
+{
+    int g = 0, m = 0;
+    while (m <= P) {
+        m = group_end(P, m) + 1;
+        ++g;
+    }
+    return g;
+}
+__host__ __device__ constexpr int group_m0(int P, int g)
+{
+    int m = 0;
+    for (int i = 0; i < g; ++i) m = group_end(P, m) + 1;
+    return m;
+}
+__host__ __device__ constexpr int col_offset(int P, int M0, int m)
+{
+    int o = 0;
+    for (int t = M0; t < m; ++t) o += col_cost(P, t);
+    return o;
+}
+
+template <int P, int M0, int M1>
+__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv, double *__restrict__ psi,
+                           float *__restrict__ psi32)
+{
+    constexpr int NACC = col_offset(P, M0, M1 + 1);
+    double acc[NACC];
 #pragma unroll
-    for (int t = 0; t < NC; ++t) accr[t] = acci[t] = 0.0;
+    for (int t = 0; t < NACC; ++t) acc[t] = 0.0;
     const int nc = g.nc;
     const int bx = (int)(cell / ((int64_t)nc * nc)), by = (int)((cell / nc) % nc), bz = (int)(cell % nc);
     const double cxw = (bx + 0.5) * g.w, cyw = (by + 0.5) * g.w, czw = (bz + 0.5) * g.w;
@@ -47,67 +81,78 @@ __device__ void sweep_column(const Geo g, int64_t M, int64_t cell, const Move mv
                     const double dx = px + g.a * i - cxw, dy = py + g.a * j - cyw, dz = pz + g.a * k - czw;
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     const double ir2 = 1.0 / r2;
-                    double dr = 1.0 / sqrt(r2), di = 0.0;
+                    double dr = qq * sqrt(ir2), di = 0.0;  // q I_0^0
 #pragma unroll
-                    for (int m = 1; m <= Mc; ++m) {
-                        const double f = -(2 * m - 1) * ir2;
-                        double ndr = f * (dx * dr - dy * di), ndi = f * (dx * di + dy * dr);
-                        dr = ndr;
-                        di = ndi;
-                    }
-                    double ar = dr, ai = di;
-                    accr[0] += qq * ar;
-                    acci[0] += qq * ai;
-                    double br = (2 * Mc + 1) * dz * ir2 * ar, bi = (2 * Mc + 1) * dz * ir2 * ai;
-                    if (NC > 1) {
-                        accr[1] += qq * br;
-                        acci[1] += qq * bi;
-                    }
+                    for (int m = 0; m <= M1; ++m) {
+                        if (m > 0) {
+                            const double f = -(2 * m - 1) * ir2;
+                            const double ndr = f * (dx * dr - dy * di), ndi = f * (dx * di + dy * dr);
+                            dr = ndr;
+                            di = ndi;
+                        }
+                        if (m >= M0) {
+                            const int o = col_offset(P, M0, m);
+                            const bool cplxcol = m > 0;
+                            double ar = dr, ai = di;
+                            acc[o] += ar;
+                            if (cplxcol) acc[o + 1] += ai;
+                            if (m + 1 <= P) {
+                                const double zf = (2 * m + 1) * dz * ir2;
+                                double br = zf * ar, bi = zf * ai;
+                                acc[o + (cplxcol ? 2 : 1)] += br;
+                                if (cplxcol) acc[o + 3] += bi;
 #pragma unroll
-                    for (int t = 2; t < NC; ++t) {
-                        const int n = Mc + t;
-                        const double cf = (double)((n - 1) * (n - 1) - Mc * Mc);
-                        double cr = ((2 * n - 1) * dz * br - cf * ar) * ir2;
-                        double ci = ((2 * n - 1) * dz * bi - cf * ai) * ir2;
-                        accr[t] += qq * cr;
-                        acci[t] += qq * ci;
-                        ar = br;
-                        ai = bi;
-                        br = cr;
-                        bi = ci;
+                                for (int n = m + 2; n <= P; ++n) {
+                                    const double zn = (2 * n - 1) * dz * ir2;
+                                    const double wn = (double)((n - 1) * (n - 1) - m * m) * ir2;
+                                    const double cr = zn * br - wn * ar, ci = zn * bi - wn * ai;
+                                    const int t = n - m;
+                                    acc[o + (cplxcol ? 2 * t : t)] += cr;
+                                    if (cplxcol) acc[o + 2 * t + 1] += ci;
+                                    ar = br;
+                                    ai = bi;
+                                    br = cr;
+                                    bi = ci;
+                                }
+                            }
+                        }
                     }
                 }
     }
 #pragma unroll
-    for (int t = 0; t < NC; ++t) {
-        const int n = Mc + t;
-        if (Mc == 0) {
-            const int64_t at = (int64_t)slot0(n) * M + cell;
-            const double v = psi[at] + accr[t];
-            psi[at] = v;
-            if (psi32) psi32[at] = (float)v;
-        } else {
-            const int64_t ar_ = (int64_t)slot_re(n, Mc) * M + cell, ai_ = (int64_t)slot_im(n, Mc) * M + cell;
-            const double vr = psi[ar_] + accr[t], vi = psi[ai_] + acci[t];
-            psi[ar_] = vr;
-            psi[ai_] = vi;
-            if (psi32) {
-                psi32[ar_] = (float)vr;
-                psi32[ai_] = (float)vi;
+    for (int m = M0; m <= M1; ++m) {
+        const int o = col_offset(P, M0, m);
+#pragma unroll
+        for (int n = m; n <= P; ++n) {
+            const int t = n - m;
+            if (m == 0) {
+                const int64_t at = (int64_t)slot0(n) * M + cell;
+                const double v = psi[at] + acc[o + t];
+                psi[at] = v;
+                if (psi32) psi32[at] = (float)v;
+            } else {
+                const int64_t ar_ = (int64_t)slot_re(n, m) * M + cell, ai_ = (int64_t)slot_im(n, m) * M + cell;
+                const double vr = psi[ar_] + acc[o + 2 * t], vi = psi[ai_] + acc[o + 2 * t + 1];
+                psi[ar_] = vr;
+                psi[ai_] = vi;
+                if (psi32) {
+                    psi32[ar_] = (float)vr;
+                    psi32[ai_] = (float)vi;
+                }
             }
         }
     }
 }
 
-template <int P, int Mc = 0>
-__device__ void sweep_dispatch(int m, const Geo g, int64_t M, int64_t cell, const Move &mv, double *psi,
+template <int P, int G = 0>
+__device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const Move &mv, double *psi,
                                float *psi32)
 {
-    if constexpr (Mc <= P) {
-        if (m == Mc)
-            sweep_column<P, Mc>(g, M, cell, mv, psi, psi32);
+    if constexpr (G < n_groups(P)) {
+        if (grp == G)
+            sweep_cols<P, group_m0(P, G), group_end(P, group_m0(P, G))>(g, M, cell, mv, psi, psi32);
         else
-            sweep_dispatch<P, Mc + 1>(m, g, M, cell, mv, psi, psi32);
+            sweep_dispatch<P, G + 1>(grp, g, M, cell, mv, psi, psi32);
     }
 }
 
@@ -121,12 +166,20 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, int64_t M, Move mv, double
 }
 
 // P2M of -q at the old and +q at the new position into the cells containing
-// them on every level; one lane per (level, m), both endpoints in turn.
+// them on every level; one lane per (level, n, m >= 0) runs the regular
+// recurrence to R_n^m itself, for both endpoints in turn.
 __global__ void k_path(Geo g, int L, int p, Move mv, double *const *__restrict__ phi)
 {
-    const int t = threadIdx.x;
-    if (t >= L * (p + 1)) return;
-    const int l = 1 + t / (p + 1), m = t % (p + 1);
+    const int per = (p + 1) * (p + 2) / 2;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L * per) return;
+    const int l = 1 + t / per;
+    int r = t % per, n = 0;
+    while (r > n) {
+        r -= n + 1;
+        ++n;
+    }
+    const int m = r;
     const int nl = 1 << (l - 1), sh = (L - l);
     const double w = g.a / nl;
     const int64_t Ml = (int64_t)nl * nl * nl;
@@ -141,36 +194,30 @@ __global__ void k_path(Geo g, int L, int p, Move mv, double *const *__restrict__
         double dr = 1.0, di = 0.0;
         for (int k = 1; k <= m; ++k) {
             const double f = -0.5 / k;
-            double ndr = f * (dx * dr - dy * di), ndi = f * (dx * di + dy * dr);
+            const double ndr = f * (dx * dr - dy * di), ndi = f * (dx * di + dy * dr);
             dr = ndr;
             di = ndi;
         }
-        double ar = dr, ai = di, br = 0, bi = 0;
-        for (int n = m; n <= p; ++n) {
-            double cr, ci;
-            if (n == m) {
-                cr = ar;
-                ci = ai;
-            } else if (n == m + 1) {
-                cr = dz * ar;
-                ci = dz * ai;
-                br = cr;
-                bi = ci;
-            } else {
-                const double wgt = rinv(n, m);
-                cr = ((2 * n - 1) * dz * br - r2 * ar) * wgt;
-                ci = ((2 * n - 1) * dz * bi - r2 * ai) * wgt;
-                ar = br;
-                ai = bi;
-                br = cr;
-                bi = ci;
-            }
-            if (m == 0) {
-                ph[(int64_t)slot0(n) * Ml + cell] += qq * cr;
-            } else {
-                ph[(int64_t)slot_re(n, m) * Ml + cell] += qq * cr;
-                ph[(int64_t)slot_im(n, m) * Ml + cell] -= qq * ci;
-            }
+        double ar = dr, ai = di, br = dz * dr, bi = dz * di;
+        double cr = ar, ci = ai;
+        if (n == m + 1) {
+            cr = br;
+            ci = bi;
+        }
+        for (int k = m + 2; k <= n; ++k) {
+            const double wgt = rinv(k, m);
+            cr = ((2 * k - 1) * dz * br - r2 * ar) * wgt;
+            ci = ((2 * k - 1) * dz * bi - r2 * ai) * wgt;
+            ar = br;
+            ai = bi;
+            br = cr;
+            bi = ci;
+        }
+        if (m == 0) {
+            ph[(int64_t)slot0(n) * Ml + cell] += qq * cr;
+        } else {
+            ph[(int64_t)slot_re(n, m) * Ml + cell] += qq * cr;
+            ph[(int64_t)slot_im(n, m) * Ml + cell] -= qq * ci;
         }
     }
 }
@@ -183,13 +230,16 @@ struct Book {
     int old_slot, new_slot;
     int moved_j;          // charge moved into old_slot (-1 if none)
     int old_cnt, new_cnt; // counts after the move
-    int64_t old_site, new_site;        // lattice order, -1 if no lattice
-    int64_t old_site_s2, new_site_s2;  // cell-major (2x2x2 path), -1 if unused
+    int64_t new_site;     // lattice order, -1 without a lattice
+    int64_t old_sord, new_sord;  // site order (cell-major on the 2x2x2 path)
+    int32_t new_ijk;
+    int s2;               // per-site charges are kept (2x2x2 path)
     int same_cell;        // the move stays inside one fine cell: slots unchanged
 };
 
 __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, int32_t *slot, int32_t *site,
-                       int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge, double *qsite, float *qsite32)
+                       int32_t *ijk, int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge, double *qsite,
+                       float *qsite32)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     x[b.i] = b.nx;
@@ -208,17 +258,18 @@ __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, i
         cell[b.i] = (int32_t)b.new_cell;
         slot[b.i] = b.new_slot;
     }
-    if (b.old_site >= 0) {
-        site_charge[b.old_site] = -1;
-        site_charge[b.new_site] = (int32_t)b.i;
+    if (b.new_site >= 0) {
+        site_charge[b.old_sord] = -1;
+        site_charge[b.new_sord] = (int32_t)b.i;
         site[b.i] = (int32_t)b.new_site;
-    }
-    if (b.old_site_s2 >= 0) {
-        qsite[b.old_site_s2] = 0.0;
-        qsite[b.new_site_s2] = b.q;
-        if (qsite32) {
-            qsite32[b.old_site_s2] = 0.0f;
-            qsite32[b.new_site_s2] = (float)b.q;
+        ijk[b.i] = b.new_ijk;
+        if (b.s2) {
+            qsite[b.old_sord] = 0.0;
+            qsite[b.new_sord] = b.q;
+            if (qsite32) {
+                qsite32[b.old_sord] = 0.0f;
+                qsite32[b.new_sord] = (float)b.q;
+            }
         }
     }
 }
@@ -239,10 +290,11 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
     mv.ngx = a.new_g[0];
     mv.ngy = a.new_g[1];
     mv.ngz = a.new_g[2];
-    dim3 grid((unsigned)((c->M + 255) / 256), c->p + 1);
     float *p32 = c->prec == FMMKMC_MIXED ? c->psi32 : nullptr;
-    FMMKMC_DISPATCH_P(c->p, launch(c, "sweep", k_sweep<P_>, grid, dim3(256), g, c->M, mv, c->psi_lv[c->L], p32));
-    launch(c, "path", k_path, dim3(1), dim3(kMaxLevels * (kMaxOrder + 1)), g, c->L, c->p, mv, c->d_phi_ptrs);
+    FMMKMC_DISPATCH_P(c->p, launch(c, "sweep", k_sweep<P_>, dim3((unsigned)((c->M + 255) / 256), n_groups(P_)),
+                                   dim3(256), g, c->M, mv, c->psi_lv[c->L], p32));
+    const int per = (c->p + 1) * (c->p + 2) / 2;
+    launch(c, "path", k_path, dim3((c->L * per + 255) / 256), dim3(256), g, c->L, c->p, mv, c->d_phi_ptrs);
     Book b;
     b.i = a.i;
     b.nx = a.new_pos[0];
@@ -256,13 +308,14 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
     b.moved_j = a.moved_j;
     b.old_cnt = a.old_cnt;
     b.new_cnt = a.new_cnt;
-    b.old_site = a.old_site;
     b.new_site = a.new_site;
-    b.old_site_s2 = c->s2 ? a.old_site_s2 : -1;
-    b.new_site_s2 = c->s2 ? a.new_site_s2 : -1;
+    b.old_sord = a.old_sord;
+    b.new_sord = a.new_sord;
+    b.new_ijk = a.new_ijk;
+    b.s2 = c->s2 ? 1 : 0;
     b.same_cell = a.old_cell == a.new_cell ? 1 : 0;
-    launch(c, "book", k_book, dim3(1), dim3(64), b, c->x, c->y, c->z, c->cell, c->slot, c->site, c->cell_cnt,
-           c->cell_slots, c->cap, c->site_charge, c->qsite, c->qsite32);
+    launch(c, "book", k_book, dim3(1), dim3(64), b, c->x, c->y, c->z, c->cell, c->slot, c->site, c->ijk,
+           c->cell_cnt, c->cell_slots, c->cap, c->site_charge, c->qsite, c->qsite32);
 }
 
 }  // namespace fmmkmc

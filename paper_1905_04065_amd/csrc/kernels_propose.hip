@@ -282,43 +282,59 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
 }
 
 // ---- per-slot gather (lattice) ---------------------------------------------
-
-__global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, int K, const int32_t *__restrict__ offs,
-                                                      const int32_t *__restrict__ site, const double *__restrict__ q,
+// One lane per slot t = i K + k.  i = t / K by a multiply-high with one
+// correction step (exact for every 32-bit t); the charge's lattice coordinates
+// come packed in one word; occupancy and potentials are read in site order
+// (cell-major on the 2x2x2 path), so a hop's two gathers share cache lines.
+__global__ __launch_bounds__(256) void k_slot_lattice(Geo g, uint32_t NK, uint32_t K, uint32_t kmul,
+                                                      const int32_t *__restrict__ offs,
+                                                      const int32_t *__restrict__ ijk, const double *__restrict__ q,
                                                       const int32_t *__restrict__ site_charge,
                                                       const double *__restrict__ phisite,
                                                       const double *__restrict__ F, int s2,
                                                       double *__restrict__ dU, uint8_t *__restrict__ mask)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * K) return;
-    const int64_t i = t / K;
-    const int k = (int)(t - i * K);
-    const int n = g.n;
-    const int s = site[i];
-    const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
-    int ti = si + offs[3 * k], tj = sj + offs[3 * k + 1], tk = sk + offs[3 * k + 2];
+    __shared__ int32_t soff[3 * kMaxHops];
+    for (uint32_t e = threadIdx.x; e < 3 * K; e += blockDim.x) soff[e] = offs[e];
+    __syncthreads();
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NK) return;
+    uint32_t i = __umulhi(t, kmul);
+    uint32_t k = t - i * K;
+    if (k >= K) {
+        ++i;
+        k -= K;
+    }
+    const int n = g.n, nc = g.nc;
+    const int32_t pk = ijk[i];
+    const int si = pk >> 20, sj = (pk >> 10) & 1023, sk = pk & 1023;
+    int ti = si + soff[3 * k], tj = sj + soff[3 * k + 1], tk = sk + soff[3 * k + 2];
     bool valid = true;
     if (g.periodic) {
-        ti = posmod(ti, n);
-        tj = posmod(tj, n);
-        tk = posmod(tk, n);
-    } else if (ti < 0 || ti >= n || tj < 0 || tj >= n || tk < 0 || tk >= n) {
-        valid = false;
+        ti += ti < 0 ? n : (ti >= n ? -n : 0);
+        tj += tj < 0 ? n : (tj >= n ? -n : 0);
+        tk += tk < 0 ? n : (tk >= n ? -n : 0);
+    } else {
+        valid = ti >= 0 && ti < n && tj >= 0 && tj < n && tk >= 0 && tk < n;
     }
     double out = __builtin_nan("");
     if (valid) {
-        const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
-        valid = site_charge[ts] < 0;
+        int64_t ps, pt;
+        if (s2) {
+            ps = (((int64_t)(si >> 1) * nc + (sj >> 1)) * nc + (sk >> 1)) * 8 + ((si & 1) * 4 + (sj & 1) * 2 + (sk & 1));
+            pt = (((int64_t)(ti >> 1) * nc + (tj >> 1)) * nc + (tk >> 1)) * 8 + ((ti & 1) * 4 + (tj & 1) * 2 + (tk & 1));
+        } else {
+            ps = ((int64_t)si * n + sj) * n + sk;
+            pt = ((int64_t)ti * n + tj) * n + tk;
+        }
+        valid = site_charge[pt] < 0;
         if (valid) {
-            const int64_t ps = s2 ? s2_site(g.nc, si, sj, sk) : (int64_t)s;
-            const int64_t pt = s2 ? s2_site(g.nc, ti, tj, tk) : ts;
             const double qi = q[i];
             double corr;
             if (g.periodic) {
                 corr = F[t];
             } else {
-                const double ox = offs[3 * k], oy = offs[3 * k + 1], oz = offs[3 * k + 2];
+                const double ox = soff[3 * k], oy = soff[3 * k + 1], oz = soff[3 * k + 2];
                 corr = -1.0 / (g.h * sqrt(ox * ox + oy * oy + oz * oz));
             }
             out = qi * (phisite[pt] - phisite[ps]) + qi * qi * corr;
@@ -330,9 +346,10 @@ __global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, int K, c
 
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask)
 {
-    const int64_t tot = c->N * K;
-    launch(c, "slot_lattice", k_slot_lattice, dim3((unsigned)((tot + 255) / 256)), dim3(256), g, c->N, K,
-           c->d_offsets, c->site, c->q, c->site_charge, c->phisite, c->F, c->s2 ? 1 : 0, dU, mask);
+    const uint32_t NK = (uint32_t)(c->N * K);
+    const uint32_t kmul = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)K);
+    launch(c, "slot_lattice", k_slot_lattice, dim3((NK + 255) / 256), dim3(256), g, NK, (uint32_t)K, kmul,
+           c->d_offsets, c->ijk, c->q, c->site_charge, c->phisite, c->F, c->s2 ? 1 : 0, dU, mask);
 }
 
 // ---- far-field helpers (LDS-tiled matrix-vector products with R) ----------
@@ -378,7 +395,7 @@ __global__ __launch_bounds__(256) void k_sigma_sites(Geo g, int p, const double 
 //   -sum_{nu in V_box} 1/|t - r - a nu| + C_box / a + 1/2 (sigma(t) + sigma(r)) - B(t, r)
 // for charge i at site r and its wrapped target t (charges listed in `which`).
 __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, const int64_t *__restrict__ which,
-                                                int K, const int32_t *__restrict__ offs,
+                                                int64_t first, int K, const int32_t *__restrict__ offs,
                                                 const int32_t *__restrict__ site, const double *__restrict__ R,
                                                 const double *__restrict__ sigma, double *__restrict__ F)
 {
@@ -388,7 +405,7 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
     const int n = g.n;
     const int64_t c0 = (int64_t)blockIdx.x * SB;
     if (threadIdx.x < SB && c0 + threadIdx.x < count) {
-        const int64_t i = which ? which[c0 + threadIdx.x] : c0 + threadIdx.x;
+        const int64_t i = which ? which[c0 + threadIdx.x] : first + c0 + threadIdx.x;
         const int s = site[i];
         const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
         unit_multipole_and_weights(p, (si + 0.5) * g.h - 0.5 * g.a, (sj + 0.5) * g.h - 0.5 * g.a,
@@ -408,7 +425,7 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
     for (int e = threadIdx.x; e < SB * K; e += blockDim.x) {
         const int b = e / K, k = e % K;
         if (c0 + b >= count) continue;
-        const int64_t i = which ? which[c0 + b] : c0 + b;
+        const int64_t i = which ? which[c0 + b] : first + c0 + b;
         const int s = site[i];
         const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
         const int ti = posmod(si + offs[3 * k], n), tj = posmod(sj + offs[3 * k + 1], n),
@@ -436,11 +453,112 @@ void launch_sigma(fmmkmc_ctx *c, const Geo &g)
                c->far.R, c->far.sigma);
 }
 
-void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K)
+void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K, int64_t first)
 {
     const size_t shm = sizeof(double) * 2 * SB * c->nt;
     launch_shm(c, "f_rows", k_f_rows, dim3((unsigned)((count + SB - 1) / SB)), dim3(256), shm, g, c->p, count,
-               which, K, c->d_offsets, c->site, c->far.R, c->far.sigma, c->F);
+               which, first, K, c->d_offsets, c->site, c->far.R, c->far.sigma, c->F);
+}
+
+// ---- dU of one move (accept step), one block, FP64 ----------------------------
+
+__device__ inline double block_sum(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// Same terms as a proposal (header of this file), recomputed for the accepted
+// move (footnote to Sec. 3.1), always from the FP64 local expansions.
+__global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_t i, double tx, double ty, double tz,
+                                                 const double *__restrict__ psi, const double *__restrict__ x,
+                                                 const double *__restrict__ y, const double *__restrict__ z,
+                                                 const double *__restrict__ q, const int32_t *__restrict__ cnt,
+                                                 const int32_t *__restrict__ slots, const double *__restrict__ R,
+                                                 const double *__restrict__ H, double *__restrict__ out)
+{
+    const int nt = nterms(p);
+    extern __shared__ double sm[];
+    double *Wt = sm, *Wr = sm + nt, *Kt = sm + 2 * nt, *Kr = sm + 3 * nt, *Ft = sm + 4 * nt, *Fr = sm + 5 * nt;
+    double *red = sm + 6 * nt;
+    const double rx = x[i], ry = y[i], rz = z[i], qi = q[i];
+    const int tcx = fine_coord(tx, g.w, g.nc), tcy = fine_coord(ty, g.w, g.nc), tcz = fine_coord(tz, g.w, g.nc);
+    const int rcx = fine_coord(rx, g.w, g.nc), rcy = fine_coord(ry, g.w, g.nc), rcz = fine_coord(rz, g.w, g.nc);
+    const int64_t tcell = cell_id(g.nc, tcx, tcy, tcz), rcell = cell_id(g.nc, rcx, rcy, rcz);
+    const double c = 0.5 * g.a;
+    if (threadIdx.x == 0)
+        l2p_weights(p, tx - (tcx + 0.5) * g.w, ty - (tcy + 0.5) * g.w, tz - (tcz + 0.5) * g.w, Wt);
+    if (threadIdx.x == 1)
+        l2p_weights(p, rx - (rcx + 0.5) * g.w, ry - (rcy + 0.5) * g.w, rz - (rcz + 0.5) * g.w, Wr);
+    if (g.periodic && threadIdx.x == 2) unit_multipole_and_weights(p, tx - c, ty - c, tz - c, Kt, Ft);
+    if (g.periodic && threadIdx.x == 3) unit_multipole_and_weights(p, rx - c, ry - c, rz - c, Kr, Fr);
+    __syncthreads();
+    double part = 0.0;
+    for (int k = threadIdx.x; k < nt; k += blockDim.x)
+        part += qi * (psi[(int64_t)k * M + tcell] * Wt[k] - psi[(int64_t)k * M + rcell] * Wr[k]);
+    // near fields of the two points
+    const int items = 2 * 27 * g.cap;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int e = it / (27 * g.cap), rem = it % (27 * g.cap), nb = rem / g.cap, sl = rem % g.cap;
+        const int bx = e ? rcx : tcx, by = e ? rcy : tcy, bz = e ? rcz : tcz;
+        int ax = bx + nb / 9 - 1, ay = by + (nb / 3) % 3 - 1, az = bz + nb % 3 - 1;
+        double shx = 0, shy = 0, shz = 0;
+        if (ax < 0 || ax >= g.nc || ay < 0 || ay >= g.nc || az < 0 || az >= g.nc) {
+            if (!g.periodic) continue;
+            shx = g.a * floordiv(ax, g.nc);
+            shy = g.a * floordiv(ay, g.nc);
+            shz = g.a * floordiv(az, g.nc);
+            ax = posmod(ax, g.nc);
+            ay = posmod(ay, g.nc);
+            az = posmod(az, g.nc);
+        }
+        const int64_t nbc = cell_id(g.nc, ax, ay, az);
+        if (sl >= cnt[nbc]) continue;
+        const int j = slots[nbc * g.cap + sl];
+        if (e == 1 && j == i && shx == 0 && shy == 0 && shz == 0) continue;
+        const double px = e ? rx : tx, py = e ? ry : ty, pz = e ? rz : tz;
+        const double d0 = px - (x[j] + shx), d1 = py - (y[j] + shy), d2 = pz - (z[j] + shz);
+        const double v = qi * q[j] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        part += e ? -v : v;
+    }
+    if (g.periodic) {
+        for (int k = threadIdx.x; k < nt; k += blockDim.x) Kt[k] = qi * (Kt[k] - Kr[k]);
+        __syncthreads();
+        for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+            double dh = 0.0;
+            for (int m = 0; m < nt; ++m) dh += R[(int64_t)m * nt + k] * Kt[m];
+            part += qi * (Ft[k] - Fr[k]) * (H[k] + 0.5 * dh);
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (g.periodic) {
+            double self = 0.0;
+            for (int a0 = -1; a0 <= 1; ++a0)
+                for (int a1 = -1; a1 <= 1; ++a1)
+                    for (int a2 = -1; a2 <= 1; ++a2) {
+                        const double d0 = tx - rx - g.a * a0, d1 = ty - ry - g.a * a1, d2 = tz - rz - g.a * a2;
+                        self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                    }
+            part += -qi * qi * self + qi * qi * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
+        } else {
+            const double d0 = tx - rx, d1 = ty - ry, d2 = tz - rz;
+            part -= qi * qi / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+    }
+    const double tot = block_sum(part, red);
+    if (threadIdx.x == 0) out[0] = tot;
+}
+
+void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out)
+{
+    const size_t shm = sizeof(double) * (6 * c->nt + 256);
+    launch_shm(c, "move_dU", k_move_dU, dim3(1), dim3(256), shm, g, c->p, c->M, i, t[0], t[1], t[2], c->psi_lv[c->L],
+               c->x, c->y, c->z, c->q, c->cell_cnt, c->cell_slots, c->far.R, c->far.H, out);
 }
 
 // ---- generic proposals ----------------------------------------------------

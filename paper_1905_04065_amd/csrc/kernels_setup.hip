@@ -231,30 +231,43 @@ void launch_downward(fmmkmc_ctx *c)
 
 // ---- far field -----------------------------------------------------------
 
-// H = R K (R stored [n][k]) then C = G H; one block.
+// H = R K and C = (G R) K: one lane per output row, both operators stored
+// column-major ([n][row]) so a wavefront's rows are read with one access.
 __global__ __launch_bounds__(256) void k_far_refresh(int nt, int ncheb, const double *__restrict__ R,
-                                                     const double *__restrict__ K, const double *__restrict__ G,
+                                                     const double *__restrict__ GR, const double *__restrict__ K,
                                                      double *__restrict__ H, double *__restrict__ C)
 {
-    __shared__ double sH[nterms(kMaxOrder)];
-    for (int k = threadIdx.x; k < nt; k += blockDim.x) {
-        double acc = 0.0;
-        for (int n = 0; n < nt; ++n) acc += R[(int64_t)n * nt + k] * K[n];
-        sH[k] = acc;
-        H[k] = acc;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < ncheb; t += blockDim.x) {
-        double acc = 0.0;
-        const double *row = G + (int64_t)t * nt;
-        for (int k = 0; k < nt; ++k) acc += row[k] * sH[k];
-        C[t] = acc;
-    }
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nt + ncheb) return;
+    const bool isH = row < nt;
+    const int r = isH ? row : row - nt;
+    const int ld = isH ? nt : ncheb;
+    const double *A = isH ? R : GR;
+    double acc = 0.0;
+    for (int n = 0; n < nt; ++n) acc += A[(int64_t)n * ld + r] * K[n];
+    if (isH)
+        H[r] = acc;
+    else
+        C[r] = acc;
 }
 
-// Bz[i][j][c] = sum_{a+b <= p-c} C[a][b][c] T_a(xi_i) T_b(xi_j)
-__global__ __launch_bounds__(256) void k_cheb_columns(int p, int n, const double *__restrict__ C,
-                                                      const double *__restrict__ Tax, double *__restrict__ Bz)
+// Chebyshev columns in two passes:
+//   A[i][b][c]  = sum_{a <= p-b-c} C[a][b][c] T_a(xi_i)
+//   Bz[i][j][c] = sum_{b <= p-c}   A[i][b][c] T_b(xi_j)
+__global__ __launch_bounds__(256) void k_cheb_a(int p, int n, const double *__restrict__ C,
+                                                const double *__restrict__ Tax, double *__restrict__ A)
+{
+    const int q = p + 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * q * q) return;
+    const int cc = (int)(t % q), b = (int)((t / q) % q), i = (int)(t / (q * q));
+    double acc = 0.0;
+    for (int a = 0; a + b + cc <= p; ++a) acc += C[(a * q + b) * q + cc] * Tax[i * q + a];
+    A[t] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_cheb_b(int p, int n, const double *__restrict__ A,
+                                                const double *__restrict__ Tax, double *__restrict__ Bz)
 {
     const int q = p + 1;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -263,23 +276,21 @@ __global__ __launch_bounds__(256) void k_cheb_columns(int p, int n, const double
     const int64_t ij = t / q;
     const int i = (int)(ij / n), j = (int)(ij % n);
     double acc = 0.0;
-    for (int a = 0; a + cc <= p; ++a) {
-        double inner = 0.0;
-        for (int b = 0; a + b + cc <= p; ++b) inner += C[(a * q + b) * q + cc] * Tax[j * q + b];
-        acc += Tax[i * q + a] * inner;
-    }
+    for (int b = 0; b + cc <= p; ++b) acc += A[((int64_t)i * q + b) * q + cc] * Tax[j * q + b];
     Bz[t] = acc;
 }
 
 void launch_far_refresh(fmmkmc_ctx *c)
 {
-    const int q = c->p + 1;
-    launch(c, "far_refresh", k_far_refresh, dim3(1), dim3(256), c->nt, q * q * q, c->far.R, c->far.K, c->far.G,
-           c->far.H, c->far.C);
+    const int q = c->p + 1, ncheb = q * q * q;
+    launch(c, "far_refresh", k_far_refresh, dim3((c->nt + ncheb + 255) / 256), dim3(256), c->nt, ncheb, c->far.R,
+           c->far.GR, c->far.K, c->far.H, c->far.C);
     if (c->lat_n > 0) {
-        const int64_t tot = (int64_t)c->lat_n * c->lat_n * q;
-        launch(c, "cheb_columns", k_cheb_columns, dim3((unsigned)((tot + 255) / 256)), dim3(256), c->p, c->lat_n,
-               c->far.C, c->far.Tax, c->far.Bz);
+        const int64_t ta = (int64_t)c->lat_n * q * q, tb = (int64_t)c->lat_n * c->lat_n * q;
+        launch(c, "cheb_a", k_cheb_a, dim3((unsigned)((ta + 255) / 256)), dim3(256), c->p, c->lat_n, c->far.C,
+               c->far.Tax, c->far.A);
+        launch(c, "cheb_b", k_cheb_b, dim3((unsigned)((tb + 255) / 256)), dim3(256), c->p, c->lat_n, c->far.A,
+               c->far.Tax, c->far.Bz);
     }
 }
 
