@@ -106,8 +106,8 @@ def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed):
         step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    names = ["site_phi_s2", "slot_lattice", "sweep", "path", "far_refresh", "cheb_columns", "f_rows", "book",
-             "prepare_targets", "point_phi", "generic_far", "generic_combine"]
+    names = ["site_phi_s2", "site_phi", "slot_lattice", "sweep", "path", "far_refresh", "cheb_a", "cheb_b", "f_rows",
+             "f_row1", "book", "move_dU"]
     ktimes = {nm: ctx.kernel_time(nm) for nm in names}
     ctx.set_profiling(False)
     # propose-only timing (no commit) for the proposal rate

@@ -116,7 +116,9 @@ void release(fmmkmc_ctx *c)
     dfree(c->cell_cnt);
     dfree(c->cell_slots);
     dfree(c->site_charge);
-    dfree(c->ijk);
+    dfree(c->order);
+    dfree(c->q_r);
+    dfree(c->ijk_r);
     dfree(c->qsite);
     dfree(c->qsite32);
     for (auto &p : c->phi_lv) dfree(p);
@@ -136,6 +138,7 @@ void release(fmmkmc_ctx *c)
     dfree(c->far.H);
     dfree(c->far.R);
     dfree(c->far.GR);
+    dfree(c->far.cz);
     dfree(c->far.A);
     dfree(c->far.C);
     dfree(c->far.Bz);
@@ -238,24 +241,33 @@ void build_far(fmmkmc_ctx *c)
         for (int n = 0; n < nt; ++n) RT[(size_t)n * nt + k] = R[(size_t)k * nt + n];
     c->far.R = dalloc<double>(RT.size());
     upload(c->far.R, RT.data(), RT.size(), c->stream);
-    // C = G H = (G R) K: fold R into the Chebyshev map once; stored [n][t]
-    std::vector<double> G((size_t)ncheb * nt), GRT((size_t)nt * ncheb, 0.0);
+    // C = G H = (G R) K: fold R into the Chebyshev map once; only the rows of
+    // total degree a + b + c <= p are nonzero; stored [n][row]
+    std::vector<double> G((size_t)ncheb * nt);
     build_cheb_map(p, c->a, G.data());
-    for (int t = 0; t < ncheb; ++t) {
-        const double *g = &G[(size_t)t * nt];
-        bool any = false;
-        for (int k = 0; k < nt; ++k) any |= g[k] != 0.0;
-        if (!any) continue;
+    std::vector<int32_t> cz;
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b)
+            for (int cc = 0; cc < q; ++cc)
+                if (a + b + cc <= p) cz.push_back((a * q + b) * q + cc);
+    const int ncz = (int)cz.size();
+    std::vector<double> GRT((size_t)nt * ncz, 0.0);
+    for (int r = 0; r < ncz; ++r) {
+        const double *g = &G[(size_t)cz[r] * nt];
         for (int n = 0; n < nt; ++n) {
             double s = 0.0;
             for (int k = 0; k < nt; ++k) s += g[k] * R[(size_t)k * nt + n];
-            GRT[(size_t)n * ncheb + t] = s;
+            GRT[(size_t)n * ncz + r] = s;
         }
     }
+    c->far.ncz = ncz;
     c->far.GR = dalloc<double>(GRT.size());
     upload(c->far.GR, GRT.data(), GRT.size(), c->stream);
+    c->far.cz = dalloc<int32_t>(ncz);
+    upload(c->far.cz, cz.data(), ncz, c->stream);
     HIPCHK(hipStreamSynchronize(c->stream));
     c->far.C = dalloc<double>((size_t)q * q * q);
+    HIPCHK(hipMemsetAsync(c->far.C, 0, sizeof(double) * q * q * q, c->stream));
     c->far.H = dalloc<double>(nt);
     c->far.K = c->phi_lv[1];
     if (c->lat_n > 0) {
@@ -431,16 +443,27 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
     if (c->lat_n > 0) {
         const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
         {
-            std::vector<int32_t> sc(ns, -1), pk(n);
-            for (int64_t i = 0; i < n; ++i) {
-                const int64_t st = c->hsite[i];
-                sc[site_order(c, st)] = (int32_t)i;
-                pk[i] = pack_ijk(c, st);
+            std::vector<int32_t> sc(ns, -1), ord, pk(n);
+            std::vector<double> qr(n);
+            for (int64_t i = 0; i < n; ++i) sc[site_order(c, c->hsite[i])] = (int32_t)i;
+            ord.reserve(n);
+            for (int64_t so = 0; so < ns; ++so)
+                if (sc[so] >= 0) ord.push_back(sc[so]);
+            c->hrank.assign(n, 0);
+            for (int64_t r = 0; r < n; ++r) {
+                const int32_t i = ord[r];
+                c->hrank[i] = (int32_t)r;
+                pk[r] = pack_ijk(c, c->hsite[i]);
+                qr[r] = c->hq[i];
             }
             c->site_charge = dalloc<int32_t>(ns);
             upload(c->site_charge, sc.data(), ns, s);
-            c->ijk = dalloc<int32_t>(n);
-            upload(c->ijk, pk.data(), n, s);
+            c->order = dalloc<int32_t>(n);
+            upload(c->order, ord.data(), n, s);
+            c->ijk_r = dalloc<int32_t>(n);
+            upload(c->ijk_r, pk.data(), n, s);
+            c->q_r = dalloc<double>(n);
+            upload(c->q_r, qr.data(), n, s);
             HIPCHK(hipStreamSynchronize(s));
         }
         c->phisite = dalloc<double>(ns);
@@ -723,7 +746,7 @@ int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double 
                 }
                 dfree(c->F);
                 c->F = dalloc<double>((size_t)c->N * K);
-                launch_f_rows(c, g, c->N, nullptr, K);
+                launch_f_rows(c, g, c->N, K, 0);
             }
             c->F_offsets = off;
         }
@@ -806,6 +829,7 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
             a.old_sord = site_order(c, old_site);
             a.new_sord = site_order(c, new_site);
             a.new_ijk = pack_ijk(c, new_site);
+            a.rank = c->hrank[i];
         }
         launch_commit(c, g, a);
         if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c);
@@ -832,7 +856,7 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
         }
         // lattice proposal table row of the moved charge
         if (c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty())
-            launch_f_rows(c, g, 1, nullptr, (int)c->F_offsets.size() / 3, i);
+            launch_f_rows(c, g, 1, (int)c->F_offsets.size() / 3, c->hrank[i]);
         double dUh = 0;
         HIPCHK(hipMemcpyAsync(&dUh, dUd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

@@ -44,7 +44,9 @@ struct FarField {
     double *K = nullptr;      // multipole of the box about its centre (nt)
     double *H = nullptr;      // local expansion of the copies in V_inf (nt)
     double *R = nullptr;      // far operator, [k][n] (nt x nt)
-    double *GR = nullptr;     // Chebyshev map times R, column-major [nt][(p+1)^3]
+    double *GR = nullptr;     // Chebyshev map times R, nonzero rows only, column-major [nt][ncz]
+    int32_t *cz = nullptr;    // index in the (p+1)^3 coefficient array of each nonzero row
+    int ncz = 0;
     double *C = nullptr;      // Chebyshev coefficients (p+1)^3
     double *A = nullptr;      // lattice: [n][p+1][p+1] partial sums over x
     double *Bz = nullptr;     // lattice: [n][n][p+1] partial sums over x and y
@@ -74,7 +76,12 @@ struct fmmkmc_ctx {
     int32_t *cell_cnt = nullptr, *cell_slots = nullptr;
     int32_t *site_charge = nullptr;  // lattice: charge on each site or -1, in site order
                                      // (cell-major on the 2x2x2 path, lattice order otherwise)
-    int32_t *ijk = nullptr;          // lattice: packed site coordinates of each charge (i<<20 | j<<10 | k)
+    // lattice: charges ranked in site order (spatial locality of the per-slot
+    // gathers); by rank: charge index, charge, packed site coordinates
+    // (i<<20 | j<<10 | k); the hop table F is stored by rank as well
+    int32_t *order = nullptr;
+    double *q_r = nullptr;
+    int32_t *ijk_r = nullptr;
     double *qsite = nullptr;         // 2x2x2 lattice: charge per site, cell-major order
     float *qsite32 = nullptr;
 
@@ -110,5 +117,5 @@ struct fmmkmc_ctx {
 
     // host mirrors
     std::vector<double> hx, hy, hz, hq;
-    std::vector<int32_t> hcell, hslot, hsite, hcnt, hslots, hsite_charge;
+    std::vector<int32_t> hcell, hslot, hsite, hcnt, hslots, hsite_charge, hrank;
 };

@@ -43,6 +43,7 @@ struct CommitArgs {
     int64_t old_site, new_site;  // lattice order, -1 without a lattice
     int64_t old_sord, new_sord;  // the same sites in the device's site order
     int32_t new_ijk;             // packed coordinates of the new site
+    int32_t rank = 0;            // the moved charge's rank in site order
 };
 
 Geo make_geo(const fmmkmc_ctx *c);
@@ -59,8 +60,8 @@ void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz,
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g);
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask);
 void launch_sigma(fmmkmc_ctx *c, const Geo &g);
-// F rows of charges which[0..count) or, without which, first..first+count-1
-void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K, int64_t first = 0);
+// F rows of the charges of ranks first..first+count-1
+void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, int K, int64_t first);
 // work: at least 8 S doubles; use: optional per-slot flag (0 = skip, NaN out)
 void launch_generic(fmmkmc_ctx *c, const Geo &g, int64_t S, const double *tgt, const int64_t *charge, double *dU,
                     double *work, const int32_t *use = nullptr);

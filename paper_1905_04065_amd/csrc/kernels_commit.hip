@@ -233,12 +233,13 @@ struct Book {
     int64_t new_site;     // lattice order, -1 without a lattice
     int64_t old_sord, new_sord;  // site order (cell-major on the 2x2x2 path)
     int32_t new_ijk;
+    int32_t rank;
     int s2;               // per-site charges are kept (2x2x2 path)
     int same_cell;        // the move stays inside one fine cell: slots unchanged
 };
 
 __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, int32_t *slot, int32_t *site,
-                       int32_t *ijk, int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge, double *qsite,
+                       int32_t *ijk_r, int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge, double *qsite,
                        float *qsite32)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -262,7 +263,7 @@ __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, i
         site_charge[b.old_sord] = -1;
         site_charge[b.new_sord] = (int32_t)b.i;
         site[b.i] = (int32_t)b.new_site;
-        ijk[b.i] = b.new_ijk;
+        ijk_r[b.rank] = b.new_ijk;
         if (b.s2) {
             qsite[b.old_sord] = 0.0;
             qsite[b.new_sord] = b.q;
@@ -312,9 +313,10 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
     b.old_sord = a.old_sord;
     b.new_sord = a.new_sord;
     b.new_ijk = a.new_ijk;
+    b.rank = a.rank;
     b.s2 = c->s2 ? 1 : 0;
     b.same_cell = a.old_cell == a.new_cell ? 1 : 0;
-    launch(c, "book", k_book, dim3(1), dim3(64), b, c->x, c->y, c->z, c->cell, c->slot, c->site, c->ijk,
+    launch(c, "book", k_book, dim3(1), dim3(64), b, c->x, c->y, c->z, c->cell, c->slot, c->site, c->ijk_r,
            c->cell_cnt, c->cell_slots, c->cap, c->site_charge, c->qsite, c->qsite32);
 }
 

@@ -207,6 +207,9 @@ __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const dou
                                                      double *__restrict__ phisite)
 {
     constexpr int NT = nterms(P);
+    constexpr int K0 = MIXED ? 1 : 0;  // mixed: the constant term is added in FP64 below
+    constexpr int KBATCH = 16;         // coefficient loads in flight per lane
+    constexpr int CBATCH = 3;          // neighbour cells loaded together
     using Real = typename std::conditional<MIXED, float, double>::type;
     const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= M) return;
@@ -214,33 +217,46 @@ __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const dou
     const int cx = (int)(cell / ((int64_t)nc * nc)), cy = (int)((cell / nc) % nc), cz = (int)(cell % nc);
     const Real *Yt = MIXED ? (const Real *)Y2f : (const Real *)Y2;
     const Real *Tt = MIXED ? (const Real *)T2f : (const Real *)T2;
+    const Real *Ps = MIXED ? (const Real *)psi32 : (const Real *)psi;
+    const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
     Real far_[8], near_[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) far_[u] = near_[u] = Real(0);
-    // L2P at the 8 sites
-#pragma unroll 4
-    for (int k = MIXED ? 1 : 0; k < NT; ++k) {
-        const Real v = MIXED ? (Real)psi32[(int64_t)k * M + cell] : (Real)psi[(int64_t)k * M + cell];
+    // L2P at the 8 sites: coefficient rows streamed KBATCH at a time
+#pragma unroll 1
+    for (int kb = K0; kb < NT; kb += KBATCH) {
+        Real v[KBATCH];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) far_[u] += Yt[u * NT + k] * v;
+        for (int t = 0; t < KBATCH; ++t)
+            if (kb + t < NT) v[t] = Ps[(int64_t)(kb + t) * M + cell];
+#pragma unroll
+        for (int t = 0; t < KBATCH; ++t)
+            if (kb + t < NT)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) far_[u] += Yt[u * NT + kb + t] * v[t];
     }
-    // near field: the 27 neighbour cells' 8 sites each
-    for (int nb = 0; nb < 27; ++nb) {
-        int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
-        if (ax < 0 || ax >= nc || ay < 0 || ay >= nc || az < 0 || az >= nc) {
-            if (!g.periodic) continue;
-            ax = posmod(ax, nc);
-            ay = posmod(ay, nc);
-            az = posmod(az, nc);
+    // near field: the 27 neighbour cells' 8 sites each (wrapped, or absent in free space)
+#pragma unroll 1
+    for (int nb0 = 0; nb0 < 27; nb0 += CBATCH) {
+        Real qv[CBATCH][8];
+#pragma unroll
+        for (int b = 0; b < CBATCH; ++b) {
+            const int nb = nb0 + b;
+            int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
+            const bool ok = g.periodic || (ax >= 0 && ax < nc && ay >= 0 && ay < nc && az >= 0 && az < nc);
+            ax += ax < 0 ? nc : (ax >= nc ? -nc : 0);
+            ay += ay < 0 ? nc : (ay >= nc ? -nc : 0);
+            az += az < 0 ? nc : (az >= nc ? -nc : 0);
+            const int64_t base = cell_id(nc, ax, ay, az) * 8;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) qv[b][v] = ok ? Qs[base + v] : Real(0);
         }
-        const int64_t base = cell_id(nc, ax, ay, az) * 8;
-        Real qv[8];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) qv[v] = MIXED ? (Real)qsite32[base + v] : (Real)qsite[base + v];
+        for (int b = 0; b < CBATCH; ++b)
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int v = 0; v < 8; ++v) near_[u] += Tt[u * 216 + nb * 8 + v] * qv[v];
+                for (int v = 0; v < 8; ++v) near_[u] += Tt[u * 216 + (nb0 + b) * 8 + v] * qv[b][v];
     }
     const double l00 = MIXED ? psi[cell] : 0.0;
 #pragma unroll
@@ -288,7 +304,8 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
 // (cell-major on the 2x2x2 path), so a hop's two gathers share cache lines.
 __global__ __launch_bounds__(256) void k_slot_lattice(Geo g, uint32_t NK, uint32_t K, uint32_t kmul,
                                                       const int32_t *__restrict__ offs,
-                                                      const int32_t *__restrict__ ijk, const double *__restrict__ q,
+                                                      const int32_t *__restrict__ order,
+                                                      const int32_t *__restrict__ ijk_r, const double *__restrict__ q_r,
                                                       const int32_t *__restrict__ site_charge,
                                                       const double *__restrict__ phisite,
                                                       const double *__restrict__ F, int s2,
@@ -299,14 +316,14 @@ __global__ __launch_bounds__(256) void k_slot_lattice(Geo g, uint32_t NK, uint32
     __syncthreads();
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= NK) return;
-    uint32_t i = __umulhi(t, kmul);
-    uint32_t k = t - i * K;
+    uint32_t r = __umulhi(t, kmul);
+    uint32_t k = t - r * K;
     if (k >= K) {
-        ++i;
+        ++r;
         k -= K;
     }
     const int n = g.n, nc = g.nc;
-    const int32_t pk = ijk[i];
+    const int32_t pk = ijk_r[r];
     const int si = pk >> 20, sj = (pk >> 10) & 1023, sk = pk & 1023;
     int ti = si + soff[3 * k], tj = sj + soff[3 * k + 1], tk = sk + soff[3 * k + 2];
     bool valid = true;
@@ -329,10 +346,10 @@ __global__ __launch_bounds__(256) void k_slot_lattice(Geo g, uint32_t NK, uint32
         }
         valid = site_charge[pt] < 0;
         if (valid) {
-            const double qi = q[i];
+            const double qi = q_r[r];
             double corr;
             if (g.periodic) {
-                corr = F[t];
+                corr = F[t];  // stored by rank
             } else {
                 const double ox = soff[3 * k], oy = soff[3 * k + 1], oz = soff[3 * k + 2];
                 corr = -1.0 / (g.h * sqrt(ox * ox + oy * oy + oz * oz));
@@ -340,8 +357,9 @@ __global__ __launch_bounds__(256) void k_slot_lattice(Geo g, uint32_t NK, uint32
             out = qi * (phisite[pt] - phisite[ps]) + qi * qi * corr;
         }
     }
-    dU[t] = out;
-    if (mask) mask[t] = valid ? 1 : 0;
+    const int64_t o = (int64_t)order[r] * K + k;
+    dU[o] = out;
+    if (mask) mask[o] = valid ? 1 : 0;
 }
 
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask)
@@ -349,7 +367,7 @@ void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t
     const uint32_t NK = (uint32_t)(c->N * K);
     const uint32_t kmul = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)K);
     launch(c, "slot_lattice", k_slot_lattice, dim3((NK + 255) / 256), dim3(256), g, NK, (uint32_t)K, kmul,
-           c->d_offsets, c->ijk, c->q, c->site_charge, c->phisite, c->F, c->s2 ? 1 : 0, dU, mask);
+           c->d_offsets, c->order, c->ijk_r, c->q_r, c->site_charge, c->phisite, c->F, c->s2 ? 1 : 0, dU, mask);
 }
 
 // ---- far-field helpers (LDS-tiled matrix-vector products with R) ----------
@@ -393,8 +411,8 @@ __global__ __launch_bounds__(256) void k_sigma_sites(Geo g, int p, const double 
 
 // F[i][k] for the lattice fast path (periodic): the q^2-terms of a hop,
 //   -sum_{nu in V_box} 1/|t - r - a nu| + C_box / a + 1/2 (sigma(t) + sigma(r)) - B(t, r)
-// for charge i at site r and its wrapped target t (charges listed in `which`).
-__global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, const int64_t *__restrict__ which,
+// for charge i at site r and its wrapped target t (charges given by rank).
+__global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, const int32_t *__restrict__ order,
                                                 int64_t first, int K, const int32_t *__restrict__ offs,
                                                 const int32_t *__restrict__ site, const double *__restrict__ R,
                                                 const double *__restrict__ sigma, double *__restrict__ F)
@@ -405,7 +423,7 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
     const int n = g.n;
     const int64_t c0 = (int64_t)blockIdx.x * SB;
     if (threadIdx.x < SB && c0 + threadIdx.x < count) {
-        const int64_t i = which ? which[c0 + threadIdx.x] : first + c0 + threadIdx.x;
+        const int64_t i = order[first + c0 + threadIdx.x];
         const int s = site[i];
         const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
         unit_multipole_and_weights(p, (si + 0.5) * g.h - 0.5 * g.a, (sj + 0.5) * g.h - 0.5 * g.a,
@@ -425,7 +443,7 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
     for (int e = threadIdx.x; e < SB * K; e += blockDim.x) {
         const int b = e / K, k = e % K;
         if (c0 + b >= count) continue;
-        const int64_t i = which ? which[c0 + b] : first + c0 + b;
+        const int64_t rk = first + c0 + b, i = order[rk];
         const int s = site[i];
         const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
         const int ti = posmod(si + offs[3 * k], n), tj = posmod(sj + offs[3 * k + 1], n),
@@ -441,7 +459,73 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
                 }
         const double B = l2p_runtime(p, Wv + b * nt, 1, tx - 0.5 * g.a, ty - 0.5 * g.a, tz - 0.5 * g.a);
         const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
-        F[i * K + k] = -self + cbox + 0.5 * (sigma[ts] + sigma[s]) - B;
+        F[rk * K + k] = -self + cbox + 0.5 * (sigma[ts] + sigma[s]) - B;
+    }
+}
+
+// F row of one charge (after an accept): K target harmonics in LDS, w = R K1(r)
+// with each output split over 16 lanes, then one dot product per hop.
+__global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, const int32_t *__restrict__ order, int K,
+                                                const int32_t *__restrict__ offs, const int32_t *__restrict__ site,
+                                                const double *__restrict__ R, const double *__restrict__ sigma,
+                                                double *__restrict__ F)
+{
+    const int nt = nterms(p);
+    extern __shared__ double sm[];
+    double *Wt = sm, *K1 = sm + (int64_t)K * nt, *w = K1 + nt, *Wr = w + nt, *red = Wr + nt;  // red: 256
+    const int n = g.n;
+    const int64_t i = order[rank];
+    const int s = site[i];
+    const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
+    const double c = 0.5 * g.a;
+    const double rx = (si + 0.5) * g.h, ry = (sj + 0.5) * g.h, rz = (sk + 0.5) * g.h;
+    const int tid = threadIdx.x;
+    if (tid < K) {
+        const int ti = posmod(si + offs[3 * tid], n), tj = posmod(sj + offs[3 * tid + 1], n),
+                  tk = posmod(sk + offs[3 * tid + 2], n);
+        l2p_weights(p, (ti + 0.5) * g.h - c, (tj + 0.5) * g.h - c, (tk + 0.5) * g.h - c, Wt + (int64_t)tid * nt);
+    }
+    if (tid == K) unit_multipole_and_weights(p, rx - c, ry - c, rz - c, K1, Wr);
+    __syncthreads();
+    // w = R K1: rows split over 16 lanes
+    for (int r0 = 0; r0 < nt; r0 += 16) {
+        const int lr = tid & 15, ls = tid >> 4, row = r0 + lr;
+        double acc = 0.0;
+        if (row < nt)
+            for (int m = ls; m < nt; m += 16) acc += R[(int64_t)m * nt + row] * K1[m];
+        red[tid] = acc;
+        __syncthreads();
+        if (ls == 0 && row < nt) {
+            double sum = 0.0;
+            for (int t = 0; t < 16; ++t) sum += red[t * 16 + lr];
+            w[row] = sum;
+        }
+        __syncthreads();
+    }
+    // B_k = W(t_k) . w, hops split over 256 / K lanes each (at least 4)
+    const int per = blockDim.x / K;
+    double b = 0.0;
+    const int hk = tid / per, ls = tid % per;
+    if (hk < K)
+        for (int m = ls; m < nt; m += per) b += Wt[(int64_t)hk * nt + m] * w[m];
+    red[tid] = b;
+    __syncthreads();
+    if (tid < K) {
+        double B = 0.0;
+        for (int t = 0; t < per; ++t) B += red[tid * per + t];
+        const int ti = posmod(si + offs[3 * tid], n), tj = posmod(sj + offs[3 * tid + 1], n),
+                  tk = posmod(sk + offs[3 * tid + 2], n);
+        const double tx = (ti + 0.5) * g.h, ty = (tj + 0.5) * g.h, tz = (tk + 0.5) * g.h;
+        double self = 0.0;
+        for (int a0 = -1; a0 <= 1; ++a0)
+            for (int a1 = -1; a1 <= 1; ++a1)
+                for (int a2 = -1; a2 <= 1; ++a2) {
+                    const double d0 = tx - rx - g.a * a0, d1 = ty - ry - g.a * a1, d2 = tz - rz - g.a * a2;
+                    self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                }
+        const double cbox = (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
+        const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
+        F[rank * K + tid] = -self + cbox + 0.5 * (sigma[ts] + sigma[s]) - B;
     }
 }
 
@@ -453,11 +537,17 @@ void launch_sigma(fmmkmc_ctx *c, const Geo &g)
                c->far.R, c->far.sigma);
 }
 
-void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, const int64_t *which, int K, int64_t first)
+void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, int K, int64_t first)
 {
+    const size_t shm1 = sizeof(double) * ((size_t)(K + 3) * c->nt + 256);
+    if (count == 1 && K <= 64 && shm1 <= 64 * 1024) {
+        launch_shm(c, "f_row1", k_f_row1, dim3(1), dim3(256), shm1, g, c->p, first, c->order, K, c->d_offsets,
+                   c->site, c->far.R, c->far.sigma, c->F);
+        return;
+    }
     const size_t shm = sizeof(double) * 2 * SB * c->nt;
     launch_shm(c, "f_rows", k_f_rows, dim3((unsigned)((count + SB - 1) / SB)), dim3(256), shm, g, c->p, count,
-               which, first, K, c->d_offsets, c->site, c->far.R, c->far.sigma, c->F);
+               c->order, first, K, c->d_offsets, c->site, c->far.R, c->far.sigma, c->F);
 }
 
 // ---- dU of one move (accept step), one block, FP64 ----------------------------
@@ -527,12 +617,17 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
         part += e ? -v : v;
     }
     if (g.periodic) {
-        for (int k = threadIdx.x; k < nt; k += blockDim.x) Kt[k] = qi * (Kt[k] - Kr[k]);
-        __syncthreads();
+        // q dW.H + 1/2 q dW^T R dK with dK = q (K1(t) - K1(r)), dW = W(t) - W(r):
+        // the bilinear form is summed over all (k, n) pairs in parallel
         for (int k = threadIdx.x; k < nt; k += blockDim.x) {
-            double dh = 0.0;
-            for (int m = 0; m < nt; ++m) dh += R[(int64_t)m * nt + k] * Kt[m];
-            part += qi * (Ft[k] - Fr[k]) * (H[k] + 0.5 * dh);
+            Kt[k] = qi * (Kt[k] - Kr[k]);
+            Ft[k] = Ft[k] - Fr[k];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nt; k += blockDim.x) part += qi * Ft[k] * H[k];
+        for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
+            const int m = e / nt, k = e - m * nt;
+            part += 0.5 * qi * Ft[k] * R[e] * Kt[m];
         }
     }
     if (threadIdx.x == 0) {

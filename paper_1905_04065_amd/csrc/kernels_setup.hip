@@ -231,24 +231,35 @@ void launch_downward(fmmkmc_ctx *c)
 
 // ---- far field -----------------------------------------------------------
 
-// H = R K and C = (G R) K: one lane per output row, both operators stored
-// column-major ([n][row]) so a wavefront's rows are read with one access.
-__global__ __launch_bounds__(256) void k_far_refresh(int nt, int ncheb, const double *__restrict__ R,
-                                                     const double *__restrict__ GR, const double *__restrict__ K,
-                                                     double *__restrict__ H, double *__restrict__ C)
+// H = R K and the nonzero Chebyshev coefficients C = (G R) K.  Rows are split
+// over 16 lanes each (partial sums reduced in LDS); both operators are stored
+// column-major ([n][row]).
+__global__ __launch_bounds__(256) void k_far_refresh(int nt, int ncz, const double *__restrict__ R,
+                                                     const double *__restrict__ GR, const int32_t *__restrict__ cz,
+                                                     const double *__restrict__ K, double *__restrict__ H,
+                                                     double *__restrict__ C)
 {
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= nt + ncheb) return;
-    const bool isH = row < nt;
-    const int r = isH ? row : row - nt;
-    const int ld = isH ? nt : ncheb;
-    const double *A = isH ? R : GR;
+    __shared__ double part[16][17];
+    const int lr = threadIdx.x & 15, ls = threadIdx.x >> 4;
+    const int row = blockIdx.x * 16 + lr;
     double acc = 0.0;
-    for (int n = 0; n < nt; ++n) acc += A[(int64_t)n * ld + r] * K[n];
-    if (isH)
-        H[r] = acc;
-    else
-        C[r] = acc;
+    if (row < nt + ncz) {
+        const bool isH = row < nt;
+        const int r = isH ? row : row - nt;
+        const int ld = isH ? nt : ncz;
+        const double *A = isH ? R : GR;
+        for (int n = ls; n < nt; n += 16) acc += A[(int64_t)n * ld + r] * K[n];
+    }
+    part[ls][lr] = acc;
+    __syncthreads();
+    if (ls == 0 && row < nt + ncz) {
+        double s = 0.0;
+        for (int t = 0; t < 16; ++t) s += part[t][lr];
+        if (row < nt)
+            H[row] = s;
+        else
+            C[cz[row - nt]] = s;
+    }
 }
 
 // Chebyshev columns in two passes:
@@ -282,9 +293,9 @@ __global__ __launch_bounds__(256) void k_cheb_b(int p, int n, const double *__re
 
 void launch_far_refresh(fmmkmc_ctx *c)
 {
-    const int q = c->p + 1, ncheb = q * q * q;
-    launch(c, "far_refresh", k_far_refresh, dim3((c->nt + ncheb + 255) / 256), dim3(256), c->nt, ncheb, c->far.R,
-           c->far.GR, c->far.K, c->far.H, c->far.C);
+    const int q = c->p + 1, rows = c->nt + c->far.ncz;
+    launch(c, "far_refresh", k_far_refresh, dim3((rows + 15) / 16), dim3(256), c->nt, c->far.ncz, c->far.R,
+           c->far.GR, c->far.cz, c->far.K, c->far.H, c->far.C);
     if (c->lat_n > 0) {
         const int64_t ta = (int64_t)c->lat_n * q * q, tb = (int64_t)c->lat_n * c->lat_n * q;
         launch(c, "cheb_a", k_cheb_a, dim3((unsigned)((ta + 255) / 256)), dim3(256), c->p, c->lat_n, c->far.C,
