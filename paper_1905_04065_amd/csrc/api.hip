@@ -131,10 +131,8 @@ void release(fmmkmc_ctx *c)
     dfree(c->m2l);
     dfree(c->m2l_index);
     dfree(c->scale);
-    dfree(c->Y2);
-    dfree(c->T2);
-    dfree(c->Y2f);
-    dfree(c->T2f);
+    dfree(c->site_rank);
+    dfree(c->phi_r);
     dfree(c->far.H);
     dfree(c->far.R);
     dfree(c->far.GR);
@@ -458,6 +456,12 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
             }
             c->site_charge = dalloc<int32_t>(ns);
             upload(c->site_charge, sc.data(), ns, s);
+            std::vector<int32_t> sr(ns, -1);
+            for (int64_t so = 0; so < ns; ++so)
+                if (sc[so] >= 0) sr[so] = c->hrank[sc[so]];
+            c->site_rank = dalloc<int32_t>(ns);
+            upload(c->site_rank, sr.data(), ns, s);
+            c->phi_r = dalloc<double>(n);
             c->order = dalloc<int32_t>(n);
             upload(c->order, ord.data(), n, s);
             c->ijk_r = dalloc<int32_t>(n);
@@ -484,17 +488,6 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
                 c->qsite32 = dalloc<float>(ns);
                 upload(c->qsite32, qs32.data(), ns, s);
             }
-            std::vector<double> Y2((size_t)8 * c->nt), T2(8 * 216);
-            build_s2_tables(c->p, c->h, Y2.data(), T2.data());
-            c->Y2 = dalloc<double>(Y2.size());
-            c->T2 = dalloc<double>(T2.size());
-            upload(c->Y2, Y2.data(), Y2.size(), s);
-            upload(c->T2, T2.data(), T2.size(), s);
-            std::vector<float> Yf(Y2.begin(), Y2.end()), Tf(T2.begin(), T2.end());
-            c->Y2f = dalloc<float>(Yf.size());
-            c->T2f = dalloc<float>(Tf.size());
-            upload(c->Y2f, Yf.data(), Yf.size(), s);
-            upload(c->T2f, Tf.data(), Tf.size(), s);
             HIPCHK(hipStreamSynchronize(s));
         }
     }

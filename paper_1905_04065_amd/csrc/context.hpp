@@ -89,7 +89,9 @@ struct fmmkmc_ctx {
     std::vector<double *> phi_lv, psi_lv;  // index = level 1..L
     double **d_phi_ptrs = nullptr;         // device copy of phi_lv
     float *psi32 = nullptr;                // mixed: FP32 copy of psi_lv[L]
-    double *phisite = nullptr;             // lattice: potential per site
+    double *phisite = nullptr;             // lattice: potential per vacant site (NaN if occupied), site order
+    double *phi_r = nullptr;               // lattice: phi_occ of each charge, by rank
+    int32_t *site_rank = nullptr;          // lattice: rank of the charge on each site or -1, site order
 
     // operators (device)
     std::vector<double *> m2m;   // [level] 8 matrices [c][n][k] (parent level 1..L-1)
@@ -97,8 +99,6 @@ struct fmmkmc_ctx {
     double *m2l = nullptr;       // 316 unit-width matrices [o][n][k]
     int32_t *m2l_index = nullptr;  // 343 entries: (dx+3)*49 + (dy+3)*7 + (dz+3) -> o or -1
     double *scale = nullptr;     // [level][2][nt]: w^-deg(n) and w^-(deg(k)+1)
-    double *Y2 = nullptr, *T2 = nullptr;   // 2x2x2 lattice tables
-    float *Y2f = nullptr, *T2f = nullptr;
     fmmkmc::FarField far;
 
     // lattice proposal table (periodic): F[i][k] per charge and hop

@@ -239,8 +239,8 @@ struct Book {
 };
 
 __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, int32_t *slot, int32_t *site,
-                       int32_t *ijk_r, int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge, double *qsite,
-                       float *qsite32)
+                       int32_t *ijk_r, int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge,
+                       int32_t *site_rank, double *qsite, float *qsite32)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     x[b.i] = b.nx;
@@ -262,6 +262,8 @@ __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, i
     if (b.new_site >= 0) {
         site_charge[b.old_sord] = -1;
         site_charge[b.new_sord] = (int32_t)b.i;
+        site_rank[b.old_sord] = -1;
+        site_rank[b.new_sord] = b.rank;
         site[b.i] = (int32_t)b.new_site;
         ijk_r[b.rank] = b.new_ijk;
         if (b.s2) {
@@ -317,7 +319,7 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
     b.s2 = c->s2 ? 1 : 0;
     b.same_cell = a.old_cell == a.new_cell ? 1 : 0;
     launch(c, "book", k_book, dim3(1), dim3(64), b, c->x, c->y, c->z, c->cell, c->slot, c->site, c->ijk_r,
-           c->cell_cnt, c->cell_slots, c->cap, c->site_charge, c->qsite, c->qsite32);
+           c->cell_cnt, c->cell_slots, c->cap, c->site_charge, c->site_rank, c->qsite, c->qsite32);
 }
 
 }  // namespace fmmkmc

@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
                                                           const int32_t *__restrict__ cnt,
                                                           const int32_t *__restrict__ slots,
                                                           const int32_t *__restrict__ site_charge,
-                                                          double *__restrict__ phisite)
+                                                          const int32_t *__restrict__ site_rank,
+                                                          double *__restrict__ phisite, double *__restrict__ phi_r)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int n = g.n;
@@ -189,82 +190,198 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
             }
     phi += MIXED ? (double)nearf : nearv;
     if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
-    phisite[s] = phi;
+    const int32_t rk = site_rank[s];
+    if (rk >= 0) phi_r[rk] = phi;
+    phisite[s] = rk >= 0 ? __builtin_nan("") : phi;
 }
 
 // ---- lattice with 2 x 2 x 2 sites per fine cell ----------------------------
-// One lane per fine cell, 8 sites.  The site offsets inside a cell are the same
-// for every cell, so the L2P weights (Y2) and the near-field 1/r weights (T2)
-// are fixed tables read with wavefront-uniform addresses.
+// One lane per fine cell, 8 sites at offsets (+-h/2, +-h/2, +-h/2) from the
+// centre.  Reflections of a site offset map the L2P weights onto each other:
+//   x -> -x: R_n^m -> (-1)^m conj(R_n^m),  y -> -y: R_n^m -> conj(R_n^m),
+//   z -> -z: R_n^m -> (-1)^(n+m) R_n^m,
+// so the 8 potentials follow from 8 sums (classes by the parities of m and
+// n + m, real or imaginary part) of one weight vector, that of (h/2)(1,1,1).
+// Those weights at unit spacing and the near-field 1/|d| for the offsets of
+// the 27-cell block are compile-time constants; only the powers h^n and 1/h
+// are applied at run time.  No tables are read.
+
+// constexpr square root (Newton from above; exact enough for 1/|d|, |d|^2 <= 27)
+__host__ __device__ constexpr double csqrt(double x)
+{
+    if (x <= 0) return 0.0;
+    double r = x > 1 ? x : 1.0;
+    for (int it = 0; it < 64; ++it) r = 0.5 * (r + x / r);
+    return r;
+}
+
+template <int P>
+struct S2Weights {
+    double w[nterms(P)];  // L2P weights at (1/2, 1/2, 1/2)
+    constexpr S2Weights() : w{}
+    {
+        const double x = 0.5, y = 0.5, z = 0.5, r2 = 0.75;
+        double cm2 = 1.0, cm1 = z;
+        w[0] = 1.0;
+        if (P >= 1) w[slot0(1)] = z;
+        for (int n = 2; n <= P; ++n) {
+            const double c = ((2 * n - 1) * z * cm1 - r2 * cm2) / ((double)(n * n));
+            w[slot0(n)] = c;
+            cm2 = cm1;
+            cm1 = c;
+        }
+        double dr = 1.0, di = 0.0;
+        for (int m = 1; m <= P; ++m) {
+            const double f = -0.5 / m;
+            const double ndr = f * (x * dr - y * di), ndi = f * (x * di + y * dr);
+            dr = ndr;
+            di = ndi;
+            double ar = dr, ai = di;
+            w[slot_re(m, m)] = 2 * ar;
+            w[slot_im(m, m)] = 2 * ai;
+            if (m + 1 > P) continue;
+            double br = z * ar, bi = z * ai;
+            w[slot_re(m + 1, m)] = 2 * br;
+            w[slot_im(m + 1, m)] = 2 * bi;
+            for (int n = m + 2; n <= P; ++n) {
+                const double q = 1.0 / ((double)((n + m) * (n - m)));
+                const double cr = ((2 * n - 1) * z * br - r2 * ar) * q;
+                const double ci = ((2 * n - 1) * z * bi - r2 * ai) * q;
+                w[slot_re(n, m)] = 2 * cr;
+                w[slot_im(n, m)] = 2 * ci;
+                ar = br;
+                ai = bi;
+                br = cr;
+                bi = ci;
+            }
+        }
+    }
+};
+
+// 1 / sqrt(d2) for the squared offsets of the 27-cell block (d2 <= 27)
+struct InvSqrt {
+    double v[28];
+    constexpr InvSqrt() : v{}
+    {
+        for (int i = 1; i < 28; ++i) v[i] = 1.0 / csqrt((double)i);
+    }
+};
+
+// squared offset (unit spacing) between site u of a cell and site v of neighbour nb
+__host__ __device__ constexpr int s2_d2(int u, int nb, int v)
+{
+    const int dx = 2 * (nb / 9 - 1) + (v >> 2) - (u >> 2);
+    const int dy = 2 * ((nb / 3) % 3 - 1) + ((v >> 1) & 1) - ((u >> 1) & 1);
+    const int dz = 2 * (nb % 3 - 1) + (v & 1) - (u & 1);
+    return dx * dx + dy * dy + dz * dz;
+}
+
 template <int P, bool MIXED>
 __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const double *__restrict__ psi,
-                                                     const float *__restrict__ psi32, const double *__restrict__ Y2,
-                                                     const double *__restrict__ T2, const float *__restrict__ Y2f,
-                                                     const float *__restrict__ T2f,
+                                                     const float *__restrict__ psi32,
                                                      const double *__restrict__ qsite,
                                                      const float *__restrict__ qsite32,
+                                                     const int32_t *__restrict__ site_rank,
                                                      const double *__restrict__ Bz, const double *__restrict__ Tax,
-                                                     double *__restrict__ phisite)
+                                                     double *__restrict__ phisite, double *__restrict__ phi_r)
 {
-    constexpr int NT = nterms(P);
-    constexpr int K0 = MIXED ? 1 : 0;  // mixed: the constant term is added in FP64 below
-    constexpr int KBATCH = 16;         // coefficient loads in flight per lane
-    constexpr int CBATCH = 3;          // neighbour cells loaded together
     using Real = typename std::conditional<MIXED, float, double>::type;
+    constexpr S2Weights<P> W{};
+    constexpr InvSqrt IS{};
+    // 1/|d| between the 8 sites of a cell and the 8 sites of each of its 27
+    // neighbours, [nb][u][v], unit spacing
+    __shared__ Real sT[27 * 64];
+    for (int e = threadIdx.x; e < 27 * 64; e += blockDim.x) {
+        const int nb = e / 64, u = (e / 8) % 8, v = e % 8;
+        sT[e] = (Real)IS.v[s2_d2(u, nb, v)];
+    }
+    __syncthreads();
     const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= M) return;
     const int nc = g.nc;
     const int cx = (int)(cell / ((int64_t)nc * nc)), cy = (int)((cell / nc) % nc), cz = (int)(cell % nc);
-    const Real *Yt = MIXED ? (const Real *)Y2f : (const Real *)Y2;
-    const Real *Tt = MIXED ? (const Real *)T2f : (const Real *)T2;
     const Real *Ps = MIXED ? (const Real *)psi32 : (const Real *)psi;
     const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
-    Real far_[8], near_[8];
+    // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part
+    Real S[2][2][2] = {};
+    Real hn = Real(1);
+    const Real h = (Real)g.h;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) far_[u] = near_[u] = Real(0);
-    // L2P at the 8 sites: coefficient rows streamed KBATCH at a time
-#pragma unroll 1
-    for (int kb = K0; kb < NT; kb += KBATCH) {
-        Real v[KBATCH];
+    for (int n = 0; n <= P; ++n) {
+        Real part[2][2] = {};  // [B][C] within degree n
+        Real v[2 * P + 1];
 #pragma unroll
-        for (int t = 0; t < KBATCH; ++t)
-            if (kb + t < NT) v[t] = Ps[(int64_t)(kb + t) * M + cell];
+        for (int k = 0; k < 2 * n + 1; ++k) v[k] = (MIXED && n == 0) ? Real(0) : Ps[(int64_t)(n * n + k) * M + cell];
 #pragma unroll
-        for (int t = 0; t < KBATCH; ++t)
-            if (kb + t < NT)
-#pragma unroll
-                for (int u = 0; u < 8; ++u) far_[u] += Yt[u * NT + kb + t] * v[t];
-    }
-    // near field: the 27 neighbour cells' 8 sites each (wrapped, or absent in free space)
-#pragma unroll 1
-    for (int nb0 = 0; nb0 < 27; nb0 += CBATCH) {
-        Real qv[CBATCH][8];
-#pragma unroll
-        for (int b = 0; b < CBATCH; ++b) {
-            const int nb = nb0 + b;
-            int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
-            const bool ok = g.periodic || (ax >= 0 && ax < nc && ay >= 0 && ay < nc && az >= 0 && az < nc);
-            ax += ax < 0 ? nc : (ax >= nc ? -nc : 0);
-            ay += ay < 0 ? nc : (ay >= nc ? -nc : 0);
-            az += az < 0 ? nc : (az >= nc ? -nc : 0);
-            const int64_t base = cell_id(nc, ax, ay, az) * 8;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) qv[b][v] = ok ? Qs[base + v] : Real(0);
+        for (int k = 0; k < 2 * n + 1; ++k) {
+            const int m = (k + 1) / 2, C = (k > 0 && (k & 1) == 0) ? 1 : 0;
+            part[m & 1][C] += (Real)W.w[n * n + k] * v[k];
         }
 #pragma unroll
-        for (int b = 0; b < CBATCH; ++b)
+        for (int B = 0; B < 2; ++B)
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int C = 0; C < 2; ++C) S[(n + B) & 1][B][C] += hn * part[B][C];
+        hn *= h;
+        // keep the next degree's loads behind this point (bounded registers)
+        if (n % 2 == 1) asm volatile("" ::: "memory");
+    }
+    // near field: the 27 neighbour cells' 8 sites each (wrapped, or absent in
+    // free space); 1/|d| (unit spacing) from the LDS copy of the block table,
+    // the next cell's charges loaded while the current one is summed
+    Real near_[8] = {};
+    auto cell_base = [&](int nb, bool &ok) {
+        int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
+        ok = g.periodic || (ax >= 0 && ax < nc && ay >= 0 && ay < nc && az >= 0 && az < nc);
+        ax += ax < 0 ? nc : (ax >= nc ? -nc : 0);
+        ay += ay < 0 ? nc : (ay >= nc ? -nc : 0);
+        az += az < 0 ? nc : (az >= nc ? -nc : 0);
+        return cell_id(nc, ax, ay, az) * 8;
+    };
+    Real qn[8];
+    {
+        bool ok;
+        const int64_t b0 = cell_base(0, ok);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) near_[u] += Tt[u * 216 + (nb0 + b) * 8 + v] * qv[b][v];
+        for (int v = 0; v < 8; ++v) qn[v] = ok ? Qs[b0 + v] : Real(0);
+    }
+#pragma unroll 1
+    for (int nb = 0; nb < 27; ++nb) {
+        Real qv[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) qv[v] = qn[v];
+        if (nb + 1 < 27) {
+            bool ok;
+            const int64_t b1 = cell_base(nb + 1, ok);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) qn[v] = ok ? Qs[b1 + v] : Real(0);
+        }
+        const Real *tb = sT + nb * 64;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) near_[u] += tb[u * 8 + v] * qv[v];
     }
     const double l00 = MIXED ? psi[cell] : 0.0;
+    const double inv_h = 1.0 / g.h;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
+        const int fx = 1 - (u >> 2), fy = 1 - ((u >> 1) & 1), fz = 1 - (u & 1);
+        Real far_ = Real(0);
+#pragma unroll
+        for (int A = 0; A < 2; ++A)
+#pragma unroll
+            for (int B = 0; B < 2; ++B) {
+                const Real sz = (fz && A) ? Real(-1) : Real(1);
+                const Real sre = sz * ((fx && B) ? Real(-1) : Real(1));
+                const Real sim = sz * ((fx && !B) ? Real(-1) : Real(1)) * (fy ? Real(-1) : Real(1));
+                far_ += sre * S[A][B][0] + sim * S[A][B][1];
+            }
         const int i = 2 * cx + (u >> 2), j = 2 * cy + ((u >> 1) & 1), k = 2 * cz + (u & 1);
-        double phi = l00 + (double)far_[u] + (double)near_[u];
+        double phi = l00 + (double)far_ + (double)near_[u] * inv_h;
         if (g.periodic) phi += far_site<P>(g.n, i, j, k, Bz, Tax);
-        phisite[cell * 8 + u] = phi;
+        const int32_t rk = site_rank[cell * 8 + u];
+        if (rk >= 0) phi_r[rk] = phi;
+        phisite[cell * 8 + u] = rk >= 0 ? __builtin_nan("") : phi;
     }
 }
 
@@ -275,12 +392,12 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
         dim3 grid((unsigned)((c->M + 255) / 256));
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, true>, grid, dim3(256), g, c->M,
-                                           c->psi_lv[c->L], c->psi32, c->Y2, c->T2, c->Y2f, c->T2f, c->qsite,
-                                           c->qsite32, c->far.Bz, c->far.Tax, c->phisite));
+                                           c->psi_lv[c->L], c->psi32, c->qsite, c->qsite32, c->site_rank, c->far.Bz,
+                                           c->far.Tax, c->phisite, c->phi_r));
         } else {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, false>, grid, dim3(256), g, c->M,
-                                           c->psi_lv[c->L], c->psi32, c->Y2, c->T2, c->Y2f, c->T2f, c->qsite,
-                                           c->qsite32, c->far.Bz, c->far.Tax, c->phisite));
+                                           c->psi_lv[c->L], c->psi32, c->qsite, c->qsite32, c->site_rank, c->far.Bz,
+                                           c->far.Tax, c->phisite, c->phi_r));
         }
     } else {
         const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
@@ -288,86 +405,115 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, true>, grid, dim3(256), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->x, c->y, c->z,
-                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->phisite));
+                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->site_rank,
+                                           c->phisite, c->phi_r));
         } else {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, false>, grid, dim3(256), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->x, c->y, c->z,
-                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->phisite));
+                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->site_rank,
+                                           c->phisite, c->phi_r));
         }
     }
 }
 
 // ---- per-slot gather (lattice) ---------------------------------------------
-// One lane per slot t = i K + k.  i = t / K by a multiply-high with one
-// correction step (exact for every 32-bit t); the charge's lattice coordinates
-// come packed in one word; occupancy and potentials are read in site order
-// (cell-major on the 2x2x2 path), so a hop's two gathers share cache lines.
-__global__ __launch_bounds__(256) void k_slot_lattice(Geo g, uint32_t NK, uint32_t K, uint32_t kmul,
+// Charges are taken in rank order (site order), TCH per block; their packed
+// coordinates, charge, phi_occ and caller index are staged in LDS once, so a
+// slot needs a single gather: phi at the target site (NaN if occupied).  The
+// F table is stored by rank, so its reads are contiguous; dU and mask go to
+// the caller's [charge][hop] layout (K contiguous entries per charge).
+constexpr int TCH = 64;   // charges per block
+constexpr int SLOTB = 4;  // slots per lane whose loads are in flight together
+
+__global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, uint32_t K, uint32_t kmul,
                                                       const int32_t *__restrict__ offs,
                                                       const int32_t *__restrict__ order,
                                                       const int32_t *__restrict__ ijk_r, const double *__restrict__ q_r,
-                                                      const int32_t *__restrict__ site_charge,
+                                                      const double *__restrict__ phi_r,
                                                       const double *__restrict__ phisite,
                                                       const double *__restrict__ F, int s2,
                                                       double *__restrict__ dU, uint8_t *__restrict__ mask)
 {
     __shared__ int32_t soff[3 * kMaxHops];
+    __shared__ int32_t s_ijk[TCH], s_ord[TCH];
+    __shared__ double s_q[TCH], s_phi[TCH];
+    const int64_t r0 = (int64_t)blockIdx.x * TCH;
+    const int nloc = (int)((N - r0) < TCH ? (N - r0) : TCH);
     for (uint32_t e = threadIdx.x; e < 3 * K; e += blockDim.x) soff[e] = offs[e];
+    if ((int)threadIdx.x < nloc) {
+        const int64_t r = r0 + threadIdx.x;
+        s_ijk[threadIdx.x] = ijk_r[r];
+        s_ord[threadIdx.x] = order[r];
+        s_q[threadIdx.x] = q_r[r];
+        s_phi[threadIdx.x] = phi_r[r];
+    }
     __syncthreads();
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= NK) return;
-    uint32_t r = __umulhi(t, kmul);
-    uint32_t k = t - r * K;
-    if (k >= K) {
-        ++r;
-        k -= K;
-    }
+    const uint32_t total = (uint32_t)nloc * K;
     const int n = g.n, nc = g.nc;
-    const int32_t pk = ijk_r[r];
-    const int si = pk >> 20, sj = (pk >> 10) & 1023, sk = pk & 1023;
-    int ti = si + soff[3 * k], tj = sj + soff[3 * k + 1], tk = sk + soff[3 * k + 2];
-    bool valid = true;
-    if (g.periodic) {
-        ti += ti < 0 ? n : (ti >= n ? -n : 0);
-        tj += tj < 0 ? n : (tj >= n ? -n : 0);
-        tk += tk < 0 ? n : (tk >= n ? -n : 0);
-    } else {
-        valid = ti >= 0 && ti < n && tj >= 0 && tj < n && tk >= 0 && tk < n;
-    }
-    double out = __builtin_nan("");
-    if (valid) {
-        int64_t ps, pt;
-        if (s2) {
-            ps = (((int64_t)(si >> 1) * nc + (sj >> 1)) * nc + (sk >> 1)) * 8 + ((si & 1) * 4 + (sj & 1) * 2 + (sk & 1));
-            pt = (((int64_t)(ti >> 1) * nc + (tj >> 1)) * nc + (tk >> 1)) * 8 + ((ti & 1) * 4 + (tj & 1) * 2 + (tk & 1));
-        } else {
-            ps = ((int64_t)si * n + sj) * n + sk;
-            pt = ((int64_t)ti * n + tj) * n + tk;
-        }
-        valid = site_charge[pt] < 0;
-        if (valid) {
-            const double qi = q_r[r];
-            double corr;
+    const double nanv = __builtin_nan("");
+    for (uint32_t e0 = threadIdx.x; e0 < total; e0 += SLOTB * blockDim.x) {
+        double v[SLOTB], f[SLOTB];
+        uint32_t lc[SLOTB], kk[SLOTB];
+#pragma unroll
+        for (int b = 0; b < SLOTB; ++b) {
+            const uint32_t e = e0 + b * blockDim.x;
+            v[b] = nanv;
+            f[b] = 0.0;
+            lc[b] = 0;
+            kk[b] = 0;
+            if (e >= total) continue;
+            uint32_t c = __umulhi(e, kmul), k = e - c * K;
+            if (k >= K) {
+                ++c;
+                k -= K;
+            }
+            lc[b] = c;
+            kk[b] = k;
+            const int32_t pk = s_ijk[c];
+            int ti = (pk >> 20) + soff[3 * k], tj = ((pk >> 10) & 1023) + soff[3 * k + 1],
+                tk = (pk & 1023) + soff[3 * k + 2];
+            bool inside = true;
             if (g.periodic) {
-                corr = F[t];  // stored by rank
+                ti += ti < 0 ? n : (ti >= n ? -n : 0);
+                tj += tj < 0 ? n : (tj >= n ? -n : 0);
+                tk += tk < 0 ? n : (tk >= n ? -n : 0);
             } else {
+                inside = ti >= 0 && ti < n && tj >= 0 && tj < n && tk >= 0 && tk < n;
+            }
+            if (inside) {
+                const int64_t pt = s2 ? ((((int64_t)(ti >> 1) * nc + (tj >> 1)) * nc + (tk >> 1)) * 8 +
+                                         ((ti & 1) * 4 + (tj & 1) * 2 + (tk & 1)))
+                                      : (((int64_t)ti * n + tj) * n + tk);
+                v[b] = phisite[pt];
+            }
+            if (g.periodic) f[b] = F[r0 * K + e];
+        }
+#pragma unroll
+        for (int b = 0; b < SLOTB; ++b) {
+            const uint32_t e = e0 + b * blockDim.x;
+            if (e >= total) continue;
+            const uint32_t c = lc[b], k = kk[b];
+            const double qi = s_q[c];
+            double corr = f[b];
+            if (!g.periodic) {
                 const double ox = soff[3 * k], oy = soff[3 * k + 1], oz = soff[3 * k + 2];
                 corr = -1.0 / (g.h * sqrt(ox * ox + oy * oy + oz * oz));
             }
-            out = qi * (phisite[pt] - phisite[ps]) + qi * qi * corr;
+            const bool valid = !__builtin_isnan(v[b]);
+            const double out = valid ? qi * (v[b] - s_phi[c]) + qi * qi * corr : nanv;
+            const int64_t o = (int64_t)s_ord[c] * K + k;
+            dU[o] = out;
+            if (mask) mask[o] = valid ? 1 : 0;
         }
     }
-    const int64_t o = (int64_t)order[r] * K + k;
-    dU[o] = out;
-    if (mask) mask[o] = valid ? 1 : 0;
 }
 
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask)
 {
-    const uint32_t NK = (uint32_t)(c->N * K);
     const uint32_t kmul = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)K);
-    launch(c, "slot_lattice", k_slot_lattice, dim3((NK + 255) / 256), dim3(256), g, NK, (uint32_t)K, kmul,
-           c->d_offsets, c->order, c->ijk_r, c->q_r, c->site_charge, c->phisite, c->F, c->s2 ? 1 : 0, dU, mask);
+    launch(c, "slot_lattice", k_slot_lattice, dim3((unsigned)((c->N + TCH - 1) / TCH)), dim3(256), g, c->N,
+           (uint32_t)K, kmul, c->d_offsets, c->order, c->ijk_r, c->q_r, c->phi_r, c->phisite, c->F, c->s2 ? 1 : 0,
+           dU, mask);
 }
 
 // ---- far-field helpers (LDS-tiled matrix-vector products with R) ----------
