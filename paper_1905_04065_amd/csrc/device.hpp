@@ -45,6 +45,70 @@ __host__ __device__ inline int64_t s2_site(int nc, int i, int j, int k)
     return cell_id(nc, i >> 1, j >> 1, k >> 1) * 8 + ((i & 1) * 4 + (j & 1) * 2 + (k & 1));
 }
 
+// Reciprocals used by the regular recurrences at a runtime order, so that the
+// recurrences carry no divisions: 1/(2k) and 1/((n+m)(n-m)) for n > m.
+struct RecTables {
+    double half_inv[kMaxOrder + 1];
+    double rinv[kMaxOrder + 1][kMaxOrder + 1];
+    constexpr RecTables() : half_inv{}, rinv{}
+    {
+        for (int k = 1; k <= kMaxOrder; ++k) half_inv[k] = 0.5 / k;
+        for (int n = 1; n <= kMaxOrder; ++n)
+            for (int m = 0; m < n; ++m) rinv[n][m] = 1.0 / (double)((n + m) * (n - m));
+    }
+};
+
+// Column m (degrees n = m..p) of the regular harmonics at offset d, as L2P
+// weights Wt (Psi(d) = sum_k L_k Wt[k]) and, if Km is not null, as the
+// real-stored multipole of a unit charge at d (Km[k] = conj(R_k(d))).  Lanes
+// m = 0..p of a group together produce the full arrays: each runs the diagonal
+// recurrence to R_m^m itself (m steps) and then its column, so the dependent
+// chain is at most p steps long instead of the (p+1)^2 of a single lane.
+__device__ inline void harmonics_column(int p, int m, double x, double y, double z, double *Km, double *Wt)
+{
+    constexpr RecTables T{};
+    const double r2 = x * x + y * y + z * z;
+    double ar = 1.0, ai = 0.0;
+    for (int k = 1; k <= m; ++k) {
+        const double f = -T.half_inv[k];
+        const double nr = f * (x * ar - y * ai), ni = f * (x * ai + y * ar);
+        ar = nr;
+        ai = ni;
+    }
+    double br = 0.0, bi = 0.0;
+    for (int n = m; n <= p; ++n) {
+        double cr, ci;
+        if (n == m) {
+            cr = ar;
+            ci = ai;
+        } else if (n == m + 1) {
+            cr = z * ar;
+            ci = z * ai;
+            br = cr;
+            bi = ci;
+        } else {
+            const double w = T.rinv[n][m];
+            cr = ((2 * n - 1) * z * br - r2 * ar) * w;
+            ci = ((2 * n - 1) * z * bi - r2 * ai) * w;
+            ar = br;
+            ai = bi;
+            br = cr;
+            bi = ci;
+        }
+        if (m == 0) {
+            Wt[slot0(n)] = cr;
+            if (Km) Km[slot0(n)] = cr;
+        } else {
+            Wt[slot_re(n, m)] = 2.0 * cr;
+            Wt[slot_im(n, m)] = 2.0 * ci;
+            if (Km) {
+                Km[slot_re(n, m)] = cr;
+                Km[slot_im(n, m)] = -ci;
+            }
+        }
+    }
+}
+
 // Real-stored multipole of a unit charge at offset d (Km[k] = conj(R_k(d))) and
 // the L2P weights at d (Wt[k], Psi(d) = sum L_k Wt[k]), written with stride s.
 __device__ inline void unit_multipole_and_weights(int p, double x, double y, double z, double *Km, double *Wt,

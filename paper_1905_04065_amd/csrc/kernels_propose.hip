@@ -276,6 +276,16 @@ __host__ __device__ constexpr int s2_d2(int u, int nb, int v)
     return dx * dx + dy * dy + dz * dz;
 }
 
+// The two halves of the work have different shapes: the class sums stream
+// (p+1)^2 coefficients per cell from HBM, the near field walks 27 neighbour
+// cells through L2.  Fused in one lane they need the registers of both and run
+// at one wave per SIMD; here waves 0-1 of a block do the class sums of its 128
+// cells and waves 2-3 the near field and far-field sites of the same cells, so
+// a wave holds the registers of one half only and both kinds of load are in
+// flight on a CU at once.  Results meet in LDS and all waves write the block's
+// 1024 sites contiguously.
+constexpr int S2_CELLS = 128;  // cells per block
+
 template <int P, bool MIXED>
 __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const double *__restrict__ psi,
                                                      const float *__restrict__ psi32,
@@ -291,97 +301,145 @@ __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const dou
     // 1/|d| between the 8 sites of a cell and the 8 sites of each of its 27
     // neighbours, [nb][u][v], unit spacing
     __shared__ Real sT[27 * 64];
+    // per cell and site: local-expansion part, near + far-field part (row of 9: no bank conflicts)
+    __shared__ double sFar[S2_CELLS * 9], sNear[S2_CELLS * 9];
     for (int e = threadIdx.x; e < 27 * 64; e += blockDim.x) {
         const int nb = e / 64, u = (e / 8) % 8, v = e % 8;
         sT[e] = (Real)IS.v[s2_d2(u, nb, v)];
     }
     __syncthreads();
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= M) return;
+    const int wave = threadIdx.x >> 6;
+    const int lc = (wave & 1) * 64 + (threadIdx.x & 63);
+    const int64_t c0 = (int64_t)blockIdx.x * S2_CELLS, cell = c0 + lc;
     const int nc = g.nc;
-    const int cx = (int)(cell / ((int64_t)nc * nc)), cy = (int)((cell / nc) % nc), cz = (int)(cell % nc);
-    const Real *Ps = MIXED ? (const Real *)psi32 : (const Real *)psi;
-    const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
-    // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part
-    Real S[2][2][2] = {};
-    Real hn = Real(1);
-    const Real h = (Real)g.h;
+    if (wave < 2) {
+        if (cell < M) {
+            const Real *Ps = MIXED ? (const Real *)psi32 : (const Real *)psi;
+            // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part
+            Real S[2][2][2] = {};
+            Real hn = Real(1);
+            const Real h = (Real)g.h;
 #pragma unroll
-    for (int n = 0; n <= P; ++n) {
-        Real part[2][2] = {};  // [B][C] within degree n
-        Real v[2 * P + 1];
+            for (int n = 0; n <= P; ++n) {
+                Real part[2][2] = {};  // [B][C] within degree n
+                Real v[2 * P + 1];
 #pragma unroll
-        for (int k = 0; k < 2 * n + 1; ++k) v[k] = (MIXED && n == 0) ? Real(0) : Ps[(int64_t)(n * n + k) * M + cell];
+                for (int k = 0; k < 2 * n + 1; ++k)
+                    v[k] = (MIXED && n == 0) ? Real(0) : Ps[(int64_t)(n * n + k) * M + cell];
 #pragma unroll
-        for (int k = 0; k < 2 * n + 1; ++k) {
-            const int m = (k + 1) / 2, C = (k > 0 && (k & 1) == 0) ? 1 : 0;
-            part[m & 1][C] += (Real)W.w[n * n + k] * v[k];
-        }
+                for (int k = 0; k < 2 * n + 1; ++k) {
+                    const int m = (k + 1) / 2, C = (k > 0 && (k & 1) == 0) ? 1 : 0;
+                    part[m & 1][C] += (Real)W.w[n * n + k] * v[k];
+                }
 #pragma unroll
-        for (int B = 0; B < 2; ++B)
+                for (int B = 0; B < 2; ++B)
 #pragma unroll
-            for (int C = 0; C < 2; ++C) S[(n + B) & 1][B][C] += hn * part[B][C];
-        hn *= h;
-        // keep the next degree's loads behind this point (bounded registers)
-        if (n % 2 == 1) asm volatile("" ::: "memory");
-    }
-    // near field: the 27 neighbour cells' 8 sites each (wrapped, or absent in
-    // free space); 1/|d| (unit spacing) from the LDS copy of the block table,
-    // the next cell's charges loaded while the current one is summed
-    Real near_[8] = {};
-    auto cell_base = [&](int nb, bool &ok) {
-        int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
-        ok = g.periodic || (ax >= 0 && ax < nc && ay >= 0 && ay < nc && az >= 0 && az < nc);
-        ax += ax < 0 ? nc : (ax >= nc ? -nc : 0);
-        ay += ay < 0 ? nc : (ay >= nc ? -nc : 0);
-        az += az < 0 ? nc : (az >= nc ? -nc : 0);
-        return cell_id(nc, ax, ay, az) * 8;
-    };
-    Real qn[8];
-    {
-        bool ok;
-        const int64_t b0 = cell_base(0, ok);
-#pragma unroll
-        for (int v = 0; v < 8; ++v) qn[v] = ok ? Qs[b0 + v] : Real(0);
-    }
-#pragma unroll 1
-    for (int nb = 0; nb < 27; ++nb) {
-        Real qv[8];
-#pragma unroll
-        for (int v = 0; v < 8; ++v) qv[v] = qn[v];
-        if (nb + 1 < 27) {
-            bool ok;
-            const int64_t b1 = cell_base(nb + 1, ok);
-#pragma unroll
-            for (int v = 0; v < 8; ++v) qn[v] = ok ? Qs[b1 + v] : Real(0);
-        }
-        const Real *tb = sT + nb * 64;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int v = 0; v < 8; ++v) near_[u] += tb[u * 8 + v] * qv[v];
-    }
-    const double l00 = MIXED ? psi[cell] : 0.0;
-    const double inv_h = 1.0 / g.h;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int fx = 1 - (u >> 2), fy = 1 - ((u >> 1) & 1), fz = 1 - (u & 1);
-        Real far_ = Real(0);
-#pragma unroll
-        for (int A = 0; A < 2; ++A)
-#pragma unroll
-            for (int B = 0; B < 2; ++B) {
-                const Real sz = (fz && A) ? Real(-1) : Real(1);
-                const Real sre = sz * ((fx && B) ? Real(-1) : Real(1));
-                const Real sim = sz * ((fx && !B) ? Real(-1) : Real(1)) * (fy ? Real(-1) : Real(1));
-                far_ += sre * S[A][B][0] + sim * S[A][B][1];
+                    for (int C = 0; C < 2; ++C) S[(n + B) & 1][B][C] += hn * part[B][C];
+                hn *= h;
             }
-        const int i = 2 * cx + (u >> 2), j = 2 * cy + ((u >> 1) & 1), k = 2 * cz + (u & 1);
-        double phi = l00 + (double)far_ + (double)near_[u] * inv_h;
-        if (g.periodic) phi += far_site<P>(g.n, i, j, k, Bz, Tax);
-        const int32_t rk = site_rank[cell * 8 + u];
+            const double l00 = MIXED ? psi[cell] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int fx = 1 - (u >> 2), fy = 1 - ((u >> 1) & 1), fz = 1 - (u & 1);
+                Real far_ = Real(0);
+#pragma unroll
+                for (int A = 0; A < 2; ++A)
+#pragma unroll
+                    for (int B = 0; B < 2; ++B) {
+                        const Real sz = (fz && A) ? Real(-1) : Real(1);
+                        const Real sre = sz * ((fx && B) ? Real(-1) : Real(1));
+                        const Real sim = sz * ((fx && !B) ? Real(-1) : Real(1)) * (fy ? Real(-1) : Real(1));
+                        far_ += sre * S[A][B][0] + sim * S[A][B][1];
+                    }
+                sFar[lc * 9 + u] = l00 + (double)far_;
+            }
+        }
+    } else if (cell < M) {
+        const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
+        const int cx = (int)(cell / ((int64_t)nc * nc)), cy = (int)((cell / nc) % nc), cz = (int)(cell % nc);
+        // near field: the 27 neighbour cells' 8 sites each (wrapped, or absent in
+        // free space); the next cell's charges are loaded while the current one is summed
+        auto cell_base = [&](int nb, bool &ok) {
+            int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
+            ok = g.periodic || (ax >= 0 && ax < nc && ay >= 0 && ay < nc && az >= 0 && az < nc);
+            ax += ax < 0 ? nc : (ax >= nc ? -nc : 0);
+            ay += ay < 0 ? nc : (ay >= nc ? -nc : 0);
+            az += az < 0 ? nc : (az >= nc ? -nc : 0);
+            return cell_id(nc, ax, ay, az) * 8;
+        };
+        // a cell's 8 charges are contiguous and 64-byte aligned: vector loads
+        auto load8 = [&](int64_t base, bool ok, Real *o) {
+            if constexpr (MIXED) {
+                const float4 *q4 = (const float4 *)(Qs + base);
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 a0 = ok ? q4[0] : z4, a1 = ok ? q4[1] : z4;
+                o[0] = a0.x, o[1] = a0.y, o[2] = a0.z, o[3] = a0.w;
+                o[4] = a1.x, o[5] = a1.y, o[6] = a1.z, o[7] = a1.w;
+            } else {
+                const double2 *q2 = (const double2 *)(Qs + base);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double2 a = ok ? q2[t] : make_double2(0.0, 0.0);
+                    o[2 * t] = a.x;
+                    o[2 * t + 1] = a.y;
+                }
+            }
+        };
+        Real near_[8] = {};
+        Real qn[8];
+        {
+            bool ok;
+            const int64_t b0 = cell_base(0, ok);
+            load8(b0, ok, qn);
+        }
+#pragma unroll 1
+        for (int nb = 0; nb < 27; ++nb) {
+            Real qv[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) qv[v] = qn[v];
+            if (nb + 1 < 27) {
+                bool ok;
+                const int64_t b1 = cell_base(nb + 1, ok);
+                load8(b1, ok, qn);
+            }
+            const Real *tb = sT + nb * 64;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int v = 0; v < 8; ++v) near_[u] += tb[u * 8 + v] * qv[v];
+        }
+        // far field of V_inf at the 8 sites: the 4 (i, j) rows of Bz against the two Tax rows 2cz, 2cz+1
+        double fs[8] = {};
+        if (g.periodic) {
+            const int n = g.n;
+            const double *t0 = Tax + (int64_t)(2 * cz) * (P + 1);
+#pragma unroll
+            for (int ij = 0; ij < 4; ++ij) {
+                const int i = 2 * cx + (ij >> 1), j = 2 * cy + (ij & 1);
+                const double *bz = Bz + ((int64_t)i * n + j) * (P + 1);
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int cc = 0; cc <= P; ++cc) {
+                    const double bb = bz[cc];
+                    a0 += bb * t0[cc];
+                    a1 += bb * t0[P + 1 + cc];
+                }
+                fs[2 * ij] = a0;
+                fs[2 * ij + 1] = a1;
+            }
+        }
+        const double inv_h = 1.0 / g.h;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sNear[lc * 9 + u] = (double)near_[u] * inv_h + fs[u];
+    }
+    __syncthreads();
+    const int nsite = (int)((M - c0 < S2_CELLS ? M - c0 : S2_CELLS) * 8);
+    for (int e = threadIdx.x; e < nsite; e += blockDim.x) {
+        const int l = e >> 3, u = e & 7;
+        const double phi = sFar[l * 9 + u] + sNear[l * 9 + u];
+        const int32_t rk = site_rank[c0 * 8 + e];
         if (rk >= 0) phi_r[rk] = phi;
-        phisite[cell * 8 + u] = rk >= 0 ? __builtin_nan("") : phi;
+        phisite[c0 * 8 + e] = rk >= 0 ? __builtin_nan("") : phi;
     }
 }
 
@@ -389,7 +447,7 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
 {
     const bool mixed = c->prec == FMMKMC_MIXED;
     if (c->s2) {
-        dim3 grid((unsigned)((c->M + 255) / 256));
+        dim3 grid((unsigned)((c->M + S2_CELLS - 1) / S2_CELLS));
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, true>, grid, dim3(256), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->qsite, c->qsite32, c->site_rank, c->far.Bz,
@@ -619,6 +677,7 @@ __global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, cons
     const int nt = nterms(p);
     extern __shared__ double sm[];
     double *Wt = sm, *K1 = sm + (int64_t)K * nt, *w = K1 + nt, *Wr = w + nt, *red = Wr + nt;  // red: 256
+    double *selfv = red + 256;                                                              // 27 K
     const int n = g.n;
     const int64_t i = order[rank];
     const int s = site[i];
@@ -626,12 +685,28 @@ __global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, cons
     const double c = 0.5 * g.a;
     const double rx = (si + 0.5) * g.h, ry = (sj + 0.5) * g.h, rz = (sk + 0.5) * g.h;
     const int tid = threadIdx.x;
-    if (tid < K) {
-        const int ti = posmod(si + offs[3 * tid], n), tj = posmod(sj + offs[3 * tid + 1], n),
-                  tk = posmod(sk + offs[3 * tid + 2], n);
-        l2p_weights(p, (ti + 0.5) * g.h - c, (tj + 0.5) * g.h - c, (tk + 0.5) * g.h - c, Wt + (int64_t)tid * nt);
+    // weights of every hop target and the unit multipole of the charge's site,
+    // one lane per (point, column m); then 1/|t - r - a nu| per (hop, copy nu)
+    const int ncol = p + 1;
+    for (int task = tid; task < (K + 1) * ncol; task += blockDim.x) {
+        const int pt = task / ncol, m = task - pt * ncol;
+        if (pt < K) {
+            const int ti = posmod(si + offs[3 * pt], n), tj = posmod(sj + offs[3 * pt + 1], n),
+                      tk = posmod(sk + offs[3 * pt + 2], n);
+            harmonics_column(p, m, (ti + 0.5) * g.h - c, (tj + 0.5) * g.h - c, (tk + 0.5) * g.h - c, nullptr,
+                             Wt + (int64_t)pt * nt);
+        } else {
+            harmonics_column(p, m, rx - c, ry - c, rz - c, K1, Wr);
+        }
     }
-    if (tid == K) unit_multipole_and_weights(p, rx - c, ry - c, rz - c, K1, Wr);
+    for (int task = tid; task < 27 * K; task += blockDim.x) {
+        const int hk = task / 27, nu = task - hk * 27;
+        const int ti = posmod(si + offs[3 * hk], n), tj = posmod(sj + offs[3 * hk + 1], n),
+                  tk = posmod(sk + offs[3 * hk + 2], n);
+        const double d0 = (ti + 0.5) * g.h - rx - g.a * (nu / 9 - 1), d1 = (tj + 0.5) * g.h - ry - g.a * ((nu / 3) % 3 - 1),
+                     d2 = (tk + 0.5) * g.h - rz - g.a * (nu % 3 - 1);
+        selfv[task] = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
     __syncthreads();
     // w = R K1: rows split over 16 lanes
     for (int r0 = 0; r0 < nt; r0 += 16) {
@@ -661,14 +736,8 @@ __global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, cons
         for (int t = 0; t < per; ++t) B += red[tid * per + t];
         const int ti = posmod(si + offs[3 * tid], n), tj = posmod(sj + offs[3 * tid + 1], n),
                   tk = posmod(sk + offs[3 * tid + 2], n);
-        const double tx = (ti + 0.5) * g.h, ty = (tj + 0.5) * g.h, tz = (tk + 0.5) * g.h;
         double self = 0.0;
-        for (int a0 = -1; a0 <= 1; ++a0)
-            for (int a1 = -1; a1 <= 1; ++a1)
-                for (int a2 = -1; a2 <= 1; ++a2) {
-                    const double d0 = tx - rx - g.a * a0, d1 = ty - ry - g.a * a1, d2 = tz - rz - g.a * a2;
-                    self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-                }
+        for (int nu = 0; nu < 27; ++nu) self += selfv[tid * 27 + nu];
         const double cbox = (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
         const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
         F[rank * K + tid] = -self + cbox + 0.5 * (sigma[ts] + sigma[s]) - B;
@@ -685,7 +754,7 @@ void launch_sigma(fmmkmc_ctx *c, const Geo &g)
 
 void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, int K, int64_t first)
 {
-    const size_t shm1 = sizeof(double) * ((size_t)(K + 3) * c->nt + 256);
+    const size_t shm1 = sizeof(double) * ((size_t)(K + 3) * c->nt + 256 + 27 * (size_t)K);
     if (count == 1 && K <= 64 && shm1 <= 64 * 1024) {
         launch_shm(c, "f_row1", k_f_row1, dim3(1), dim3(256), shm1, g, c->p, first, c->order, K, c->d_offsets,
                    c->site, c->far.R, c->far.sigma, c->F);
@@ -727,12 +796,20 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
     const int rcx = fine_coord(rx, g.w, g.nc), rcy = fine_coord(ry, g.w, g.nc), rcz = fine_coord(rz, g.w, g.nc);
     const int64_t tcell = cell_id(g.nc, tcx, tcy, tcz), rcell = cell_id(g.nc, rcx, rcy, rcz);
     const double c = 0.5 * g.a;
-    if (threadIdx.x == 0)
-        l2p_weights(p, tx - (tcx + 0.5) * g.w, ty - (tcy + 0.5) * g.w, tz - (tcz + 0.5) * g.w, Wt);
-    if (threadIdx.x == 1)
-        l2p_weights(p, rx - (rcx + 0.5) * g.w, ry - (rcy + 0.5) * g.w, rz - (rcz + 0.5) * g.w, Wr);
-    if (g.periodic && threadIdx.x == 2) unit_multipole_and_weights(p, tx - c, ty - c, tz - c, Kt, Ft);
-    if (g.periodic && threadIdx.x == 3) unit_multipole_and_weights(p, rx - c, ry - c, rz - c, Kr, Fr);
+    // the four weight arrays on four waves, one lane per column m
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    if (ln <= p) {
+        if (wv == 0)
+            harmonics_column(p, ln, tx - (tcx + 0.5) * g.w, ty - (tcy + 0.5) * g.w, tz - (tcz + 0.5) * g.w, nullptr,
+                             Wt);
+        else if (wv == 1)
+            harmonics_column(p, ln, rx - (rcx + 0.5) * g.w, ry - (rcy + 0.5) * g.w, rz - (rcz + 0.5) * g.w, nullptr,
+                             Wr);
+        else if (wv == 2 && g.periodic)
+            harmonics_column(p, ln, tx - c, ty - c, tz - c, Kt, Ft);
+        else if (wv == 3 && g.periodic)
+            harmonics_column(p, ln, rx - c, ry - c, rz - c, Kr, Fr);
+    }
     __syncthreads();
     double part = 0.0;
     for (int k = threadIdx.x; k < nt; k += blockDim.x)
@@ -776,20 +853,18 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
             part += 0.5 * qi * Ft[k] * R[e] * Kt[m];
         }
     }
-    if (threadIdx.x == 0) {
-        if (g.periodic) {
-            double self = 0.0;
-            for (int a0 = -1; a0 <= 1; ++a0)
-                for (int a1 = -1; a1 <= 1; ++a1)
-                    for (int a2 = -1; a2 <= 1; ++a2) {
-                        const double d0 = tx - rx - g.a * a0, d1 = ty - ry - g.a * a1, d2 = tz - rz - g.a * a2;
-                        self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-                    }
-            part += -qi * qi * self + qi * qi * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
-        } else {
-            const double d0 = tx - rx, d1 = ty - ry, d2 = tz - rz;
+    // self terms: one copy nu of the old position per lane
+    if (g.periodic) {
+        if (threadIdx.x < 27) {
+            const int nu = threadIdx.x;
+            const double d0 = tx - rx - g.a * (nu / 9 - 1), d1 = ty - ry - g.a * ((nu / 3) % 3 - 1),
+                         d2 = tz - rz - g.a * (nu % 3 - 1);
             part -= qi * qi / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         }
+        if (threadIdx.x == 0) part += qi * qi * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
+    } else if (threadIdx.x == 0) {
+        const double d0 = tx - rx, d1 = ty - ry, d2 = tz - rz;
+        part -= qi * qi / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
     }
     const double tot = block_sum(part, red);
     if (threadIdx.x == 0) out[0] = tot;
@@ -858,10 +933,15 @@ __global__ __launch_bounds__(256) void k_generic_far(Geo g, int p, int64_t S, co
     const int64_t s0 = (int64_t)blockIdx.x * SBF;
     const double c = 0.5 * g.a;
     const int b = threadIdx.x;
-    if (b < SBF && s0 + b < S) {
-        const int64_t s = s0 + b, i = charge[s];
-        unit_multipole_and_weights(p, tw[3 * s] - c, tw[3 * s + 1] - c, tw[3 * s + 2] - c, Kt + b * nt, Wt + b * nt);
-        unit_multipole_and_weights(p, x[i] - c, y[i] - c, z[i] - c, Kr + b * nt, Wr + b * nt);
+    // one lane per (proposal, endpoint, column m)
+    for (int task = threadIdx.x; task < SBF * 2 * (p + 1); task += blockDim.x) {
+        const int bb = task / (2 * (p + 1)), e = (task / (p + 1)) & 1, m = task % (p + 1);
+        if (s0 + bb >= S) continue;
+        const int64_t s = s0 + bb, i = charge[s];
+        if (e == 0)
+            harmonics_column(p, m, tw[3 * s] - c, tw[3 * s + 1] - c, tw[3 * s + 2] - c, Kt + bb * nt, Wt + bb * nt);
+        else
+            harmonics_column(p, m, x[i] - c, y[i] - c, z[i] - c, Kr + bb * nt, Wr + bb * nt);
     }
     __syncthreads();
     // Kt <- dK = q (K1(t) - K1(r)), Wt <- W(t) - W(r)
