@@ -150,6 +150,11 @@ void release(fmmkmc_ctx *c)
     dfree(c->red);
     dfree(c->iota);
     dfree(c->acc_buf);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
+    c->ev_fork = c->ev_join = nullptr;
+    c->aux = nullptr;
     for (auto &pd : c->prof.pending) {
         (void)hipEventDestroy(pd.a);
         (void)hipEventDestroy(pd.b);
@@ -322,6 +327,9 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
         if (c->lat_n > kMaxLattice) return fail(c, FMMKMC_EINVAL, "lattice_n must be <= 1024");
     }
     HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     // host copies; periodic positions wrapped into the box
     c->hx.resize(n);
     c->hy.resize(n);
@@ -787,10 +795,22 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
     API_GUARD(c, {
         HIPCHK(hipSetDevice(c->device));
         const Geo g = make_geo(c);
-        // C1: dU of the move (footnote to Sec. 3.1), read back after the commit
-        // kernels are queued behind it (one synchronisation per accept)
+        // C1: dU of the move (footnote to Sec. 3.1) as partial sums, read back
+        // after the commit kernels are queued behind it (one synchronisation per accept)
         double *dUd = c->acc_buf;
         launch_move_dU(c, g, i, np, dUd);
+        // the moved charge's row of the lattice proposal table depends only on
+        // its new site: computed on the side stream while the sweep runs, after
+        // every earlier proposal (which reads the table) has finished
+        const bool need_row = c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty();
+        const int Krow = (int)c->F_offsets.size() / 3;
+        bool row_launched = false;
+        if (need_row) {
+            HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+            HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+            row_launched = launch_f_row1(c, g, Krow, c->hrank[i], new_site, c->aux);
+            if (row_launched) HIPCHK(hipEventRecord(c->ev_join, c->aux));
+        }
         // C2 + C3
         CommitArgs a;
         a.i = i;
@@ -847,12 +867,17 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
             c->hsite_charge[new_site] = (int32_t)i;
             c->hsite[i] = (int32_t)new_site;
         }
-        // lattice proposal table row of the moved charge
-        if (c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty())
-            launch_f_rows(c, g, 1, (int)c->F_offsets.size() / 3, c->hrank[i]);
-        double dUh = 0;
-        HIPCHK(hipMemcpyAsync(&dUh, dUd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (need_row) {
+            if (row_launched)
+                HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+            else
+                launch_f_rows(c, g, 1, Krow, c->hrank[i]);  // reads the updated site table
+        }
+        double parts[kMoveParts];
+        HIPCHK(hipMemcpyAsync(parts, dUd, sizeof(parts), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        double dUh = 0;
+        for (int k = 0; k < kMoveParts; ++k) dUh += parts[k];
         if (dU_out) *dU_out = dUh;
         c->U += dUh;
         return FMMKMC_OK;

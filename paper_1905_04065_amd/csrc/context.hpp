@@ -61,6 +61,8 @@ struct fmmkmc_ctx {
     double a = 0, h = 0;
     int bc = 0, L = 0, p = 0, nt = 0, prec = 0, lat_n = 0, cap = 0, device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;        // library-owned side stream (accept: F row beside the sweep)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t N = 0;
     int nc = 0;
     int64_t M = 0;        // fine cells

@@ -10,22 +10,30 @@
 
 namespace fmmkmc {
 
-// Launch on the context's stream; with profiling on, bracket with HIP events.
+// Launch on stream s; with profiling on, bracket with HIP events on that stream.
 template <typename Kern, typename... Args>
-inline void launch_shm(fmmkmc_ctx *c, const char *name, Kern k, dim3 grid, dim3 block, size_t shm, Args... args)
+inline void launch_on(fmmkmc_ctx *c, hipStream_t s, const char *name, Kern k, dim3 grid, dim3 block, size_t shm,
+                      Args... args)
 {
     if (grid.x == 0 || grid.y == 0 || grid.z == 0) return;
     hipEvent_t a = nullptr, b = nullptr;
     if (c->prof.on) {
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
-        (void)hipEventRecord(a, c->stream);
+        (void)hipEventRecord(a, s);
     }
-    hipLaunchKernelGGL(k, grid, block, shm, c->stream, args...);
+    hipLaunchKernelGGL(k, grid, block, shm, s, args...);
     if (c->prof.on) {
-        (void)hipEventRecord(b, c->stream);
+        (void)hipEventRecord(b, s);
         c->prof.pending.push_back({name, a, b});
     }
+}
+
+// Launch on the context's stream.
+template <typename Kern, typename... Args>
+inline void launch_shm(fmmkmc_ctx *c, const char *name, Kern k, dim3 grid, dim3 block, size_t shm, Args... args)
+{
+    launch_on(c, c->stream, name, k, grid, block, shm, args...);
 }
 
 template <typename Kern, typename... Args>
@@ -70,7 +78,12 @@ void launch_expand_groups(fmmkmc_ctx *c, int64_t G, const int64_t *idx, const in
 void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int ntypes, const int32_t *T,
                         const uint8_t *Mk, int32_t *use);
 // accept
+// dU of a move as kMoveParts partial sums out[0..kMoveParts-1] (added by the caller in index order)
+constexpr int kMoveParts = 4;
 void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out);
+// F row of one charge (rank, lattice site s) on stream st; false (nothing
+// launched) when its tables exceed the kernel's LDS, then use launch_f_rows
+bool launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t s, hipStream_t st);
 void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a);
 
 }  // namespace fmmkmc

@@ -669,18 +669,16 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
 
 // F row of one charge (after an accept): K target harmonics in LDS, w = R K1(r)
 // with each output split over 16 lanes, then one dot product per hop.
-__global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, const int32_t *__restrict__ order, int K,
-                                                const int32_t *__restrict__ offs, const int32_t *__restrict__ site,
-                                                const double *__restrict__ R, const double *__restrict__ sigma,
-                                                double *__restrict__ F)
+__global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, int64_t s_site, int K,
+                                                const int32_t *__restrict__ offs, const double *__restrict__ R,
+                                                const double *__restrict__ sigma, double *__restrict__ F)
 {
     const int nt = nterms(p);
     extern __shared__ double sm[];
     double *Wt = sm, *K1 = sm + (int64_t)K * nt, *w = K1 + nt, *Wr = w + nt, *red = Wr + nt;  // red: 256
     double *selfv = red + 256;                                                              // 27 K
     const int n = g.n;
-    const int64_t i = order[rank];
-    const int s = site[i];
+    const int s = (int)s_site;
     const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
     const double c = 0.5 * g.a;
     const double rx = (si + 0.5) * g.h, ry = (sj + 0.5) * g.h, rz = (sk + 0.5) * g.h;
@@ -752,14 +750,17 @@ void launch_sigma(fmmkmc_ctx *c, const Geo &g)
                c->far.R, c->far.sigma);
 }
 
-void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, int K, int64_t first)
+bool launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t site, hipStream_t st)
 {
     const size_t shm1 = sizeof(double) * ((size_t)(K + 3) * c->nt + 256 + 27 * (size_t)K);
-    if (count == 1 && K <= 64 && shm1 <= 64 * 1024) {
-        launch_shm(c, "f_row1", k_f_row1, dim3(1), dim3(256), shm1, g, c->p, first, c->order, K, c->d_offsets,
-                   c->site, c->far.R, c->far.sigma, c->F);
-        return;
-    }
+    if (shm1 > 64 * 1024) return false;
+    launch_on(c, st, "f_row1", k_f_row1, dim3(1), dim3(256), shm1, g, c->p, rank, site, K, c->d_offsets, c->far.R,
+              c->far.sigma, c->F);
+    return true;
+}
+
+void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, int K, int64_t first)
+{
     const size_t shm = sizeof(double) * 2 * SB * c->nt;
     launch_shm(c, "f_rows", k_f_rows, dim3((unsigned)((count + SB - 1) / SB)), dim3(256), shm, g, c->p, count,
                c->order, first, K, c->d_offsets, c->site, c->far.R, c->far.sigma, c->F);
@@ -779,7 +780,12 @@ __device__ inline double block_sum(double v, double *red)
 }
 
 // Same terms as a proposal (header of this file), recomputed for the accepted
-// move (footnote to Sec. 3.1), always from the FP64 local expansions.
+// move (footnote to Sec. 3.1), always from the FP64 local expansions.  Four
+// blocks work on independent parts and each writes one partial sum:
+//   0: q (Psi(t) - Psi(r)) from the fine-level local expansions, and the self terms
+//   1: q times the near field at t,  2: minus q times the near field at r
+//      (the moving charge itself left out)
+//   3: the far-field change q dW.H + 1/2 q dW^T R dK (periodic; else 0)
 __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_t i, double tx, double ty, double tz,
                                                  const double *__restrict__ psi, const double *__restrict__ x,
                                                  const double *__restrict__ y, const double *__restrict__ z,
@@ -789,92 +795,131 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
 {
     const int nt = nterms(p);
     extern __shared__ double sm[];
-    double *Wt = sm, *Wr = sm + nt, *Kt = sm + 2 * nt, *Kr = sm + 3 * nt, *Ft = sm + 4 * nt, *Fr = sm + 5 * nt;
-    double *red = sm + 6 * nt;
+    double *red = sm;  // 256
+    double *Wa = sm + 256, *Wb = Wa + nt, *Ka = Wb + nt, *Kb = Ka + nt;
+    __shared__ int32_t s_cnt[27];
+    __shared__ int64_t s_cell[27];
+    __shared__ double s_shift[27][3];
     const double rx = x[i], ry = y[i], rz = z[i], qi = q[i];
     const int tcx = fine_coord(tx, g.w, g.nc), tcy = fine_coord(ty, g.w, g.nc), tcz = fine_coord(tz, g.w, g.nc);
     const int rcx = fine_coord(rx, g.w, g.nc), rcy = fine_coord(ry, g.w, g.nc), rcz = fine_coord(rz, g.w, g.nc);
-    const int64_t tcell = cell_id(g.nc, tcx, tcy, tcz), rcell = cell_id(g.nc, rcx, rcy, rcz);
-    const double c = 0.5 * g.a;
-    // the four weight arrays on four waves, one lane per column m
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    if (ln <= p) {
-        if (wv == 0)
-            harmonics_column(p, ln, tx - (tcx + 0.5) * g.w, ty - (tcy + 0.5) * g.w, tz - (tcz + 0.5) * g.w, nullptr,
-                             Wt);
-        else if (wv == 1)
-            harmonics_column(p, ln, rx - (rcx + 0.5) * g.w, ry - (rcy + 0.5) * g.w, rz - (rcz + 0.5) * g.w, nullptr,
-                             Wr);
-        else if (wv == 2 && g.periodic)
-            harmonics_column(p, ln, tx - c, ty - c, tz - c, Kt, Ft);
-        else if (wv == 3 && g.periodic)
-            harmonics_column(p, ln, rx - c, ry - c, rz - c, Kr, Fr);
-    }
-    __syncthreads();
+    const int part_id = blockIdx.x;
     double part = 0.0;
-    for (int k = threadIdx.x; k < nt; k += blockDim.x)
-        part += qi * (psi[(int64_t)k * M + tcell] * Wt[k] - psi[(int64_t)k * M + rcell] * Wr[k]);
-    // near fields of the two points
-    const int items = 2 * 27 * g.cap;
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
-        const int e = it / (27 * g.cap), rem = it % (27 * g.cap), nb = rem / g.cap, sl = rem % g.cap;
-        const int bx = e ? rcx : tcx, by = e ? rcy : tcy, bz = e ? rcz : tcz;
-        int ax = bx + nb / 9 - 1, ay = by + (nb / 3) % 3 - 1, az = bz + nb % 3 - 1;
-        double shx = 0, shy = 0, shz = 0;
-        if (ax < 0 || ax >= g.nc || ay < 0 || ay >= g.nc || az < 0 || az >= g.nc) {
-            if (!g.periodic) continue;
-            shx = g.a * floordiv(ax, g.nc);
-            shy = g.a * floordiv(ay, g.nc);
-            shz = g.a * floordiv(az, g.nc);
-            ax = posmod(ax, g.nc);
-            ay = posmod(ay, g.nc);
-            az = posmod(az, g.nc);
-        }
-        const int64_t nbc = cell_id(g.nc, ax, ay, az);
-        if (sl >= cnt[nbc]) continue;
-        const int j = slots[nbc * g.cap + sl];
-        if (e == 1 && j == i && shx == 0 && shy == 0 && shz == 0) continue;
-        const double px = e ? rx : tx, py = e ? ry : ty, pz = e ? rz : tz;
-        const double d0 = px - (x[j] + shx), d1 = py - (y[j] + shy), d2 = pz - (z[j] + shz);
-        const double v = qi * q[j] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        part += e ? -v : v;
-    }
-    if (g.periodic) {
-        // q dW.H + 1/2 q dW^T R dK with dK = q (K1(t) - K1(r)), dW = W(t) - W(r):
-        // the bilinear form is summed over all (k, n) pairs in parallel
-        for (int k = threadIdx.x; k < nt; k += blockDim.x) {
-            Kt[k] = qi * (Kt[k] - Kr[k]);
-            Ft[k] = Ft[k] - Fr[k];
+    if (part_id == 0) {
+        // harmonics at t and r relative to their fine cells, one lane per column m
+        if (ln <= p) {
+            if (wv == 0)
+                harmonics_column(p, ln, tx - (tcx + 0.5) * g.w, ty - (tcy + 0.5) * g.w, tz - (tcz + 0.5) * g.w,
+                                 nullptr, Wa);
+            else if (wv == 1)
+                harmonics_column(p, ln, rx - (rcx + 0.5) * g.w, ry - (rcy + 0.5) * g.w, rz - (rcz + 0.5) * g.w,
+                                 nullptr, Wb);
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < nt; k += blockDim.x) part += qi * Ft[k] * H[k];
-        for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
-            const int m = e / nt, k = e - m * nt;
-            part += 0.5 * qi * Ft[k] * R[e] * Kt[m];
-        }
-    }
-    // self terms: one copy nu of the old position per lane
-    if (g.periodic) {
-        if (threadIdx.x < 27) {
-            const int nu = threadIdx.x;
-            const double d0 = tx - rx - g.a * (nu / 9 - 1), d1 = ty - ry - g.a * ((nu / 3) % 3 - 1),
-                         d2 = tz - rz - g.a * (nu % 3 - 1);
+        const int64_t tcell = cell_id(g.nc, tcx, tcy, tcz), rcell = cell_id(g.nc, rcx, rcy, rcz);
+        for (int k = threadIdx.x; k < nt; k += blockDim.x)
+            part += qi * (psi[(int64_t)k * M + tcell] * Wa[k] - psi[(int64_t)k * M + rcell] * Wb[k]);
+        // self terms: one copy nu of the old position per lane
+        if (g.periodic) {
+            if (threadIdx.x < 27) {
+                const int nu = threadIdx.x;
+                const double d0 = tx - rx - g.a * (nu / 9 - 1), d1 = ty - ry - g.a * ((nu / 3) % 3 - 1),
+                             d2 = tz - rz - g.a * (nu % 3 - 1);
+                part -= qi * qi / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            }
+            if (threadIdx.x == 0) part += qi * qi * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
+        } else if (threadIdx.x == 0) {
+            const double d0 = tx - rx, d1 = ty - ry, d2 = tz - rz;
             part -= qi * qi / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         }
-        if (threadIdx.x == 0) part += qi * qi * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
-    } else if (threadIdx.x == 0) {
-        const double d0 = tx - rx, d1 = ty - ry, d2 = tz - rz;
-        part -= qi * qi / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    } else if (part_id <= 2) {
+        // near field of one endpoint: the neighbour cells' counts first, then one lane per (cell, slot)
+        const int e = part_id - 1;  // 0: target, 1: old position
+        const int bx = e ? rcx : tcx, by = e ? rcy : tcy, bz = e ? rcz : tcz;
+        if (threadIdx.x < 27) {
+            const int nb = threadIdx.x;
+            int ax = bx + nb / 9 - 1, ay = by + (nb / 3) % 3 - 1, az = bz + nb % 3 - 1;
+            double shx = 0, shy = 0, shz = 0;
+            bool ok = true;
+            if (ax < 0 || ax >= g.nc || ay < 0 || ay >= g.nc || az < 0 || az >= g.nc) {
+                ok = g.periodic != 0;
+                shx = g.a * floordiv(ax, g.nc);
+                shy = g.a * floordiv(ay, g.nc);
+                shz = g.a * floordiv(az, g.nc);
+                ax = posmod(ax, g.nc);
+                ay = posmod(ay, g.nc);
+                az = posmod(az, g.nc);
+            }
+            const int64_t nbc = cell_id(g.nc, ax, ay, az);
+            s_cell[nb] = nbc;
+            s_cnt[nb] = ok ? cnt[nbc] : 0;
+            s_shift[nb][0] = shx;
+            s_shift[nb][1] = shy;
+            s_shift[nb][2] = shz;
+        }
+        __syncthreads();
+        const double px = e ? rx : tx, py = e ? ry : ty, pz = e ? rz : tz;
+        for (int it = threadIdx.x; it < 27 * g.cap; it += blockDim.x) {
+            const int nb = it / g.cap, sl = it - nb * g.cap;
+            if (sl >= s_cnt[nb]) continue;
+            const int j = slots[s_cell[nb] * g.cap + sl];
+            const double shx = s_shift[nb][0], shy = s_shift[nb][1], shz = s_shift[nb][2];
+            if (e == 1 && j == i && shx == 0 && shy == 0 && shz == 0) continue;
+            const double d0 = px - (x[j] + shx), d1 = py - (y[j] + shy), d2 = pz - (z[j] + shz);
+            const double v = qi * q[j] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            part += e ? -v : v;
+        }
+    } else if (g.periodic) {
+        // q dW.H + 1/2 q dW^T R dK with dK = q (K1(t) - K1(r)), dW = W(t) - W(r),
+        // harmonics about the box centre; the bilinear form over all (m, k) pairs
+        const double c = 0.5 * g.a;
+        double *Wt = Wa, *Wr = Wb, *Kt = Ka, *Kr = Kb;
+        if (ln <= p) {
+            if (wv == 0)
+                harmonics_column(p, ln, tx - c, ty - c, tz - c, Kt, Wt);
+            else if (wv == 1)
+                harmonics_column(p, ln, rx - c, ry - c, rz - c, Kr, Wr);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+            Kt[k] = qi * (Kt[k] - Kr[k]);
+            Wt[k] = Wt[k] - Wr[k];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nt; k += blockDim.x) part += qi * Wt[k] * H[k];
+        // eight independent loads of R in flight per lane
+        const int nn = nt * nt;
+        double acc8[8] = {};
+        int e = threadIdx.x;
+        for (; e + 7 * 256 < nn; e += 8 * 256) {
+            double r8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) r8[u] = R[e + u * 256];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int ee = e + u * 256, m = ee / nt, k = ee - m * nt;
+                acc8[u] += Wt[k] * r8[u] * Kt[m];
+            }
+        }
+        for (; e < nn; e += 256) {
+            const int m = e / nt, k = e - m * nt;
+            acc8[0] += Wt[k] * R[e] * Kt[m];
+        }
+        double bil = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bil += acc8[u];
+        part += 0.5 * qi * bil;
     }
     const double tot = block_sum(part, red);
-    if (threadIdx.x == 0) out[0] = tot;
+    if (threadIdx.x == 0) out[part_id] = tot;
 }
 
 void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out)
 {
-    const size_t shm = sizeof(double) * (6 * c->nt + 256);
-    launch_shm(c, "move_dU", k_move_dU, dim3(1), dim3(256), shm, g, c->p, c->M, i, t[0], t[1], t[2], c->psi_lv[c->L],
-               c->x, c->y, c->z, c->q, c->cell_cnt, c->cell_slots, c->far.R, c->far.H, out);
+    const size_t shm = sizeof(double) * (4 * c->nt + 256);
+    launch_shm(c, "move_dU", k_move_dU, dim3(kMoveParts), dim3(256), shm, g, c->p, c->M, i, t[0], t[1], t[2],
+               c->psi_lv[c->L], c->x, c->y, c->z, c->q, c->cell_cnt, c->cell_slots, c->far.R, c->far.H, out);
 }
 
 // ---- generic proposals ----------------------------------------------------
