@@ -4,9 +4,9 @@
 // old position (free space: nu = 0 only; periodic: the 27 copies in V_box) whose
 // cell is not one of the 27 cells around beta, and +P2L(q at r' + a nu)
 // likewise.  P2L of a point charge is the multipole-to-local translation of a
-// monopole, L_n^m = q I_n^m(y - c_beta).  One lane per (cell, order m): the lane
-// runs the irregular recurrence down column m and owns coefficients (n, m),
-// n >= m, of its cell, so no two lanes write the same word.
+// monopole, L_n^m = q I_n^m(y - c_beta).  One lane per (cell, group of orders
+// m): the lane runs the irregular recurrences down its columns and owns
+// coefficients (n, m), n >= m, of its cell, so no two lanes write the same word.
 //
 // Path: the multipole expansions of the old and new cell of the moved charge
 // on every level change by -/+ its P2M; level 1 is the box multipole K of the
@@ -57,10 +57,48 @@ __host__ __device__ constexpr int col_offset(int P, int M0, int m)
     return o;
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton-Raphson
+// steps y <- y (3 - x y^2) / 2 (each doubles the correct bits).
+__device__ inline double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
+    return y;
+}
+
+// Scaled irregular harmonics.  With rho = 1/|d| and the unit vector
+// (xh, yh, zh) = rho d, write I_n^m(d) = q rho^(n+1) (2n-1)!! T_n^m; the
+// recurrences of I become
+//   T_0^0 = 1,  T_m^m = -(xh + i yh) T_{m-1}^{m-1},  T_{m+1}^m = zh T_m^m,
+//   T_n^m = zh T_{n-1}^m - c_n^m T_{n-2}^m,  c_n^m = ((n-1)^2 - m^2) / ((2n-1)(2n-3)),
+// with constant coefficients, so a term costs two operations and its
+// accumulation one fused multiply-add with q rho^(n+1); (2n-1)!! is applied
+// once per cell when the sums are added to the expansion.
+template <int P>
+struct ScaledIrregular {
+    double c[P + 1][P + 1];
+    double dfact[P + 1];  // (2n-1)!!
+    constexpr ScaledIrregular() : c{}, dfact{}
+    {
+        for (int n = 2; n <= P; ++n)
+            for (int m = 0; m + 2 <= n; ++m)
+                c[n][m] = (double)((n - 1) * (n - 1) - m * m) / (double)((2 * n - 1) * (2 * n - 3));
+        double f = 1.0;
+        dfact[0] = 1.0;
+        for (int n = 1; n <= P; ++n) {
+            f *= (double)(2 * n - 1);
+            dfact[n] = f;
+        }
+    }
+};
+
 template <int P, int M0, int M1>
 __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv, double *__restrict__ psi,
                            float *__restrict__ psi32)
 {
+    constexpr ScaledIrregular<P> SI{};
     constexpr int NACC = col_offset(P, M0, M1 + 1);
     double acc[NACC];
 #pragma unroll
@@ -68,56 +106,65 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv,
     const int nc = g.nc;
     const int bx = (int)(cell / ((int64_t)nc * nc)), by = (int)((cell / nc) % nc), bz = (int)(cell % nc);
     const double cxw = (bx + 0.5) * g.w, cyw = (by + 0.5) * g.w, czw = (bz + 0.5) * g.w;
-    const int lim = g.periodic ? 1 : 0;
-    for (int e = 0; e < 2; ++e) {
-        const double px = e ? mv.nx : mv.ox, py = e ? mv.ny : mv.oy, pz = e ? mv.nz : mv.oz;
-        const int gx0 = e ? mv.ngx : mv.ogx, gy0 = e ? mv.ngy : mv.ogy, gz0 = e ? mv.ngz : mv.ogz;
-        const double qq = e ? mv.q : -mv.q;
-        for (int i = -lim; i <= lim; ++i)
-            for (int j = -lim; j <= lim; ++j)
-                for (int k = -lim; k <= lim; ++k) {
-                    const int gx = gx0 + i * nc, gy = gy0 + j * nc, gz = gz0 + k * nc;
-                    if (abs(gx - bx) <= 1 && abs(gy - by) <= 1 && abs(gz - bz) <= 1) continue;
-                    const double dx = px + g.a * i - cxw, dy = py + g.a * j - cyw, dz = pz + g.a * k - czw;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    const double ir2 = 1.0 / r2;
-                    double dr = qq * sqrt(ir2), di = 0.0;  // q I_0^0
+    // sources: -q at the old and +q at the new position, each with its copies
+    // nu in V_box (periodic) or alone; a copy whose cell is one of the 27 around
+    // this cell is in the near field and contributes with charge 0 (no branch,
+    // so the sums stay in place across iterations)
+    const int nimg = g.periodic ? 27 : 1;
+#pragma unroll 1
+    for (int t = 0; t < 2 * nimg; ++t) {
+        const int e = t >= nimg ? 1 : 0;
+        const int nu = t - e * nimg;
+        const int i = g.periodic ? nu / 9 - 1 : 0, j = g.periodic ? (nu / 3) % 3 - 1 : 0,
+                  k = g.periodic ? nu % 3 - 1 : 0;
+        const int gx = (e ? mv.ngx : mv.ogx) + i * nc, gy = (e ? mv.ngy : mv.ogy) + j * nc,
+                  gz = (e ? mv.ngz : mv.ogz) + k * nc;
+        const bool near = abs(gx - bx) <= 1 && abs(gy - by) <= 1 && abs(gz - bz) <= 1;
+        double dx = (e ? mv.nx : mv.ox) + g.a * i - cxw, dy = (e ? mv.ny : mv.oy) + g.a * j - cyw,
+               dz = (e ? mv.nz : mv.oz) + g.a * k - czw;
+        dx = near ? 1.0 : dx;
+        dy = near ? 0.0 : dy;
+        dz = near ? 0.0 : dz;
+        const double qq = near ? 0.0 : (e ? mv.q : -mv.q);
+        const double rho = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+        const double xh = dx * rho, yh = dy * rho, zh = dz * rho;
+        double w[P + 1];  // q rho^(n+1)
+        w[0] = qq * rho;
 #pragma unroll
-                    for (int m = 0; m <= M1; ++m) {
-                        if (m > 0) {
-                            const double f = -(2 * m - 1) * ir2;
-                            const double ndr = f * (dx * dr - dy * di), ndi = f * (dx * di + dy * dr);
-                            dr = ndr;
-                            di = ndi;
-                        }
-                        if (m >= M0) {
-                            const int o = col_offset(P, M0, m);
-                            const bool cplxcol = m > 0;
-                            double ar = dr, ai = di;
-                            acc[o] += ar;
-                            if (cplxcol) acc[o + 1] += ai;
-                            if (m + 1 <= P) {
-                                const double zf = (2 * m + 1) * dz * ir2;
-                                double br = zf * ar, bi = zf * ai;
-                                acc[o + (cplxcol ? 2 : 1)] += br;
-                                if (cplxcol) acc[o + 3] += bi;
+        for (int n = 1; n <= P; ++n) w[n] = w[n - 1] * rho;
+        double dr = 1.0, di = 0.0;
 #pragma unroll
-                                for (int n = m + 2; n <= P; ++n) {
-                                    const double zn = (2 * n - 1) * dz * ir2;
-                                    const double wn = (double)((n - 1) * (n - 1) - m * m) * ir2;
-                                    const double cr = zn * br - wn * ar, ci = zn * bi - wn * ai;
-                                    const int t = n - m;
-                                    acc[o + (cplxcol ? 2 * t : t)] += cr;
-                                    if (cplxcol) acc[o + 2 * t + 1] += ci;
-                                    ar = br;
-                                    ai = bi;
-                                    br = cr;
-                                    bi = ci;
-                                }
-                            }
-                        }
+        for (int m = 0; m <= M1; ++m) {
+            if (m > 0) {
+                const double ndr = yh * di - xh * dr, ndi = -(xh * di + yh * dr);
+                dr = ndr;
+                di = ndi;
+            }
+            if (m >= M0) {
+                const int o = col_offset(P, M0, m);
+                const bool cplxcol = m > 0;
+                double ar = dr, ai = di;
+                acc[o] = fma(w[m], ar, acc[o]);
+                if (cplxcol) acc[o + 1] = fma(w[m], ai, acc[o + 1]);
+                if (m + 1 <= P) {
+                    double br = zh * ar, bi = zh * ai;
+                    acc[o + (cplxcol ? 2 : 1)] = fma(w[m + 1], br, acc[o + (cplxcol ? 2 : 1)]);
+                    if (cplxcol) acc[o + 3] = fma(w[m + 1], bi, acc[o + 3]);
+#pragma unroll
+                    for (int n = m + 2; n <= P; ++n) {
+                        const double cnm = SI.c[n][m];
+                        const double cr = fma(zh, br, -cnm * ar), ci = fma(zh, bi, -cnm * ai);
+                        const int tt = n - m;
+                        acc[o + (cplxcol ? 2 * tt : tt)] = fma(w[n], cr, acc[o + (cplxcol ? 2 * tt : tt)]);
+                        if (cplxcol) acc[o + 2 * tt + 1] = fma(w[n], ci, acc[o + 2 * tt + 1]);
+                        ar = br;
+                        ai = bi;
+                        br = cr;
+                        bi = ci;
                     }
                 }
+            }
+        }
     }
 #pragma unroll
     for (int m = M0; m <= M1; ++m) {
@@ -125,14 +172,15 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv,
 #pragma unroll
         for (int n = m; n <= P; ++n) {
             const int t = n - m;
+            const double f = SI.dfact[n];
             if (m == 0) {
                 const int64_t at = (int64_t)slot0(n) * M + cell;
-                const double v = psi[at] + acc[o + t];
+                const double v = fma(f, acc[o + t], psi[at]);
                 psi[at] = v;
                 if (psi32) psi32[at] = (float)v;
             } else {
                 const int64_t ar_ = (int64_t)slot_re(n, m) * M + cell, ai_ = (int64_t)slot_im(n, m) * M + cell;
-                const double vr = psi[ar_] + acc[o + 2 * t], vi = psi[ai_] + acc[o + 2 * t + 1];
+                const double vr = fma(f, acc[o + 2 * t], psi[ar_]), vi = fma(f, acc[o + 2 * t + 1], psi[ai_]);
                 psi[ar_] = vr;
                 psi[ai_] = vi;
                 if (psi32) {
