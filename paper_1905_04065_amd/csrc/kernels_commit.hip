@@ -27,7 +27,7 @@ struct Move {
 // fit in registers (at most kSweepBudget doubles); one lane per (cell, group).
 // The per-source work (offset, 1/r, the near test) is shared by a group's
 // columns, and the irregular diagonal I_m^m is carried across them.
-constexpr int kSweepBudget = 64;
+constexpr int kSweepBudget = 56;
 __host__ __device__ constexpr int col_cost(int P, int m) { return m == 0 ? P + 1 : 2 * (P - m + 1); }
 __host__ __device__ constexpr int group_end(int P, int m0)
 {
