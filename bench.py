@@ -28,31 +28,102 @@ sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector, published
+FP32_PEAK_TFLOPS = 157.3
+P2L_FLOP = 850             # one P2L of a point charge at p = 12 (irregular recurrences + accumulation)
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = {"site_phi_s2": "kernels_propose.hip", "slot_lattice": "kernels_propose.hip",
+                  "sweep": "kernels_commit.hip"}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel, n, N, K, p, precision):
-    """Bytes one launch must move at minimum (each input read once, each output written once)."""
+def kernel_work(kernel, n, N, K, p, precision):
+    """(bound, algorithmic amount per launch, unit) of the three kernels that
+    carry a step: what the method must move (bytes) or compute (flop) once."""
     nt = (p + 1) ** 2
     sites = n ** 3
     cells = sites // 8
+    mixed = precision == "mixed"
     if kernel == "site_phi_s2":
-        psi = cells * nt * (8 if precision == "fp64" else 4) + (0 if precision == "fp64" else cells * 8)
-        charges = sites * (8 if precision == "fp64" else 4)
-        far = n * n * (p + 1) * 8 + n * (p + 1) * 8
-        return psi + charges + far + sites * 8
+        # local expansions once (FP32 shadow + FP64 L_0^0 in mixed), charges, occupancy ranks,
+        # far-field tables, potentials out (per site and per charge)
+        psi = cells * nt * (4 if mixed else 8) + (cells * 8 if mixed else 0)
+        return "hbm", psi + sites * ((4 if mixed else 8) + 4 + 8) + N * 8 + n * n * (p + 1) * 8, "B"
     if kernel == "slot_lattice":
-        per_slot = 8 + 1 + 8          # dU out, mask out, F in
-        per_charge = 4 + 8            # site, q
-        return N * K * per_slot + N * per_charge + sites * 8 + sites * 4  # phi per site, site occupancy
+        # per slot: dU out, mask out, F in; per charge: site, index, q, phi_occ; potential of every site once
+        return "hbm", N * K * (8 + 1 + 8) + N * (4 + 4 + 8 + 8) + sites * 8, "B"
     if kernel == "sweep":
-        return 2 * cells * nt * 8 + (cells * nt * 4 if precision == "mixed" else 0)
+        # 27 copies x 2 endpoints of P2L into every fine cell
+        return "alu", cells * 54 * P2L_FLOP, "flop"
     raise KeyError(kernel)
+
+
+def sweep_bytes(n, p, precision):
+    nt = (p + 1) ** 2
+    cells = n ** 3 // 8
+    return 2 * cells * nt * 8 + (cells * nt * 4 if precision == "mixed" else 0)
+
+
+def source_sha(kernel):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1905_04065_amd", "csrc", KERNEL_SOURCES[kernel])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def profiled_traffic(workload_tag, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, per
+    kernel, scaled by the copy-kernel calibration; a kernel whose source changed
+    since the counters were taken gets None."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{workload_tag}.txt")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    cal = {}
+    rows = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+            if line.startswith("calibration"):
+                cal = {k: float(v) for k, v in kv.items()}
+            elif line.startswith("kernel"):
+                rows.append(kv)
+    for kv in rows:
+        if kv.get("precision") != precision:
+            continue
+        name = kv["name"]
+        if name not in KERNEL_SOURCES or kv.get("source_sha") != source_sha(name):
+            out[name] = None
+            continue
+        fetch = float(kv["fetch_kib"]) * 1024 * cal.get("fetch_factor", 1.0)
+        write = float(kv["write_kib"]) * 1024 * cal.get("write_factor", 1.0)
+        out[name] = fetch + write
+    return out
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read + write), GB/s of bytes moved."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms / 1e3) / 1e9
 
 
 def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed):
@@ -107,7 +178,7 @@ def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     names = ["site_phi_s2", "site_phi", "slot_lattice", "sweep", "path", "far_refresh", "cheb_a", "cheb_b", "f_rows",
-             "f_row1", "book", "move_dU"]
+             "f_row1", "book", "move_dU"]  # f_row1 runs on the side stream, beside the sweep
     ktimes = {nm: ctx.kernel_time(nm) for nm in names}
     ctx.set_profiling(False)
     # propose-only timing (no commit) for the proposal rate
@@ -170,6 +241,28 @@ def cpu_baseline(n, N, L, p, hops, seed, budget_s=20.0):
                        f"formation of the touched cells' local expansions excluded")
 
 
+def roofline_entry(kernel, kt, n, N, K, p, precision, copy_gbs, traffic):
+    ms, launches = kt.get(kernel, (0.0, 0))
+    if launches == 0:
+        return None
+    avg_s = ms / launches / 1e3
+    bound, amount, unit = kernel_work(kernel, n, N, K, p, precision)
+    e = {"kernel": kernel, "avg_us": avg_s * 1e6, "launches": launches}
+    if bound == "hbm":
+        ach = amount / avg_s / 1e9
+        e.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                 frac_of_copy=ach / copy_gbs if copy_gbs else None, algorithmic_bytes=amount)
+    else:
+        ach = amount / avg_s / 1e12
+        peak = FP64_PEAK_TFLOPS
+        e.update(bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, algorithmic_flop=amount,
+                 hbm_bytes=sweep_bytes(n, p, precision),
+                 hbm_GBps=sweep_bytes(n, p, precision) / avg_s / 1e9)
+    t = traffic.get(kernel) if traffic else None
+    e["traffic"] = t
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +270,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run the 1 GiB device copy used to calibrate rocprofv3 byte counters")
     ap.add_argument("--quick", action="store_true", help="small periodic system (64^3, N=1e5, L=6)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -187,57 +282,70 @@ def main():
         n, N, L, p, hops = 64, 100000, 6, 12, W.HOPS26
     else:
         n, N, L, p, hops = 128, 1000000, 7, 12, W.HOPS26
+    tag = f"periodic{n}_N{N}_p{p}"
     seed = W.BASE_SEED + 4
     K = len(hops)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     res = {pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed) for pr in precs}
-    head = res["fp64"] if "fp64" in res else res[precs[0]]
+    copy_gbs = copy_bandwidth()
+    if args.copy_calibration:
+        copy_bandwidth(1 << 30, reps=3)
+    head_prec = "fp64" if "fp64" in res else precs[0]
     slots = N * K
-    step_ms = head["ms_per_step"]
-    # dominant kernel of the propose pass and its roofline
-    kt = head["kernels"]
-    dom = max(["site_phi_s2", "slot_lattice"], key=lambda k: kt[k][0])
-    ms, launches = kt[dom]
-    avg_s = ms / max(launches, 1) / 1e3
-    hprec = "fp64" if "fp64" in res else precs[0]
-    bytes_ = algorithmic_bytes(dom, n, N, K, p, hprec)
-    achieved = bytes_ / avg_s / 1e9
+
+    def summary(pr):
+        r = res[pr]
+        kt = r["kernels"]
+        traffic = profiled_traffic(tag, pr)
+        roof = {k: roofline_entry(k, kt, n, N, K, p, pr, copy_gbs, traffic)
+                for k in ("site_phi_s2", "slot_lattice", "sweep")}
+        # the kernel that takes the largest share of a step
+        dom = max(roof, key=lambda k: roof[k]["avg_us"] if roof[k] else -1)
+        return dict(value=slots / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"],
+                    valid_per_s=r["valid_slots"] / (r["ms_per_step"] / 1e3),
+                    propose_only_per_s=slots / (r["propose_ms"] / 1e3), propose_us=r["propose_ms"] * 1e3,
+                    commit_us=r["commit_us"], setup_s=r["setup_s"],
+                    kernel_avg_us={k: (v[0] / max(v[1], 1) * 1e3) for k, v in kt.items() if v[1] > 0},
+                    dominant=dom, rooflines=roof)
+
+    head = summary(head_prec)
+    dom = head["dominant"]
+    droof = dict(head["rooflines"][dom])
     out = {
         "metric": "dU proposals/sec at N=1e6, p=12 (FP64 vs mixed); accepted-move commit us",
-        "value": slots / (step_ms / 1e3),
+        "value": head["value"],
         "unit": "proposals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": step_ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if hprec == "fp64" else "f32+f64",
+        "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"periodic {n}^3 lattice, N={N} +-1 charges, {K} hops/charge ({slots} slots/step), "
                                f"L={L}, p={p}, one accepted move per step",
                    "global_batch": slots, "parallelism": "single GPU"},
-        "propose_only_per_s": slots / (head["propose_ms"] / 1e3),
+        "valid_proposals_per_s": head["valid_per_s"],
+        "valid_slots": res[head_prec]["valid_slots"],
+        "propose_only_per_s": head["propose_only_per_s"],
+        "propose_us": head["propose_us"],
         "commit_us": head["commit_us"],
-        "valid_slots": head["valid_slots"],
         "setup_s": head["setup_s"],
-        "kernel_avg_us": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kt.items() if v[1] > 0},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": bytes_},
+        "copy_GBps": copy_gbs,
+        "kernel_avg_us": head["kernel_avg_us"],
+        "roofline": {k: droof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": dom,
+        "rooflines": head["rooflines"],
     }
-    if "mixed" in res and "fp64" in res:
-        m = res["mixed"]
-        out["mixed"] = {"value": slots / (m["ms_per_step"] / 1e3), "ms_per_step": m["ms_per_step"],
-                        "propose_only_per_s": slots / (m["propose_ms"] / 1e3), "commit_us": m["commit_us"],
+    if "mixed" in res and head_prec != "mixed":
+        m = summary("mixed")
+        out["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "valid_proposals_per_s": m["valid_per_s"],
+                        "propose_only_per_s": m["propose_only_per_s"], "propose_us": m["propose_us"],
+                        "commit_us": m["commit_us"],
                         "dtype": "f32 fine-level evaluation, f64 difference/far field/commit",
-                        "kernel_avg_us": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in m["kernels"].items()
-                                          if v[1] > 0}}
-        mk = m["kernels"][dom]
-        mavg = mk[0] / max(mk[1], 1) / 1e3
-        mb = algorithmic_bytes(dom, n, N, K, p, "mixed")
-        out["mixed"]["roofline"] = {"kernel": dom, "achieved": mb / mavg / 1e9, "peak": HBM_PEAK_GBS,
-                                    "frac": mb / mavg / 1e9 / HBM_PEAK_GBS}
+                        "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"]}
     if not args.skip_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(n, N, L, p, hops, seed)
