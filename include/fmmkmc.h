@@ -57,8 +57,8 @@ typedef struct fmmkmc_params {
     int order;         /* expansion order p, 1 <= p <= 16: (p+1)^2 coefficients per expansion */
     int precision;     /* FMMKMC_FP64, or FMMKMC_MIXED: FP32 fine-level local expansions
                           (constant term kept in FP64), FP32 near field and L2P with FP32
-                          accumulation; dU subtraction, far field, and all accept-step
-                          updates in FP64 */
+                          accumulation; dU subtraction, far field, all accept-step
+                          updates and the total energy in FP64 */
     int lattice_n;     /* 0, or n > 0: every charge sits on a site ((i+1/2)h, (j+1/2)h, (k+1/2)h)
                           of the n^3 lattice with h = a/n; enables fmmkmc_propose_lattice() */
     int cell_capacity; /* charge slots per fine cell; 0 picks sites-per-cell (lattice mode)

@@ -631,8 +631,9 @@ int fmmkmc_initialise(fmmkmc_ctx *c, double *U_out)
         if (c->prec == FMMKMC_MIXED) launch_shadow(c);
         if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c);
         double *phi = (double *)scratch(c, sizeof(double) * c->N);
+        // the total energy is always evaluated from the FP64 expansions
         launch_point_phi(c, g, c->N, nullptr, c->iota, c->iota, c->bc == FMMKMC_PERIODIC ? 1 : 0, phi,
-                         "point_phi_energy");
+                         "point_phi_energy", true);
         const int nb = 1024;
         launch(c, "energy_partials", k_energy_partials, dim3(nb), dim3(256), c->N, c->q, phi, c->red);
         std::vector<double> part(nb);

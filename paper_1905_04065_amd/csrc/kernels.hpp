@@ -64,7 +64,8 @@ void launch_far_refresh(fmmkmc_ctx *c);
 void launch_shadow(fmmkmc_ctx *c);
 // propose
 void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz, const int64_t *pidx,
-                      const int64_t *exclude, int with_far, double *out, const char *name);
+                      const int64_t *exclude, int with_far, double *out, const char *name,
+                      bool fp64 = false);
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g);
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask);
 void launch_sigma(fmmkmc_ctx *c, const Geo &g);

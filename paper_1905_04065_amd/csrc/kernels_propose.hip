@@ -99,11 +99,11 @@ __global__ __launch_bounds__(256) void k_point_phi(Geo g, int64_t M, int64_t m, 
 }
 
 void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz, const int64_t *pidx,
-                      const int64_t *exclude, int with_far, double *out, const char *name)
+                      const int64_t *exclude, int with_far, double *out, const char *name, bool fp64)
 {
     if (m <= 0) return;
     dim3 grid((unsigned)((m + 255) / 256));
-    if (c->prec == FMMKMC_MIXED) {
+    if (c->prec == FMMKMC_MIXED && !fp64) {
         FMMKMC_DISPATCH_P(c->p, launch(c, name, k_point_phi<P_, true>, grid, dim3(256), g, c->M, m, xyz, pidx,
                                        exclude, c->psi_lv[c->L], c->psi32, c->far.H, with_far, c->x, c->y, c->z,
                                        c->q, c->cell_cnt, c->cell_slots, out));

@@ -1,0 +1,219 @@
+"""GPU parity at the workload sizes of the benchmark configurations.
+
+Config 1 (free space, 32^3, N = 1000, L = 4, p = 8, FP64): every slot against
+O-fmm; the error of both against the direct sum (O-exact) is reported.
+Config 2 (periodic, 64^3, N = 1e5, L = 6, p = 12, FP64): 100 KMC steps, each a
+full proposal pass and one accepted move; every accepted dU against O-fmm
+replaying the same moves, then a seeded sample of proposals after the last
+commit, and the full mask.
+Config 3 (config 1 in mixed precision): 10^4 accepted moves, then every slot
+against O-fmm (FP64) replaying the same moves: the drift of the mixed path.
+Config 4 (periodic, 128^3, N = 1e6, 26 hops, L = 7, p = 12): the whole mask,
+bit-exact, and seeded samples of the 26M slots in FP64 and mixed; three
+accepted moves.
+
+Tolerances as in test_gpu_parity: guarded relative error 1e-10 (FP64) and
+1e-5 (mixed) against O-fmm with the same L, p, box and BC.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def guarded_err(d, ref, scale=None):
+    if scale is None:
+        scale = float(np.mean(np.abs(ref)))
+    return float(np.max(np.abs(d - ref) / np.maximum(np.abs(ref), scale)))
+
+
+def paper_rel_err(d, ref):
+    """the per-proposal relative error of the paper's error study (Sec. 6.1)"""
+    r = np.abs(d - ref) / np.abs(ref)
+    return float(np.mean(r)), float(np.max(r))
+
+
+def make_ctx(xyz, q, c, precision):
+    from paper_1905_04065_amd import Context
+    return Context(xyz, q, a=c["a"], levels=c["L"], order=c["p"], bc=c["bc"], precision=precision,
+                   lattice_n=c["n"], device=0)
+
+
+def gpu_lattice(ctx, hops):
+    import torch
+    dU, mask = ctx.propose_lattice(hops)
+    torch.cuda.synchronize()
+    return dU.cpu().numpy().reshape(-1), mask.cpu().numpy().reshape(-1).astype(bool)
+
+
+def test_config1_every_slot():
+    sites, xyz, q, c = W.config_system(1)
+    hops = W.hops(c["hops"])
+    print(f"config 1: n={c['n']} N={len(q)} L={c['L']} p={c['p']} free", flush=True)
+    t, v = W.lattice_targets(sites, c["n"], hops, False)
+    v = v.reshape(-1)
+    idx = np.repeat(np.arange(len(q)), len(hops))[v]
+    tgt = W.site_xyz(t.reshape(-1)[v], c["n"])
+    ctx = make_ctx(xyz, q, c, "fp64")
+    ctx.initialise()
+    dU, mask = gpu_lattice(ctx, hops)
+    ctx.close()
+    assert np.array_equal(mask, v)
+    assert np.all(np.isnan(dU[~v]))
+    ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "free").propose(idx, tgt)
+    err = guarded_err(dU[v], ref)
+    exact = O.direct_dU(xyz, q, idx, tgt)
+    g_mean, g_max = paper_rel_err(dU[v], exact)
+    o_mean, o_max = paper_rel_err(ref, exact)
+    print(f"  vs O-fmm: max guarded rel err {err:.3e} over {v.sum()} slots", flush=True)
+    print(f"  vs O-exact (direct sum): GPU mean/max rel err {g_mean:.3e}/{g_max:.3e}, "
+          f"O-fmm {o_mean:.3e}/{o_max:.3e}", flush=True)
+    assert err < 1e-10
+    # truncation error at p = 8 is of the size the paper's error study shows (Tab. error_p_diffs)
+    assert g_mean < 1e-2
+    assert abs(g_mean - o_mean) < 1e-6
+
+
+def test_config2_hundred_steps_with_commit():
+    sites, xyz, q, c = W.config_system(2)
+    hops = W.hops(c["hops"])
+    n, K, N = c["n"], len(hops), len(q)
+    print(f"config 2: n={n} N={N} L={c['L']} p={c['p']} periodic, {c['steps']} steps", flush=True)
+    ctx = make_ctx(xyz, q, c, "fp64")
+    U0 = ctx.initialise()
+    ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "periodic", lazy=True)
+    u = W.commit_choices(c["steps"], W.BASE_SEED + 2)
+    cur = sites.copy()
+    worst = 0.0
+    total = 0.0
+    for step in range(c["steps"]):
+        dU, mask = gpu_lattice(ctx, hops)
+        t, v = W.lattice_targets(cur, n, hops, True)
+        v = v.reshape(-1)
+        if step == 0 or step == c["steps"] - 1:
+            assert np.array_equal(mask, v), step
+            assert np.all(np.isnan(dU[~v])), step
+        vs = np.nonzero(v)[0]
+        s = vs[int(u[step] * len(vs))]
+        i = int(s // K)
+        new = W.site_xyz([t.reshape(-1)[s]], n)[0]
+        d_gpu = ctx.accept(i, new)
+        d_ref = ref.accept(i, new)
+        # the accepted move's dU, and the proposal pass's value for the same slot
+        assert abs(d_gpu - d_ref) <= 1e-10 * max(abs(d_ref), 0.05), (step, d_gpu, d_ref)
+        assert abs(dU[s] - d_ref) <= 1e-10 * max(abs(d_ref), 0.05), (step, dU[s], d_ref)
+        worst = max(worst, abs(d_gpu - d_ref) / max(abs(d_ref), 0.05))
+        total += d_gpu
+        cur[i] = t.reshape(-1)[s]
+    print(f"  {c['steps']} accepted moves: max guarded rel err {worst:.3e}", flush=True)
+    assert ctx.energy == pytest.approx(U0 + total, abs=1e-12 * max(1.0, abs(U0)))
+    np.testing.assert_array_equal(ctx.positions().cpu().numpy(), ref.positions())
+    dU, mask = gpu_lattice(ctx, hops)
+    t, v = W.lattice_targets(cur, n, hops, True)
+    v = v.reshape(-1)
+    assert np.array_equal(mask, v)
+    rng = np.random.default_rng(W.BASE_SEED + 20)
+    pick = rng.choice(np.nonzero(v)[0], 512, replace=False)
+    d_ref = ref.propose(pick // K, W.site_xyz(t.reshape(-1)[pick], n))
+    err = guarded_err(dU[pick], d_ref, scale=float(np.nanmean(np.abs(dU[v]))))
+    print(f"  after the steps, 512 sampled slots: max guarded rel err {err:.3e}", flush=True)
+    assert err < 1e-10
+    ctx.close()
+    ref.close()
+
+
+def test_config3_mixed_drift_after_ten_thousand_commits():
+    sites, xyz, q, c = W.config_system(3)
+    hops = W.hops(c["hops"])
+    n, K, N = c["n"], len(hops), len(q)
+    commits = c["commits"]
+    print(f"config 3: n={n} N={N} L={c['L']} p={c['p']} free, mixed, {commits} commits", flush=True)
+    ctx = make_ctx(xyz, q, c, "mixed")
+    ctx.initialise()
+    ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "free")
+    d0, _ = gpu_lattice(ctx, hops)
+    t, v = W.lattice_targets(sites, n, hops, False)
+    v = v.reshape(-1)
+    idx = np.repeat(np.arange(N), K)
+    r0 = ref.propose(idx[v], W.site_xyz(t.reshape(-1)[v], n))
+    err0 = guarded_err(d0[v], r0)
+    u = W.commit_choices(commits, W.BASE_SEED + 3)
+    cur = sites.copy()
+    worst = 0.0
+    scale = float(np.mean(np.abs(r0)))
+    for step in range(commits):
+        t, v = W.lattice_targets(cur, n, hops, False)
+        vs = np.nonzero(v.reshape(-1))[0]
+        s = vs[int(u[step] * len(vs))]
+        i = int(s // K)
+        new = W.site_xyz([t.reshape(-1)[s]], n)[0]
+        d_gpu = ctx.accept(i, new)
+        d_ref = ref.accept(i, new)
+        worst = max(worst, abs(d_gpu - d_ref) / max(abs(d_ref), scale))
+        cur[i] = t.reshape(-1)[s]
+    d1, mask = gpu_lattice(ctx, hops)
+    t, v = W.lattice_targets(cur, n, hops, False)
+    v = v.reshape(-1)
+    assert np.array_equal(mask, v)
+    r1 = ref.propose(idx[v], W.site_xyz(t.reshape(-1)[v], n))
+    err1 = guarded_err(d1[v], r1)
+    dE = abs(ctx.energy - ref.energy)
+    print(f"  before: max guarded rel err {err0:.3e}; after {commits} commits: {err1:.3e}; "
+          f"accepted dU (FP64 accept path) max {worst:.3e}; energy drift {dE:.3e}", flush=True)
+    assert err0 < 1e-5 and err1 < 1e-5
+    # accepted moves are recomputed from the FP64 expansions
+    assert worst < 1e-10
+    assert dE <= 1e-10 * max(1.0, abs(ref.energy))
+    ctx.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_config4_sampled_slots_and_full_mask(precision, tol):
+    sites, xyz, q, c = W.config_system(4)
+    hops = W.hops(c["hops"])
+    n, K, N = c["n"], len(hops), len(q)
+    print(f"config 4: n={n} N={N} L={c['L']} p={c['p']} periodic, {K} hops, {precision}", flush=True)
+    ctx = make_ctx(xyz, q, c, precision)
+    ctx.initialise()
+    dU, mask = gpu_lattice(ctx, hops)
+    t, v = W.lattice_targets(sites, n, hops, True)
+    v = v.reshape(-1)
+    assert np.array_equal(mask, v)
+    assert np.all(np.isnan(dU[~v])) and not np.any(np.isnan(dU[v]))
+    ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "periodic", lazy=True)
+    rng = np.random.default_rng(W.BASE_SEED + 40)
+    pick = rng.choice(np.nonzero(v)[0], 384, replace=False)
+    d_ref = ref.propose(pick // K, W.site_xyz(t.reshape(-1)[pick], n))
+    scale = float(np.mean(np.abs(dU[v])))
+    err = guarded_err(dU[pick], d_ref, scale=scale)
+    print(f"  384 sampled slots of {v.sum()} valid: max guarded rel err {err:.3e} (mean |dU| {scale:.4f})",
+          flush=True)
+    assert err < tol
+    # three accepted moves, then a second sample
+    u = W.commit_choices(3, W.BASE_SEED + 41)
+    cur = sites.copy()
+    for step in range(3):
+        t, v = W.lattice_targets(cur, n, hops, True)
+        vs = np.nonzero(v.reshape(-1))[0]
+        s = vs[int(u[step] * len(vs))]
+        i = int(s // K)
+        new = W.site_xyz([t.reshape(-1)[s]], n)[0]
+        d_gpu = ctx.accept(i, new)
+        d_ref = ref.accept(i, new)
+        assert abs(d_gpu - d_ref) <= 1e-10 * max(abs(d_ref), scale), (step, d_gpu, d_ref)
+        cur[i] = t.reshape(-1)[s]
+    dU, mask = gpu_lattice(ctx, hops)
+    t, v = W.lattice_targets(cur, n, hops, True)
+    v = v.reshape(-1)
+    assert np.array_equal(mask, v)
+    pick = rng.choice(np.nonzero(v)[0], 128, replace=False)
+    d_ref = ref.propose(pick // K, W.site_xyz(t.reshape(-1)[pick], n))
+    err = guarded_err(dU[pick], d_ref, scale=scale)
+    print(f"  after 3 commits, 128 sampled slots: max guarded rel err {err:.3e}", flush=True)
+    assert err < tol
+    ctx.close()
+    ref.close()
