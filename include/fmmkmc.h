@@ -139,6 +139,62 @@ const char *fmmkmc_last_error(fmmkmc_ctx *c);
 /* Free the context and all its device memory. */
 int fmmkmc_destroy(fmmkmc_ctx *c);
 
+/* ---- batched replicas --------------------------------------------------
+ * Independent KMC systems of uneven sizes run side by side (ensembles, which
+ * Sec. 6.4 runs as simultaneous instances) and advance together: each KMC step of Alg. 1 (every proposal's dU, selection of one
+ * move, accept) is one launch per phase over all replicas, and the whole step
+ * is captured once as a HIP graph and replayed. */
+typedef struct fmmkmc_batch fmmkmc_batch;
+
+/* Group n initialised lattice-mode contexts (HOST array ctx[n]) that share
+ * expansion order, precision and device; the contexts stay owned by the
+ * caller and must outlive the batch.  Every replica proposes the same K hops
+ * offsets[k] (K x 3 HOST ints, |entries| <= 1, as in fmmkmc_propose_lattice).
+ * stream: hipStream_t for the batch's work, not the legacy null stream (a step
+ * is captured as a graph on it); NULL: the batch creates a stream of its own.
+ * Errors: EINVAL (n < 1, mixed orders/precisions/devices, no lattice, bad K),
+ * ESTATE (a context not initialised), EHIP, ENOMEM. */
+int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *offsets, void *stream,
+                        fmmkmc_batch **out);
+
+/* n_steps KMC steps on every replica r.  Step s: dU of every (charge, hop) slot;
+ * then the move taken is valid slot number floor(u[s n + r] * V) of the V valid
+ * slots in slot order (i * K + k), u uniform in [0, 1) (a selection that does
+ * not look at dU; u: n_steps x n DEVICE doubles); then that move is accepted
+ * (dU recomputed from the FP64 expansions, every expansion updated, U += dU).
+ * A replica with no valid slot does not move.  Outputs (DEVICE arrays of
+ * n_steps x n, each may be NULL): moved[s n + r] the charge moved (-1 if none),
+ * site[s n + r] its new lattice site (lattice order), dU[s n + r] the accepted
+ * dU (NaN if none).  Returns after the steps are complete; the contexts' energies
+ * are updated and their single-context calls see the new configuration. */
+int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *moved, int64_t *site, double *dU);
+
+/* Copy replica r's dU and mask of the last proposal pass (N_r x K device arrays;
+ * mask may be NULL). */
+int fmmkmc_batch_proposals(fmmkmc_batch *b, int r, double *dU, uint8_t *mask);
+
+/* Autotuner: time the tile choices of the phases that have them (charges per
+ * block of the slot gather, threads per block of the sweep) on this batch and
+ * keep the fastest; the step graph is captured again with them.  rounds: timed
+ * launches per candidate (>= 1).  The choices can be read with
+ * fmmkmc_batch_info(). */
+int fmmkmc_batch_tune(fmmkmc_batch *b, int rounds);
+
+/* Slots per step (sum of N_r K) and the current tile choices. */
+int fmmkmc_batch_info(fmmkmc_batch *b, int64_t *slots_per_step, int *slot_tile, int *sweep_block);
+
+/* Per-phase timing of batched steps: with profiling on, steps run as plain
+ * launches (not the graph) bracketed by HIP events; names as in the kernels
+ * ("b_site", "b_slot", "b_select", "b_sweep", ...). */
+int fmmkmc_batch_set_profiling(fmmkmc_batch *b, int on);
+int fmmkmc_batch_kernel_time(fmmkmc_batch *b, const char *name, double *ms, int64_t *launches);
+
+/* Text of the last error on this batch. */
+const char *fmmkmc_batch_last_error(fmmkmc_batch *b);
+
+/* Free the batch (not its contexts). */
+int fmmkmc_batch_destroy(fmmkmc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

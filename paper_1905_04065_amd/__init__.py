@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Context", "FmmKmcError", "library_path", "load_library"]
+__all__ = ["Batch", "Context", "FmmKmcError", "library_path", "load_library"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -65,6 +65,15 @@ def load_library():
         "fmmkmc_kernel_time": (i32, [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64)]),
         "fmmkmc_last_error": (C.c_char_p, [vp]),
         "fmmkmc_destroy": (i32, [vp]),
+        "fmmkmc_batch_create": (i32, [i32, vp, i32, vp, vp, C.POINTER(vp)]),
+        "fmmkmc_batch_step": (i32, [vp, i32, vp, vp, vp, vp]),
+        "fmmkmc_batch_proposals": (i32, [vp, i32, vp, vp]),
+        "fmmkmc_batch_tune": (i32, [vp, i32]),
+        "fmmkmc_batch_info": (i32, [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
+        "fmmkmc_batch_set_profiling": (i32, [vp, i32]),
+        "fmmkmc_batch_kernel_time": (i32, [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64)]),
+        "fmmkmc_batch_last_error": (C.c_char_p, [vp]),
+        "fmmkmc_batch_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -244,4 +253,81 @@ class Context:
         """(total ms, launches) of a kernel since profiling was switched on"""
         ms, n = C.c_double(), C.c_int64()
         self._check(self._L.fmmkmc_kernel_time(self._h, name.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+class Batch:
+    """Replicas (initialised lattice-mode Contexts with one order and precision)
+    advanced together: each KMC step is one launch per phase over all of them,
+    replayed from a captured HIP graph.  The contexts stay owned by the caller."""
+
+    def __init__(self, contexts, offsets, stream=None):
+        torch = _torch()
+        self._L = load_library()
+        self.contexts = list(contexts)
+        self.R = len(self.contexts)
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+        self.K = off.shape[0]
+        self.device = self.contexts[0].device
+        arr = (C.c_void_p * self.R)(*[c._h.value for c in self.contexts])
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        h = C.c_void_p()
+        rc = self._L.fmmkmc_batch_create(self.R, C.cast(arr, C.c_void_p), self.K, off.ctypes.data_as(C.c_void_p),
+                                         st, C.byref(h))
+        if rc != OK:
+            raise FmmKmcError(rc, self._L.fmmkmc_batch_last_error(None).decode())
+        self._h = h
+        self._torch = torch
+
+    def _check(self, rc):
+        if rc != OK:
+            raise FmmKmcError(rc, self._L.fmmkmc_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fmmkmc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, u):
+        """len(u) // R steps with the uniforms u (n_steps x R); returns device
+        tensors (moved charge, new site, dU), each n_steps x R."""
+        torch = self._torch
+        u = torch.as_tensor(u, dtype=torch.float64, device=self.device).reshape(-1, self.R).contiguous()
+        n = u.shape[0]
+        moved = torch.empty((n, self.R), dtype=torch.int64, device=self.device)
+        site = torch.empty((n, self.R), dtype=torch.int64, device=self.device)
+        dU = torch.empty((n, self.R), dtype=torch.float64, device=self.device)
+        self._check(self._L.fmmkmc_batch_step(self._h, n, _ptr(u), _ptr(moved), _ptr(site), _ptr(dU)))
+        return moved, site, dU
+
+    def proposals(self, r):
+        """dU and mask (N_r x K device tensors) of replica r's last proposal pass"""
+        torch = self._torch
+        N = self.contexts[r].N
+        dU = torch.empty((N, self.K), dtype=torch.float64, device=self.device)
+        mask = torch.empty((N, self.K), dtype=torch.uint8, device=self.device)
+        self._check(self._L.fmmkmc_batch_proposals(self._h, int(r), _ptr(dU), _ptr(mask)))
+        return dU, mask
+
+    def tune(self, rounds=5):
+        self._check(self._L.fmmkmc_batch_tune(self._h, int(rounds)))
+        return self.info()
+
+    def info(self):
+        slots, tile, blk = C.c_int64(), C.c_int(), C.c_int()
+        self._check(self._L.fmmkmc_batch_info(self._h, C.byref(slots), C.byref(tile), C.byref(blk)))
+        return {"slots_per_step": slots.value, "slot_tile": tile.value, "sweep_block": blk.value}
+
+    def set_profiling(self, on=True):
+        self._check(self._L.fmmkmc_batch_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_time(self, name):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self._L.fmmkmc_batch_kernel_time(self._h, name.encode(), C.byref(ms), C.byref(n)))
         return ms.value, n.value

@@ -7,51 +7,13 @@
 #include <string>
 #include <vector>
 
+#include "hostutil.hpp"
 #include "kernels.hpp"
 #include "tables.hpp"
 
 using namespace fmmkmc;
 
 namespace {
-
-struct HipError {
-    std::string what;
-};
-
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess) throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_)}; \
-    } while (0)
-
-int fail(fmmkmc_ctx *c, int code, const std::string &msg)
-{
-    if (c) c->err = msg;
-    return code;
-}
-
-template <typename T>
-T *dalloc(size_t count)
-{
-    if (count == 0) count = 1;
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(T) * count);
-    if (e != hipSuccess) throw std::bad_alloc();
-    return (T *)p;
-}
-
-template <typename T>
-void dfree(T *&p)
-{
-    if (p) (void)hipFree((void *)p);
-    p = nullptr;
-}
-
-template <typename T>
-void upload(T *dst, const T *src, size_t count, hipStream_t s)
-{
-    HIPCHK(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s));
-}
 
 // scratch buffer of at least `bytes`
 void *scratch(fmmkmc_ctx *c, size_t bytes)
@@ -104,6 +66,36 @@ int32_t pack_ijk(const fmmkmc_ctx *c, int64_t lat)
     return (int32_t)((i << 20) | (j << 10) | k);
 }
 
+}  // namespace
+
+// Host mirrors of a context whose device state was advanced by batched steps
+// (the batch moves charges on the device only): download what the
+// single-context accept validates against.
+void refresh_mirrors(fmmkmc_ctx *c)
+{
+    if (!c->dev_ahead) return;
+    const int64_t n = c->N;
+    const hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->hx.data(), c->x, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hy.data(), c->y, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hz.data(), c->z, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hcell.data(), c->cell, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hslot.data(), c->slot, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hcnt.data(), c->cell_cnt, sizeof(int32_t) * c->M, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->hslots.data(), c->cell_slots, sizeof(int32_t) * c->M * c->cap, hipMemcpyDeviceToHost,
+                          s));
+    if (c->lat_n > 0) {
+        HIPCHK(hipMemcpyAsync(c->hsite.data(), c->site, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::fill(c->hsite_charge.begin(), c->hsite_charge.end(), -1);
+        for (int64_t i = 0; i < n; ++i) c->hsite_charge[c->hsite[i]] = (int32_t)i;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    c->dev_ahead = false;
+}
+
+namespace {
+
 void release(fmmkmc_ctx *c)
 {
     dfree(c->x);
@@ -150,6 +142,7 @@ void release(fmmkmc_ctx *c)
     dfree(c->red);
     dfree(c->iota);
     dfree(c->acc_buf);
+    dfree(c->rank_of);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -472,6 +465,8 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
             c->phi_r = dalloc<double>(n);
             c->order = dalloc<int32_t>(n);
             upload(c->order, ord.data(), n, s);
+            c->rank_of = dalloc<int32_t>(n);
+            upload(c->rank_of, c->hrank.data(), n, s);
             c->ijk_r = dalloc<int32_t>(n);
             upload(c->ijk_r, pk.data(), n, s);
             c->q_r = dalloc<double>(n);
@@ -534,13 +529,6 @@ __global__ void k_interleave(int64_t n, const double *x, const double *y, const 
     out[3 * i + 2] = z[i];
 }
 
-// message of the last failed fmmkmc_create on this thread
-std::string &create_error()
-{
-    static thread_local std::string msg;
-    return msg;
-}
-
 int read_flags(fmmkmc_ctx *c, int32_t *out)
 {
     HIPCHK(hipMemcpyAsync(out, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -583,15 +571,6 @@ void Profiler::resolve()
 }
 
 }  // namespace fmmkmc
-
-#define API_GUARD(c, ...)                                            \
-    try {                                                            \
-        __VA_ARGS__                                                  \
-    } catch (const HipError &e) {                                    \
-        return fail(c, FMMKMC_EHIP, e.what);                         \
-    } catch (const std::bad_alloc &) {                               \
-        return fail(c, FMMKMC_ENOMEM, "device or host allocation failed"); \
-    }
 
 extern "C" {
 
@@ -763,6 +742,9 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
     if (!c) return FMMKMC_EINVAL;
     if (!c->initialised) return fail(c, FMMKMC_ESTATE, "accept before initialise");
     if (i < 0 || i >= c->N || !new_xyz) return fail(c, FMMKMC_EINVAL, "bad charge index or position");
+    if (c->dev_ahead) {
+        API_GUARD(c, { refresh_mirrors(c); })
+    }
     double np[3];
     for (int d = 0; d < 3; ++d) {
         if (!std::isfinite(new_xyz[d])) return fail(c, FMMKMC_EDOMAIN, "non-finite position");

@@ -1,0 +1,789 @@
+// Batched replicas: many independent lattice systems advanced by one launch
+// per phase of a KMC step (Alg. 1: every proposal's dU, selection of one move,
+// accept), the whole step captured once as a HIP graph.
+//
+// Phases of a step, each one launch over every replica (block ranges per
+// replica, see batch.hpp):
+//   b_site, b_slot      the proposal pass (Sec. 3: dU of every hop)
+//   b_count, b_select   the move: valid slot number floor(u V) in slot order,
+//                       then the accept arguments built on the device
+//   b_move_dU           dU of the move recomputed (footnote to Sec. 3.1)
+//   b_frow              the moved charge's row of the hop table
+//   b_sweep, b_path     every fine-level local expansion, the multipole path
+//   b_book              positions, cell slots, site tables
+//   b_far_refresh, b_cheb_a, b_cheb_b   far field (Sec. 3.1)
+//   b_finish            U += dU, outputs, step counter
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmkmc.h"
+#include "batch.hpp"
+#include "hostutil.hpp"
+#include "kernels.hpp"
+
+using namespace fmmkmc;
+
+namespace {
+
+constexpr int kSelChunk = 1024;  // slots per counting block (256 lanes x 4)
+
+// valid slots in each chunk of kSelChunk consecutive slots of a replica
+__global__ __launch_bounds__(256) void k_b_count(const RepDev *__restrict__ reps, int R,
+                                                 const int64_t *__restrict__ base, int32_t *__restrict__ counts)
+{
+    __shared__ int red[256];
+    const int r = find_rep(base, R, blockIdx.x);
+    const RepDev &d = reps[r];
+    const int64_t S = d.N * d.K, s0 = (blockIdx.x - base[r]) * (int64_t)kSelChunk;
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t s = s0 + j * 256 + threadIdx.x;
+        if (s < S && d.mask[s]) ++c;
+    }
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+}
+
+// exclusive prefix sum over the 256 lanes of a block; *total gets the sum
+__device__ int64_t block_excl_scan(int64_t v, int64_t *sm, int64_t *total)
+{
+    const int t = threadIdx.x;
+    sm[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int64_t x = t >= off ? sm[t - off] : 0;
+        __syncthreads();
+        sm[t] += x;
+        __syncthreads();
+    }
+    const int64_t incl = sm[t];
+    *total = sm[255];
+    __syncthreads();
+    return incl - v;
+}
+
+// the accept arguments of moving charge i by hop k (the device-side
+// counterpart of what fmmkmc_accept derives on the host)
+__device__ void prepare_move(const RepDev &d, int64_t slot, MoveDev &m)
+{
+    const int K = d.K, n = d.g.n, nc = d.g.nc, cap = d.cap;
+    const int64_t i = slot / K;
+    const int k = (int)(slot - i * K);
+    const int32_t os = d.site[i];
+    const int si = os / (n * n), sj = (os / n) % n, sk = os % n;
+    int ti = si + d.offsets[3 * k], tj = sj + d.offsets[3 * k + 1], tk = sk + d.offsets[3 * k + 2];
+    if (d.g.periodic) {
+        ti = posmod(ti, n);
+        tj = posmod(tj, n);
+        tk = posmod(tk, n);
+    }
+    const int64_t ns = ((int64_t)ti * n + tj) * n + tk;
+    const double h = d.g.h, w = d.g.w;
+    const double nx = (ti + 0.5) * h, ny = (tj + 0.5) * h, nz = (tk + 0.5) * h;
+    const double ox = d.x[i], oy = d.y[i], oz = d.z[i], q = d.q[i];
+    const int ogx = fine_coord(ox, w, nc), ogy = fine_coord(oy, w, nc), ogz = fine_coord(oz, w, nc);
+    const int ngx = fine_coord(nx, w, nc), ngy = fine_coord(ny, w, nc), ngz = fine_coord(nz, w, nc);
+    const int64_t old_cell = d.cell[i], new_cell = cell_id(nc, ngx, ngy, ngz);
+    const int old_slot = d.slot[i];
+    int moved_j = -1, old_cnt = d.cnt[old_cell], new_slot = old_slot, new_cnt = d.cnt[new_cell];
+    if (new_cell != old_cell) {
+        const int last = d.cnt[old_cell] - 1;
+        const int jlast = d.slots[old_cell * cap + last];
+        moved_j = jlast != i ? jlast : -1;
+        old_cnt = last;
+        new_slot = d.cnt[new_cell];
+        new_cnt = d.cnt[new_cell] + 1;
+    }
+    m.valid = 1;
+    m.i = i;
+    m.slot = slot;
+    m.new_site = ns;
+    m.rank = d.rank_of[i];
+    m.t[0] = nx;
+    m.t[1] = ny;
+    m.t[2] = nz;
+    Move &mv = m.mv;
+    mv.ox = ox;
+    mv.oy = oy;
+    mv.oz = oz;
+    mv.nx = nx;
+    mv.ny = ny;
+    mv.nz = nz;
+    mv.q = q;
+    mv.ogx = ogx;
+    mv.ogy = ogy;
+    mv.ogz = ogz;
+    mv.ngx = ngx;
+    mv.ngy = ngy;
+    mv.ngz = ngz;
+    Book &b = m.bk;
+    b.i = i;
+    b.nx = nx;
+    b.ny = ny;
+    b.nz = nz;
+    b.q = q;
+    b.old_cell = old_cell;
+    b.new_cell = new_cell;
+    b.old_slot = old_slot;
+    b.new_slot = new_slot;
+    b.moved_j = moved_j;
+    b.old_cnt = old_cnt;
+    b.new_cnt = new_cnt;
+    b.new_site = ns;
+    b.old_sord = d.s2 ? s2_site(nc, si, sj, sk) : (int64_t)os;
+    b.new_sord = d.s2 ? s2_site(nc, ti, tj, tk) : ns;
+    b.new_ijk = (ti << 20) | (tj << 10) | tk;
+    b.rank = m.rank;
+    b.s2 = d.s2;
+    b.same_cell = old_cell == new_cell ? 1 : 0;
+}
+
+// one block per replica: the valid slot number floor(u V) in slot order
+__global__ __launch_bounds__(256) void k_b_select(const RepDev *__restrict__ reps, int R,
+                                                  const int64_t *__restrict__ cbase,
+                                                  const int32_t *__restrict__ counts, const double *__restrict__ u,
+                                                  const int32_t *__restrict__ step, MoveDev *__restrict__ moves)
+{
+    __shared__ int64_t sm[256];
+    __shared__ int64_t s_chunk, s_rank, s_slot;
+    const int r = blockIdx.x;
+    const RepDev &d = reps[r];
+    const int t = threadIdx.x;
+    const int64_t c0 = cbase[r], nch = cbase[r + 1] - c0;
+    // chunks split into 256 contiguous ranges, one per lane
+    const int64_t per = (nch + 255) / 256;
+    const int64_t k0 = (int64_t)t * per < nch ? (int64_t)t * per : nch;
+    const int64_t k1 = k0 + per < nch ? k0 + per : nch;
+    int64_t mine = 0;
+    for (int64_t k = k0; k < k1; ++k) mine += counts[c0 + k];
+    int64_t V;
+    const int64_t excl = block_excl_scan(mine, sm, &V);
+    if (V == 0) {
+        if (t == 0) moves[r].valid = 0;
+        return;  // uniform across the block
+    }
+    const double uu = u[(int64_t)(*step) * R + r];
+    int64_t want = (int64_t)floor(uu * (double)V);
+    want = want < 0 ? 0 : (want >= V ? V - 1 : want);
+    if (want >= excl && want < excl + mine) {
+        int64_t acc = excl;
+        for (int64_t k = k0; k < k1; ++k) {
+            const int c = counts[c0 + k];
+            if (want < acc + c) {
+                s_chunk = k;
+                s_rank = want - acc;
+                break;
+            }
+            acc += c;
+        }
+    }
+    __syncthreads();
+    // within the chunk: 4 consecutive slots per lane
+    const int64_t S = d.N * d.K, b0 = s_chunk * kSelChunk + 4 * t;
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (b0 + j < S && d.mask[b0 + j]) ++cnt;
+    int64_t tot;
+    const int64_t ex2 = block_excl_scan(cnt, sm, &tot);
+    const int64_t rk = s_rank;
+    if (rk >= ex2 && rk < ex2 + cnt) {
+        int64_t acc = ex2;
+        for (int j = 0; j < 4; ++j) {
+            if (b0 + j < S && d.mask[b0 + j]) {
+                if (acc == rk) {
+                    s_slot = b0 + j;
+                    break;
+                }
+                ++acc;
+            }
+        }
+    }
+    __syncthreads();
+    if (t == 0) prepare_move(d, s_slot, moves[r]);
+}
+
+// U += dU (parts added in order, as the single-context accept does), outputs, next step
+__global__ __launch_bounds__(256) void k_b_finish(const MoveDev *__restrict__ moves, int R,
+                                                  const double *__restrict__ acc, double *__restrict__ U,
+                                                  int32_t *__restrict__ step, int64_t *__restrict__ out_i,
+                                                  int64_t *__restrict__ out_site, double *__restrict__ out_dU)
+{
+    const int st = *step;
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        const MoveDev &m = moves[r];
+        double dU = __builtin_nan("");
+        int64_t i = -1, site = -1;
+        if (m.valid) {
+            dU = 0.0;
+            for (int k = 0; k < kMoveParts; ++k) dU += acc[(int64_t)r * kMoveParts + k];
+            U[r] += dU;
+            i = m.i;
+            site = m.new_site;
+        }
+        const int64_t o = (int64_t)st * R + r;
+        out_i[o] = i;
+        out_site[o] = site;
+        out_dU[o] = dU;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *step = st + 1;
+}
+
+__global__ void k_b_set_step(int32_t *step, int v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step = v;
+}
+
+// zero-charge moves (valid, q = 0) for timing the sweep: they add exact zeros
+__global__ void k_b_null_moves(const RepDev *__restrict__ reps, int R, MoveDev *__restrict__ moves)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double p = 0.3 * reps[r].g.w;
+    MoveDev &m = moves[r];
+    m.valid = 1;
+    m.mv.ox = m.mv.oy = m.mv.oz = m.mv.nx = m.mv.ny = m.mv.nz = p;
+    m.mv.q = 0.0;
+    m.mv.ogx = m.mv.ogy = m.mv.ogz = m.mv.ngx = m.mv.ngy = m.mv.ngz = 0;
+}
+
+}  // namespace
+
+namespace fmmkmc {
+// block ranges of one batched phase
+struct Phase {
+    std::vector<int64_t> base;  // host copy, R + 1
+    int64_t *d = nullptr;       // device copy
+    int64_t blocks = 0;
+};
+}  // namespace fmmkmc
+
+struct fmmkmc_batch {
+    int R = 0, p = 0, nt = 0, K = 0, device = 0;
+    bool mixed = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<fmmkmc_ctx *> ctx;
+    std::vector<int32_t> offsets;
+    std::vector<RepDev> host_reps;  // what the device descriptors hold
+    std::string err;
+    Profiler prof;
+    // device state
+    RepDev *reps = nullptr;
+    MoveDev *moves = nullptr, *null_moves = nullptr;
+    double *acc = nullptr, *U = nullptr;
+    int32_t *step = nullptr, *counts = nullptr;
+    std::vector<double *> dU;
+    std::vector<uint8_t *> mask;
+    double *u = nullptr;
+    int64_t *out_i = nullptr, *out_site = nullptr;
+    double *out_dU = nullptr;
+    int cap_steps = 0;
+    // phases
+    Phase site, slot, count, sweep, path, far, cheb_a, cheb_b;
+    int slot_tc = 64, sweep_block = 256;
+    int64_t slots_per_step = 0;
+    // graph of one step
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int bfail(fmmkmc_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BATCH_GUARD(b, ...)                                                      \
+    try {                                                                        \
+        __VA_ARGS__                                                              \
+    } catch (const HipError &e) {                                                \
+        return bfail(b, FMMKMC_EHIP, e.what);                                    \
+    } catch (const std::bad_alloc &) {                                           \
+        return bfail(b, FMMKMC_ENOMEM, "device or host allocation failed");      \
+    }
+
+void set_phase(Phase &ph, const std::vector<int64_t> &blocks_per_rep, hipStream_t s)
+{
+    const int R = (int)blocks_per_rep.size();
+    ph.base.assign(R + 1, 0);
+    for (int r = 0; r < R; ++r) ph.base[r + 1] = ph.base[r] + blocks_per_rep[r];
+    ph.blocks = ph.base[R];
+    dfree(ph.d);
+    ph.d = dalloc<int64_t>(R + 1);
+    upload(ph.d, ph.base.data(), R + 1, s);
+}
+
+void set_sweep_phase(fmmkmc_batch *b)
+{
+    std::vector<int64_t> nb(b->R);
+    for (int r = 0; r < b->R; ++r) nb[r] = (b->ctx[r]->M + b->sweep_block - 1) / b->sweep_block;
+    set_phase(b->sweep, nb, b->stream);
+}
+
+void set_slot_phase(fmmkmc_batch *b)
+{
+    std::vector<int64_t> nb(b->R);
+    for (int r = 0; r < b->R; ++r) nb[r] = (b->ctx[r]->N + b->slot_tc - 1) / b->slot_tc;
+    set_phase(b->slot, nb, b->stream);
+}
+
+// the phases of one step, in order
+void record_step(fmmkmc_batch *b)
+{
+    const hipStream_t s = b->stream;
+    const int R = b->R;
+    launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->p, b->mixed);
+    launch_b_slot(b->prof, s, b->reps, R, b->slot.d, b->slot.blocks, b->slot_tc);
+    launch_prof(b->prof, s, "b_count", k_b_count, dim3((unsigned)b->count.blocks), dim3(256), 0, b->reps, R,
+                b->count.d, b->counts);
+    launch_prof(b->prof, s, "b_select", k_b_select, dim3((unsigned)R), dim3(256), 0, b->reps, R, b->count.d,
+                b->counts, b->u, b->step, b->moves);
+    launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt);
+    launch_b_frow(b->prof, s, b->reps, R, b->moves, b->nt, b->K);
+    launch_b_sweep(b->prof, s, b->reps, R, b->sweep.d, b->sweep.blocks, b->p, b->moves, b->sweep_block);
+    launch_b_path(b->prof, s, b->reps, R, b->path.d, b->path.blocks, b->moves);
+    launch_b_book(b->prof, s, b->reps, R, b->moves);
+    launch_b_far(b->prof, s, b->reps, R, b->far.d, b->far.blocks, b->cheb_a.d, b->cheb_a.blocks, b->cheb_b.d,
+                 b->cheb_b.blocks, b->moves);
+    launch_prof(b->prof, s, "b_finish", k_b_finish, dim3(1), dim3(256), 0, (const MoveDev *)b->moves, R,
+                (const double *)b->acc, b->U, b->step, b->out_i, b->out_site, b->out_dU);
+}
+
+void drop_graph(fmmkmc_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+void capture(fmmkmc_batch *b)
+{
+    drop_graph(b);
+    const bool was = b->prof.on;
+    b->prof.on = false;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    record_step(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    b->prof.on = was;
+    HIPCHK(e);
+    b->graph = g;
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+}
+
+void ensure_steps(fmmkmc_batch *b, int n_steps)
+{
+    if (n_steps <= b->cap_steps) return;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const int cap = std::max(n_steps, 2 * b->cap_steps);
+    const size_t m = (size_t)cap * b->R;
+    dfree(b->u);
+    dfree(b->out_i);
+    dfree(b->out_site);
+    dfree(b->out_dU);
+    b->u = dalloc<double>(m);
+    b->out_i = dalloc<int64_t>(m);
+    b->out_site = dalloc<int64_t>(m);
+    b->out_dU = dalloc<double>(m);
+    b->cap_steps = cap;
+    drop_graph(b);  // the captured launches hold the old pointers
+}
+
+void release_batch(fmmkmc_batch *b)
+{
+    drop_graph(b);
+    dfree(b->reps);
+    dfree(b->moves);
+    dfree(b->null_moves);
+    dfree(b->acc);
+    dfree(b->U);
+    dfree(b->step);
+    dfree(b->counts);
+    for (auto &p : b->dU) dfree(p);
+    for (auto &p : b->mask) dfree(p);
+    dfree(b->u);
+    dfree(b->out_i);
+    dfree(b->out_site);
+    dfree(b->out_dU);
+    for (Phase *ph : {&b->site, &b->slot, &b->count, &b->sweep, &b->path, &b->far, &b->cheb_a, &b->cheb_b})
+        dfree(ph->d);
+    for (auto &pd : b->prof.pending) {
+        (void)hipEventDestroy(pd.a);
+        (void)hipEventDestroy(pd.b);
+    }
+    b->prof.pending.clear();
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    b->stream = nullptr;
+    b->own_stream = false;
+}
+
+RepDev make_rep(const fmmkmc_ctx *c, int K, double *dU, uint8_t *mask)
+{
+    RepDev d{};
+    d.g = make_geo(c);
+    d.M = c->M;
+    d.N = c->N;
+    d.L = c->L;
+    d.p = c->p;
+    d.nt = c->nt;
+    d.K = K;
+    d.s2 = c->s2 ? 1 : 0;
+    d.cap = c->cap;
+    d.kmul = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)K);
+    d.psi = c->psi_lv[c->L];
+    d.psi32 = c->prec == FMMKMC_MIXED ? c->psi32 : nullptr;
+    d.phi_lv = c->d_phi_ptrs;
+    d.x = c->x;
+    d.y = c->y;
+    d.z = c->z;
+    d.q = c->q;
+    d.cell = c->cell;
+    d.slot = c->slot;
+    d.site = c->site;
+    d.cnt = c->cell_cnt;
+    d.slots = c->cell_slots;
+    d.rank_of = c->rank_of;
+    d.site_charge = c->site_charge;
+    d.site_rank = c->site_rank;
+    d.qsite = c->qsite;
+    d.qsite32 = c->qsite32;
+    d.phisite = c->phisite;
+    d.order = c->order;
+    d.ijk_r = c->ijk_r;
+    d.q_r = c->q_r;
+    d.phi_r = c->phi_r;
+    d.F = c->bc == FMMKMC_PERIODIC ? c->F : nullptr;
+    d.offsets = c->d_offsets;
+    d.dU = dU;
+    d.mask = mask;
+    d.R = c->far.R;
+    d.GR = c->far.GR;
+    d.Kf = c->far.K;
+    d.H = c->far.H;
+    d.C = c->far.C;
+    d.A = c->far.A;
+    d.Bz = c->far.Bz;
+    d.Tax = c->far.Tax;
+    d.sigma = c->far.sigma;
+    d.cz = c->far.cz;
+    d.ncz = c->far.ncz;
+    return d;
+}
+
+// A context proposed with other hop offsets since the batch was built has a new
+// hop table: rebuild it for the batch's offsets and refresh the descriptors
+// (the step graph holds only the descriptor array, whose address is fixed).
+void sync_descriptors(fmmkmc_batch *b)
+{
+    bool changed = false;
+    for (int r = 0; r < b->R; ++r) {
+        fmmkmc_ctx *c = b->ctx[r];
+        if (c->F_offsets != b->offsets) {
+            const int rc = fmmkmc_propose_lattice(c, b->K, b->offsets.data(), b->dU[r], b->mask[r]);
+            if (rc != FMMKMC_OK) throw HipError{"proposal pass of replica " + std::to_string(r) + ": " + c->err};
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
+        const RepDev d = make_rep(c, b->K, b->dU[r], b->mask[r]);
+        if (std::memcmp(&d, &b->host_reps[r], sizeof(RepDev)) != 0) {
+            b->host_reps[r] = d;
+            changed = true;
+        }
+    }
+    if (changed) {
+        upload(b->reps, b->host_reps.data(), b->R, b->stream);
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+}
+
+// median of the timed launches of fn (events on the batch stream)
+template <typename Fn>
+float time_launches(fmmkmc_batch *b, int rounds, Fn fn)
+{
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    fn();  // warm-up
+    std::vector<float> t;
+    for (int k = 0; k < rounds; ++k) {
+        HIPCHK(hipEventRecord(e0, b->stream));
+        fn();
+        HIPCHK(hipEventRecord(e1, b->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *offsets, void *stream,
+                        fmmkmc_batch **out)
+{
+    if (!out) return FMMKMC_EINVAL;
+    *out = nullptr;
+    if (n < 1 || !ctx || !offsets || K < 1 || K > kMaxHops) return FMMKMC_EINVAL;
+    for (int k = 0; k < 3 * K; ++k)
+        if (offsets[k] < -1 || offsets[k] > 1) return FMMKMC_EINVAL;
+    for (int r = 0; r < n; ++r) {
+        const fmmkmc_ctx *c = ctx[r];
+        if (!c || c->lat_n <= 0) return FMMKMC_EINVAL;
+        if (!c->initialised) return FMMKMC_ESTATE;
+        if (c->p != ctx[0]->p || c->prec != ctx[0]->prec || c->device != ctx[0]->device) return FMMKMC_EINVAL;
+        if (c->N * (int64_t)K >= ((int64_t)1 << 32)) return FMMKMC_EINVAL;
+    }
+    if (f_row1_shm(ctx[0]->nt, K) > 64 * 1024) return FMMKMC_EINVAL;
+    fmmkmc_batch *b = new (std::nothrow) fmmkmc_batch();
+    if (!b) return FMMKMC_ENOMEM;
+    b->R = n;
+    b->p = ctx[0]->p;
+    b->nt = ctx[0]->nt;
+    b->K = K;
+    b->device = ctx[0]->device;
+    b->mixed = ctx[0]->prec == FMMKMC_MIXED;
+    b->stream = (hipStream_t)stream;
+    b->ctx.assign(ctx, ctx + n);
+    b->offsets.assign(offsets, offsets + 3 * K);
+    try {
+        HIPCHK(hipSetDevice(b->device));
+        if (!b->stream) {
+            // graphs cannot be captured on the legacy null stream: use a stream of our own
+            HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+            b->own_stream = true;
+        }
+        const hipStream_t s = b->stream;
+        std::vector<RepDev> reps(n);
+        std::vector<double> U(n);
+        b->dU.assign(n, nullptr);
+        b->mask.assign(n, nullptr);
+        for (int r = 0; r < n; ++r) {
+            fmmkmc_ctx *c = ctx[r];
+            b->dU[r] = dalloc<double>((size_t)c->N * K);
+            b->mask[r] = dalloc<uint8_t>((size_t)c->N * K);
+            // one ordinary proposal pass builds the context's hop table for these offsets
+            const int rc = fmmkmc_propose_lattice(c, K, offsets, b->dU[r], b->mask[r]);
+            if (rc != FMMKMC_OK) throw HipError{"proposal pass of replica " + std::to_string(r) + ": " + c->err};
+            HIPCHK(hipStreamSynchronize(c->stream));
+            reps[r] = make_rep(c, K, b->dU[r], b->mask[r]);
+            U[r] = c->U;
+            b->slots_per_step += c->N * K;
+        }
+        b->reps = dalloc<RepDev>(n);
+        upload(b->reps, reps.data(), n, s);
+        b->host_reps = reps;
+        b->moves = dalloc<MoveDev>(n);
+        b->null_moves = dalloc<MoveDev>(n);
+        b->acc = dalloc<double>((size_t)n * kMoveParts);
+        b->U = dalloc<double>(n);
+        upload(b->U, U.data(), n, s);
+        b->step = dalloc<int32_t>(1);
+        // phase block tables
+        std::vector<int64_t> nsite(n), ncount(n), npath(n), nfar(n), na(n), nb(n);
+        for (int r = 0; r < n; ++r) {
+            const fmmkmc_ctx *c = ctx[r];
+            const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+            const int q = c->p + 1;
+            nsite[r] = c->s2 ? (c->M + 127) / 128 : (ns + 255) / 256;
+            ncount[r] = (c->N * K + kSelChunk - 1) / kSelChunk;
+            npath[r] = ((int64_t)c->L * (q * (q + 1) / 2) + 255) / 256;
+            const bool per = c->bc == FMMKMC_PERIODIC;
+            nfar[r] = per ? (c->nt + c->far.ncz + 15) / 16 : 0;
+            na[r] = per ? ((int64_t)c->lat_n * q * q + 255) / 256 : 0;
+            nb[r] = per ? ((int64_t)c->lat_n * c->lat_n * q + 255) / 256 : 0;
+        }
+        set_phase(b->site, nsite, s);
+        set_phase(b->count, ncount, s);
+        set_phase(b->path, npath, s);
+        set_phase(b->far, nfar, s);
+        set_phase(b->cheb_a, na, s);
+        set_phase(b->cheb_b, nb, s);
+        set_slot_phase(b);
+        set_sweep_phase(b);
+        b->counts = dalloc<int32_t>(b->count.blocks);
+        hipLaunchKernelGGL(k_b_null_moves, dim3((n + 63) / 64), dim3(64), 0, s, (const RepDev *)b->reps, n,
+                           b->null_moves);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const HipError &e) {
+        create_error() = e.what;
+        release_batch(b);
+        delete b;
+        return FMMKMC_EHIP;
+    } catch (const std::bad_alloc &) {
+        create_error() = "device or host allocation failed";
+        release_batch(b);
+        delete b;
+        return FMMKMC_ENOMEM;
+    }
+    *out = b;
+    return FMMKMC_OK;
+}
+
+int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *moved, int64_t *site, double *dU)
+{
+    if (!b) return FMMKMC_EINVAL;
+    if (n_steps < 0 || (n_steps > 0 && !u)) return bfail(b, FMMKMC_EINVAL, "need n_steps >= 0 and u");
+    if (n_steps == 0) return FMMKMC_OK;
+    BATCH_GUARD(b, {
+        HIPCHK(hipSetDevice(b->device));
+        for (fmmkmc_ctx *c : b->ctx) HIPCHK(hipStreamSynchronize(c->stream));
+        sync_descriptors(b);
+        ensure_steps(b, n_steps);
+        const hipStream_t s = b->stream;
+        const size_t m = (size_t)n_steps * b->R;
+        HIPCHK(hipMemcpyAsync(b->u, u, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_b_set_step, dim3(1), dim3(64), 0, s, b->step, 0);
+        HIPCHK(hipGetLastError());
+        if (b->prof.on) {
+            for (int k = 0; k < n_steps; ++k) record_step(b);
+        } else {
+            if (!b->exec) capture(b);
+            for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->exec, s));
+        }
+        HIPCHK(hipGetLastError());
+        if (moved) HIPCHK(hipMemcpyAsync(moved, b->out_i, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, s));
+        if (site) HIPCHK(hipMemcpyAsync(site, b->out_site, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, s));
+        if (dU) HIPCHK(hipMemcpyAsync(dU, b->out_dU, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+        std::vector<double> U(b->R);
+        HIPCHK(hipMemcpyAsync(U.data(), b->U, sizeof(double) * b->R, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int r = 0; r < b->R; ++r) {
+            b->ctx[r]->U = U[r];
+            b->ctx[r]->dev_ahead = true;
+        }
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_batch_proposals(fmmkmc_batch *b, int r, double *dU, uint8_t *mask)
+{
+    if (!b) return FMMKMC_EINVAL;
+    if (r < 0 || r >= b->R || !dU) return bfail(b, FMMKMC_EINVAL, "bad replica or dU");
+    BATCH_GUARD(b, {
+        HIPCHK(hipSetDevice(b->device));
+        const size_t m = (size_t)b->ctx[r]->N * b->K;
+        HIPCHK(hipMemcpyAsync(dU, b->dU[r], sizeof(double) * m, hipMemcpyDeviceToDevice, b->stream));
+        if (mask) HIPCHK(hipMemcpyAsync(mask, b->mask[r], m, hipMemcpyDeviceToDevice, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_batch_tune(fmmkmc_batch *b, int rounds)
+{
+    if (!b) return FMMKMC_EINVAL;
+    if (rounds < 1) return bfail(b, FMMKMC_EINVAL, "rounds must be >= 1");
+    BATCH_GUARD(b, {
+        HIPCHK(hipSetDevice(b->device));
+        for (fmmkmc_ctx *c : b->ctx) HIPCHK(hipStreamSynchronize(c->stream));
+        const hipStream_t s = b->stream;
+        const bool was = b->prof.on;
+        b->prof.on = false;
+        // slot gather: charges per block (reads the site potentials of the current configuration)
+        launch_b_site(b->prof, s, b->reps, b->R, b->site.d, b->site.blocks, b->p, b->mixed);
+        float best = 0;
+        int best_tc = b->slot_tc;
+        for (int tc : {32, 64, 128}) {
+            b->slot_tc = tc;
+            set_slot_phase(b);
+            const float t = time_launches(b, rounds, [&] {
+                launch_b_slot(b->prof, s, b->reps, b->R, b->slot.d, b->slot.blocks, b->slot_tc);
+            });
+            if (tc == 32 || t < best) {
+                best = t;
+                best_tc = tc;
+            }
+        }
+        b->slot_tc = best_tc;
+        set_slot_phase(b);
+        // sweep: threads per block, timed with zero-charge moves (they leave every expansion unchanged)
+        int best_blk = b->sweep_block;
+        for (int blk : {128, 256}) {
+            b->sweep_block = blk;
+            set_sweep_phase(b);
+            const float t = time_launches(b, rounds, [&] {
+                launch_b_sweep(b->prof, s, b->reps, b->R, b->sweep.d, b->sweep.blocks, b->p, b->null_moves,
+                               b->sweep_block);
+            });
+            if (blk == 128 || t < best) {
+                best = t;
+                best_blk = blk;
+            }
+        }
+        b->sweep_block = best_blk;
+        set_sweep_phase(b);
+        HIPCHK(hipStreamSynchronize(s));
+        b->prof.on = was;
+        drop_graph(b);
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_batch_info(fmmkmc_batch *b, int64_t *slots_per_step, int *slot_tile, int *sweep_block)
+{
+    if (!b) return FMMKMC_EINVAL;
+    if (slots_per_step) *slots_per_step = b->slots_per_step;
+    if (slot_tile) *slot_tile = b->slot_tc;
+    if (sweep_block) *sweep_block = b->sweep_block;
+    return FMMKMC_OK;
+}
+
+int fmmkmc_batch_set_profiling(fmmkmc_batch *b, int on)
+{
+    if (!b) return FMMKMC_EINVAL;
+    BATCH_GUARD(b, {
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->prof.resolve();
+        b->prof.total.clear();
+        b->prof.on = on != 0;
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_batch_kernel_time(fmmkmc_batch *b, const char *name, double *ms, int64_t *launches)
+{
+    if (!b || !name) return FMMKMC_EINVAL;
+    b->prof.resolve();
+    auto it = b->prof.total.find(name);
+    if (ms) *ms = it == b->prof.total.end() ? 0.0 : it->second.first;
+    if (launches) *launches = it == b->prof.total.end() ? 0 : it->second.second;
+    return FMMKMC_OK;
+}
+
+const char *fmmkmc_batch_last_error(fmmkmc_batch *b)
+{
+    if (!b) return create_error().c_str();
+    return b->err.c_str();
+}
+
+int fmmkmc_batch_destroy(fmmkmc_batch *b)
+{
+    if (!b) return FMMKMC_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    release_batch(b);
+    delete b;
+    return FMMKMC_OK;
+}
+
+}  // extern "C"

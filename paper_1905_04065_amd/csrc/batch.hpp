@@ -1,0 +1,93 @@
+// Replica descriptors for the batched kernels: many independent lattice
+// systems (KMC replicas of uneven sizes) advanced by one launch per phase.
+// Each replica is an ordinary context; RepDev is a device-resident view of its
+// arrays, and a batched kernel maps each block to (replica, local block)
+// through a prefix table of per-replica block counts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace fmmkmc {
+
+struct RepDev {
+    Geo g;
+    int64_t M, N;
+    int L, p, nt, K, s2, cap;
+    uint32_t kmul;  // floor(2^32 / K)
+    // fine-level local expansions (coefficient-major) and the level pointers of the multipoles
+    double *psi;
+    float *psi32;
+    double *const *phi_lv;
+    // charges
+    double *x, *y, *z, *q;
+    int32_t *cell, *slot, *site, *cnt, *slots, *rank_of;
+    // site tables (site order)
+    int32_t *site_charge, *site_rank;
+    double *qsite;
+    float *qsite32;
+    double *phisite;
+    // by rank
+    int32_t *order, *ijk_r;
+    double *q_r, *phi_r, *F;
+    // hops and the proposal output of this replica ([charge][hop])
+    int32_t *offsets;
+    double *dU;
+    uint8_t *mask;
+    // far field
+    double *R, *GR, *Kf, *H, *C, *A, *Bz, *Tax, *sigma;
+    int32_t *cz;
+    int ncz;
+};
+
+// the move a replica makes in the current step (written by the selection kernel)
+struct MoveDev {
+    int valid;         // 0: no valid slot, the replica does not move
+    int64_t i;         // charge
+    int64_t slot;      // selected slot i * K + k
+    int64_t new_site;  // lattice order
+    int32_t rank;
+    double t[3];       // new position
+    Move mv;
+    Book bk;
+};
+
+// replica owning block b of a batched launch: base[r] <= b < base[r + 1]
+__device__ inline int find_rep(const int64_t *__restrict__ base, int R, int64_t b)
+{
+    int lo = 0, hi = R;  // invariant: base[lo] <= b < base[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// launchers of the batched kernels (grids: one block range per replica)
+void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                   int p, bool mixed);
+void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                   int tc);
+void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, double *acc,
+                      int nt);
+size_t f_row1_shm(int nt, int K);
+void launch_b_frow(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, int nt, int K);
+void launch_b_sweep(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                    int p, const MoveDev *moves, int block);
+void launch_b_path(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                   const MoveDev *moves);
+void launch_b_book(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves);
+void launch_b_far(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base_far,
+                  int64_t blocks_far, const int64_t *base_a, int64_t blocks_a, const int64_t *base_b,
+                  int64_t blocks_b, const MoveDev *moves);
+
+}  // namespace fmmkmc
+
+// host mirrors of a context after batched steps (api.hip)
+void refresh_mirrors(fmmkmc_ctx *c);

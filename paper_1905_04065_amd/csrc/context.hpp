@@ -68,6 +68,7 @@ struct fmmkmc_ctx {
     int64_t M = 0;        // fine cells
     bool s2 = false;      // lattice with 2x2x2 sites per fine cell
     bool initialised = false;
+    bool dev_ahead = false;  // batched steps moved charges: host mirrors are stale
     double U = 0;
     std::string err;
     fmmkmc::Profiler prof;
@@ -82,6 +83,7 @@ struct fmmkmc_ctx {
     // gathers); by rank: charge index, charge, packed site coordinates
     // (i<<20 | j<<10 | k); the hop table F is stored by rank as well
     int32_t *order = nullptr;
+    int32_t *rank_of = nullptr;      // lattice: rank of each charge (device copy of hrank)
     double *q_r = nullptr;
     int32_t *ijk_r = nullptr;
     double *qsite = nullptr;         // 2x2x2 lattice: charge per site, cell-major order

@@ -12,21 +12,28 @@ namespace fmmkmc {
 
 // Launch on stream s; with profiling on, bracket with HIP events on that stream.
 template <typename Kern, typename... Args>
-inline void launch_on(fmmkmc_ctx *c, hipStream_t s, const char *name, Kern k, dim3 grid, dim3 block, size_t shm,
-                      Args... args)
+inline void launch_prof(Profiler &pr, hipStream_t s, const char *name, Kern k, dim3 grid, dim3 block, size_t shm,
+                        Args... args)
 {
     if (grid.x == 0 || grid.y == 0 || grid.z == 0) return;
     hipEvent_t a = nullptr, b = nullptr;
-    if (c->prof.on) {
+    if (pr.on) {
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
         (void)hipEventRecord(a, s);
     }
     hipLaunchKernelGGL(k, grid, block, shm, s, args...);
-    if (c->prof.on) {
+    if (pr.on) {
         (void)hipEventRecord(b, s);
-        c->prof.pending.push_back({name, a, b});
+        pr.pending.push_back({name, a, b});
     }
+}
+
+template <typename Kern, typename... Args>
+inline void launch_on(fmmkmc_ctx *c, hipStream_t s, const char *name, Kern k, dim3 grid, dim3 block, size_t shm,
+                      Args... args)
+{
+    launch_prof(c->prof, s, name, k, grid, block, shm, args...);
 }
 
 // Launch on the context's stream.
@@ -41,6 +48,31 @@ inline void launch(fmmkmc_ctx *c, const char *name, Kern k, dim3 grid, dim3 bloc
 {
     launch_shm(c, name, k, grid, block, 0, args...);
 }
+
+// an accepted move as the commit kernels see it
+struct Move {
+    double ox, oy, oz;   // old position (in the box)
+    double nx, ny, nz;   // new position (in the box)
+    double q;
+    int ogx, ogy, ogz;   // fine-cell coordinates of the old position
+    int ngx, ngy, ngz;   // and of the new one
+};
+
+// bookkeeping of an accepted move: positions, cell slots, site tables
+struct Book {
+    int64_t i;
+    double nx, ny, nz, q;
+    int64_t old_cell, new_cell;
+    int old_slot, new_slot;
+    int moved_j;          // charge moved into old_slot (-1 if none)
+    int old_cnt, new_cnt; // counts after the move
+    int64_t new_site;     // lattice order, -1 without a lattice
+    int64_t old_sord, new_sord;  // site order (cell-major on the 2x2x2 path)
+    int32_t new_ijk;
+    int32_t rank;
+    int s2;               // per-site charges are kept (2x2x2 path)
+    int same_cell;        // the move stays inside one fine cell: slots unchanged
+};
 
 struct CommitArgs {
     int64_t i;

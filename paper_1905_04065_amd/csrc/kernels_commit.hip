@@ -11,17 +11,11 @@
 // Path: the multipole expansions of the old and new cell of the moved charge
 // on every level change by -/+ its P2M; level 1 is the box multipole K of the
 // far field.
+#include "batch.hpp"
 #include "kernels.hpp"
 
 namespace fmmkmc {
 
-struct Move {
-    double ox, oy, oz;   // old position (in the box)
-    double nx, ny, nz;   // new position (in the box)
-    double q;
-    int ogx, ogy, ogz;   // fine-cell coordinates of the old position
-    int ngx, ngy, ngz;   // and of the new one
-};
 
 // Columns m of the local expansion are split into groups whose coefficients
 // fit in registers (at most kSweepBudget doubles); one lane per (cell, group).
@@ -216,10 +210,11 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, int64_t M, Move mv, double
 // P2M of -q at the old and +q at the new position into the cells containing
 // them on every level; one lane per (level, n, m >= 0) runs the regular
 // recurrence to R_n^m itself, for both endpoints in turn.
-__global__ void k_path(Geo g, int L, int p, Move mv, double *const *__restrict__ phi)
+__device__ __forceinline__ void path_body(int64_t blk, Geo g, int L, int p, const Move &mv,
+                                          double *const *__restrict__ phi)
 {
     const int per = (p + 1) * (p + 2) / 2;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = (int)(blk * blockDim.x + threadIdx.x);
     if (t >= L * per) return;
     const int l = 1 + t / per;
     int r = t % per, n = 0;
@@ -270,27 +265,18 @@ __global__ void k_path(Geo g, int L, int p, Move mv, double *const *__restrict__
     }
 }
 
-// position, cell-slot and site bookkeeping of the moved charge
-struct Book {
-    int64_t i;
-    double nx, ny, nz, q;
-    int64_t old_cell, new_cell;
-    int old_slot, new_slot;
-    int moved_j;          // charge moved into old_slot (-1 if none)
-    int old_cnt, new_cnt; // counts after the move
-    int64_t new_site;     // lattice order, -1 without a lattice
-    int64_t old_sord, new_sord;  // site order (cell-major on the 2x2x2 path)
-    int32_t new_ijk;
-    int32_t rank;
-    int s2;               // per-site charges are kept (2x2x2 path)
-    int same_cell;        // the move stays inside one fine cell: slots unchanged
-};
-
-__global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, int32_t *slot, int32_t *site,
-                       int32_t *ijk_r, int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge,
-                       int32_t *site_rank, double *qsite, float *qsite32)
+__global__ void k_path(Geo g, int L, int p, Move mv, double *const *__restrict__ phi)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    path_body(blockIdx.x, g, L, p, mv, phi);
+}
+
+// position, cell-slot and site bookkeeping of the moved charge
+
+__device__ __forceinline__ void book_body(const Book &b, double *x, double *y, double *z, int32_t *cell,
+                                          int32_t *slot, int32_t *site, int32_t *ijk_r, int32_t *cnt,
+                                          int32_t *slots, int cap, int32_t *site_charge, int32_t *site_rank,
+                                          double *qsite, float *qsite32)
+{
     x[b.i] = b.nx;
     y[b.i] = b.ny;
     z[b.i] = b.nz;
@@ -323,6 +309,14 @@ __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, i
             }
         }
     }
+}
+
+__global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, int32_t *slot, int32_t *site,
+                       int32_t *ijk_r, int32_t *cnt, int32_t *slots, int cap, int32_t *site_charge,
+                       int32_t *site_rank, double *qsite, float *qsite32)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    book_body(b, x, y, z, cell, slot, site, ijk_r, cnt, slots, cap, site_charge, site_rank, qsite, qsite32);
 }
 
 void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
@@ -368,6 +362,60 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
     b.same_cell = a.old_cell == a.new_cell ? 1 : 0;
     launch(c, "book", k_book, dim3(1), dim3(64), b, c->x, c->y, c->z, c->cell, c->slot, c->site, c->ijk_r,
            c->cell_cnt, c->cell_slots, c->cap, c->site_charge, c->site_rank, c->qsite, c->qsite32);
+}
+
+
+// ---- batched replicas ---------------------------------------------------------
+
+template <int P>
+__global__ __launch_bounds__(256) void k_b_sweep(const RepDev *__restrict__ reps, int R,
+                                                 const int64_t *__restrict__ base, const MoveDev *__restrict__ moves)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    const MoveDev &mv = moves[r];
+    if (!mv.valid) return;
+    const RepDev &d = reps[r];
+    const int64_t cell = (blockIdx.x - base[r]) * blockDim.x + threadIdx.x;
+    if (cell >= d.M) return;
+    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, mv.mv, d.psi, d.psi32);
+}
+
+__global__ void k_b_path(const RepDev *__restrict__ reps, int R, const int64_t *__restrict__ base,
+                         const MoveDev *__restrict__ moves)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    const MoveDev &mv = moves[r];
+    if (!mv.valid) return;
+    const RepDev &d = reps[r];
+    path_body(blockIdx.x - base[r], d.g, d.L, d.p, mv.mv, d.phi_lv);
+}
+
+// one lane per replica
+__global__ void k_b_book(const RepDev *__restrict__ reps, int R, const MoveDev *__restrict__ moves)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R || !moves[r].valid) return;
+    const RepDev &d = reps[r];
+    book_body(moves[r].bk, d.x, d.y, d.z, d.cell, d.slot, d.site, d.ijk_r, d.cnt, d.slots, d.cap, d.site_charge,
+              d.site_rank, d.qsite, d.qsite32);
+}
+
+void launch_b_sweep(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                    int p, const MoveDev *moves, int block)
+{
+    FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_sweep", k_b_sweep<P_>, dim3((unsigned)blocks, n_groups(P_)),
+                                     dim3(block), 0, reps, R, base, moves));
+}
+
+void launch_b_path(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                   const MoveDev *moves)
+{
+    launch_prof(pr, st, "b_path", k_b_path, dim3((unsigned)blocks), dim3(256), 0, reps, R, base, moves);
+}
+
+void launch_b_book(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves)
+{
+    launch_prof(pr, st, "b_book", k_b_book, dim3((unsigned)((R + 63) / 64)), dim3(64), 0, reps, R, moves);
 }
 
 }  // namespace fmmkmc

@@ -16,6 +16,7 @@
 // and the per-slot kernel only gathers; the hop-dependent but
 // charge-configuration-independent terms (self terms and the quadratic far-field
 // term) are tabulated per charge and hop in F.
+#include "batch.hpp"
 #include "kernels.hpp"
 
 namespace fmmkmc {
@@ -132,7 +133,7 @@ __device__ inline double far_site(int n, int i, int j, int k, const double *__re
 // one lane per lattice site (lattice order); the occupant of a site, if any,
 // is left out of its own potential, so occupied sites get phi_occ.
 template <int P, bool MIXED>
-__global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, const double *__restrict__ psi,
+__device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
                                                           const float *__restrict__ psi32,
                                                           const double *__restrict__ Bz,
                                                           const double *__restrict__ Tax,
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
                                                           const int32_t *__restrict__ site_rank,
                                                           double *__restrict__ phisite, double *__restrict__ phi_r)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = blk * blockDim.x + threadIdx.x;
     const int n = g.n;
     if (s >= (int64_t)n * n * n) return;
     const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
@@ -193,6 +194,23 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
     const int32_t rk = site_rank[s];
     if (rk >= 0) phi_r[rk] = phi;
     phisite[s] = rk >= 0 ? __builtin_nan("") : phi;
+}
+
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, const double *__restrict__ psi,
+                                                          const float *__restrict__ psi32,
+                                                          const double *__restrict__ Bz,
+                                                          const double *__restrict__ Tax,
+                                                          const double *__restrict__ x, const double *__restrict__ y,
+                                                          const double *__restrict__ z, const double *__restrict__ q,
+                                                          const int32_t *__restrict__ cnt,
+                                                          const int32_t *__restrict__ slots,
+                                                          const int32_t *__restrict__ site_charge,
+                                                          const int32_t *__restrict__ site_rank,
+                                                          double *__restrict__ phisite, double *__restrict__ phi_r)
+{
+    site_general_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, Bz, Tax, x, y, z, q, cnt, slots, site_charge,
+                                site_rank, phisite, phi_r);
 }
 
 // ---- lattice with 2 x 2 x 2 sites per fine cell ----------------------------
@@ -287,13 +305,12 @@ __host__ __device__ constexpr int s2_d2(int u, int nb, int v)
 constexpr int S2_CELLS = 128;  // cells per block
 
 template <int P, bool MIXED>
-__global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const double *__restrict__ psi,
-                                                     const float *__restrict__ psi32,
-                                                     const double *__restrict__ qsite,
-                                                     const float *__restrict__ qsite32,
-                                                     const int32_t *__restrict__ site_rank,
-                                                     const double *__restrict__ Bz, const double *__restrict__ Tax,
-                                                     double *__restrict__ phisite, double *__restrict__ phi_r)
+__device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
+                                             const float *__restrict__ psi32, const double *__restrict__ qsite,
+                                             const float *__restrict__ qsite32,
+                                             const int32_t *__restrict__ site_rank, const double *__restrict__ Bz,
+                                             const double *__restrict__ Tax, double *__restrict__ phisite,
+                                             double *__restrict__ phi_r)
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     constexpr S2Weights<P> W{};
@@ -310,7 +327,7 @@ __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const dou
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int lc = (wave & 1) * 64 + (threadIdx.x & 63);
-    const int64_t c0 = (int64_t)blockIdx.x * S2_CELLS, cell = c0 + lc;
+    const int64_t c0 = blk * S2_CELLS, cell = c0 + lc;
     const int nc = g.nc;
     if (wave < 2) {
         if (cell < M) {
@@ -443,6 +460,18 @@ __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const dou
     }
 }
 
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const double *__restrict__ psi,
+                                                     const float *__restrict__ psi32,
+                                                     const double *__restrict__ qsite,
+                                                     const float *__restrict__ qsite32,
+                                                     const int32_t *__restrict__ site_rank,
+                                                     const double *__restrict__ Bz, const double *__restrict__ Tax,
+                                                     double *__restrict__ phisite, double *__restrict__ phi_r)
+{
+    site_s2_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, qsite, qsite32, site_rank, Bz, Tax, phisite, phi_r);
+}
+
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
 {
     const bool mixed = c->prec == FMMKMC_MIXED;
@@ -480,23 +509,22 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
 // slot needs a single gather: phi at the target site (NaN if occupied).  The
 // F table is stored by rank, so its reads are contiguous; dU and mask go to
 // the caller's [charge][hop] layout (K contiguous entries per charge).
-constexpr int TCH = 64;   // charges per block
+constexpr int TCH = 64;   // charges per block (the single-context default)
 constexpr int SLOTB = 4;  // slots per lane whose loads are in flight together
 
-__global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, uint32_t K, uint32_t kmul,
-                                                      const int32_t *__restrict__ offs,
-                                                      const int32_t *__restrict__ order,
-                                                      const int32_t *__restrict__ ijk_r, const double *__restrict__ q_r,
-                                                      const double *__restrict__ phi_r,
-                                                      const double *__restrict__ phisite,
-                                                      const double *__restrict__ F, int s2,
-                                                      double *__restrict__ dU, uint8_t *__restrict__ mask)
+template <int TC>
+__device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_t K, uint32_t kmul,
+                                          const int32_t *__restrict__ offs, const int32_t *__restrict__ order,
+                                          const int32_t *__restrict__ ijk_r, const double *__restrict__ q_r,
+                                          const double *__restrict__ phi_r, const double *__restrict__ phisite,
+                                          const double *__restrict__ F, int s2, double *__restrict__ dU,
+                                          uint8_t *__restrict__ mask)
 {
     __shared__ int32_t soff[3 * kMaxHops];
-    __shared__ int32_t s_ijk[TCH], s_ord[TCH];
-    __shared__ double s_q[TCH], s_phi[TCH];
-    const int64_t r0 = (int64_t)blockIdx.x * TCH;
-    const int nloc = (int)((N - r0) < TCH ? (N - r0) : TCH);
+    __shared__ int32_t s_ijk[TC], s_ord[TC];
+    __shared__ double s_q[TC], s_phi[TC];
+    const int64_t r0 = blk * TC;
+    const int nloc = (int)((N - r0) < TC ? (N - r0) : TC);
     for (uint32_t e = threadIdx.x; e < 3 * K; e += blockDim.x) soff[e] = offs[e];
     if ((int)threadIdx.x < nloc) {
         const int64_t r = r0 + threadIdx.x;
@@ -564,6 +592,18 @@ __global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, uint32_t
             if (mask) mask[o] = valid ? 1 : 0;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, uint32_t K, uint32_t kmul,
+                                                      const int32_t *__restrict__ offs,
+                                                      const int32_t *__restrict__ order,
+                                                      const int32_t *__restrict__ ijk_r, const double *__restrict__ q_r,
+                                                      const double *__restrict__ phi_r,
+                                                      const double *__restrict__ phisite,
+                                                      const double *__restrict__ F, int s2,
+                                                      double *__restrict__ dU, uint8_t *__restrict__ mask)
+{
+    slot_body<TCH>(blockIdx.x, g, N, K, kmul, offs, order, ijk_r, q_r, phi_r, phisite, F, s2, dU, mask);
 }
 
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask)
@@ -669,9 +709,9 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
 
 // F row of one charge (after an accept): K target harmonics in LDS, w = R K1(r)
 // with each output split over 16 lanes, then one dot product per hop.
-__global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, int64_t s_site, int K,
-                                                const int32_t *__restrict__ offs, const double *__restrict__ R,
-                                                const double *__restrict__ sigma, double *__restrict__ F)
+__device__ __forceinline__ void f_row1_body(Geo g, int p, int64_t rank, int64_t s_site, int K,
+                                            const int32_t *__restrict__ offs, const double *__restrict__ R,
+                                            const double *__restrict__ sigma, double *__restrict__ F)
 {
     const int nt = nterms(p);
     extern __shared__ double sm[];
@@ -742,6 +782,13 @@ __global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, int6
     }
 }
 
+__global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, int64_t s_site, int K,
+                                                const int32_t *__restrict__ offs, const double *__restrict__ R,
+                                                const double *__restrict__ sigma, double *__restrict__ F)
+{
+    f_row1_body(g, p, rank, s_site, K, offs, R, sigma, F);
+}
+
 void launch_sigma(fmmkmc_ctx *c, const Geo &g)
 {
     const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
@@ -786,12 +833,13 @@ __device__ inline double block_sum(double v, double *red)
 //   1: q times the near field at t,  2: minus q times the near field at r
 //      (the moving charge itself left out)
 //   3: the far-field change q dW.H + 1/2 q dW^T R dK (periodic; else 0)
-__global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_t i, double tx, double ty, double tz,
-                                                 const double *__restrict__ psi, const double *__restrict__ x,
-                                                 const double *__restrict__ y, const double *__restrict__ z,
-                                                 const double *__restrict__ q, const int32_t *__restrict__ cnt,
-                                                 const int32_t *__restrict__ slots, const double *__restrict__ R,
-                                                 const double *__restrict__ H, double *__restrict__ out)
+__device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t M, int64_t i, double tx, double ty,
+                                             double tz, const double *__restrict__ psi,
+                                             const double *__restrict__ x, const double *__restrict__ y,
+                                             const double *__restrict__ z, const double *__restrict__ q,
+                                             const int32_t *__restrict__ cnt, const int32_t *__restrict__ slots,
+                                             const double *__restrict__ R, const double *__restrict__ H,
+                                             double *__restrict__ out)
 {
     const int nt = nterms(p);
     extern __shared__ double sm[];
@@ -804,7 +852,6 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
     const int tcx = fine_coord(tx, g.w, g.nc), tcy = fine_coord(ty, g.w, g.nc), tcz = fine_coord(tz, g.w, g.nc);
     const int rcx = fine_coord(rx, g.w, g.nc), rcy = fine_coord(ry, g.w, g.nc), rcz = fine_coord(rz, g.w, g.nc);
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    const int part_id = blockIdx.x;
     double part = 0.0;
     if (part_id == 0) {
         // harmonics at t and r relative to their fine cells, one lane per column m
@@ -913,6 +960,16 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
     }
     const double tot = block_sum(part, red);
     if (threadIdx.x == 0) out[part_id] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_t i, double tx, double ty, double tz,
+                                                 const double *__restrict__ psi, const double *__restrict__ x,
+                                                 const double *__restrict__ y, const double *__restrict__ z,
+                                                 const double *__restrict__ q, const int32_t *__restrict__ cnt,
+                                                 const int32_t *__restrict__ slots, const double *__restrict__ R,
+                                                 const double *__restrict__ H, double *__restrict__ out)
+{
+    move_dU_body(blockIdx.x, g, p, M, i, tx, ty, tz, psi, x, y, z, q, cnt, slots, R, H, out);
 }
 
 void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out)
@@ -1119,6 +1176,94 @@ void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int n
 {
     launch(c, "dats_select", k_dats_select, dim3((unsigned)((N * K + 255) / 256)), dim3(256), N, K, C, ntypes, T, Mk,
            use, c->flags);
+}
+
+
+// ---- batched replicas: one launch per phase over every replica ----------------
+// base[r] .. base[r+1] are replica r's blocks; all replicas share p and precision.
+
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_b_site(const RepDev *__restrict__ reps, int R,
+                                                const int64_t *__restrict__ base)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    const RepDev &d = reps[r];
+    const int64_t blk = blockIdx.x - base[r];
+    if (d.s2)
+        site_s2_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
+                               d.phisite, d.phi_r);
+    else
+        site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.x, d.y, d.z, d.q, d.cnt,
+                                    d.slots, d.site_charge, d.site_rank, d.phisite, d.phi_r);
+}
+
+template <int TC>
+__global__ __launch_bounds__(256) void k_b_slot(const RepDev *__restrict__ reps, int R,
+                                                const int64_t *__restrict__ base)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    const RepDev &d = reps[r];
+    slot_body<TC>(blockIdx.x - base[r], d.g, d.N, (uint32_t)d.K, d.kmul, d.offsets, d.order, d.ijk_r, d.q_r,
+                  d.phi_r, d.phisite, d.F, d.s2, d.dU, d.mask);
+}
+
+// kMoveParts blocks per replica
+__global__ __launch_bounds__(256) void k_b_move_dU(const RepDev *__restrict__ reps,
+                                                   const MoveDev *__restrict__ moves, double *__restrict__ acc)
+{
+    const int r = blockIdx.x / kMoveParts, part = blockIdx.x % kMoveParts;
+    const MoveDev &mv = moves[r];
+    if (!mv.valid) return;
+    const RepDev &d = reps[r];
+    move_dU_body(part, d.g, d.p, d.M, mv.i, mv.t[0], mv.t[1], mv.t[2], d.psi, d.x, d.y, d.z, d.q, d.cnt, d.slots,
+                 d.R, d.H, acc + (int64_t)r * kMoveParts);
+}
+
+// the moved charge's F row, one block per replica (periodic replicas)
+__global__ __launch_bounds__(256) void k_b_frow(const RepDev *__restrict__ reps, const MoveDev *__restrict__ moves)
+{
+    const int r = blockIdx.x;
+    const MoveDev &mv = moves[r];
+    const RepDev &d = reps[r];
+    if (!mv.valid || !d.F) return;
+    f_row1_body(d.g, d.p, mv.rank, mv.new_site, d.K, d.offsets, d.R, d.sigma, d.F);
+}
+
+void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                   int p, bool mixed)
+{
+    if (mixed) {
+        FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site<P_, true>, dim3((unsigned)blocks), dim3(256), 0,
+                                       reps, R, base));
+    } else {
+        FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site<P_, false>, dim3((unsigned)blocks), dim3(256), 0,
+                                       reps, R, base));
+    }
+}
+
+void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                   int tc)
+{
+    if (tc == 32)
+        launch_prof(pr, st, "b_slot", k_b_slot<32>, dim3((unsigned)blocks), dim3(256), 0, reps, R, base);
+    else if (tc == 128)
+        launch_prof(pr, st, "b_slot", k_b_slot<128>, dim3((unsigned)blocks), dim3(256), 0, reps, R, base);
+    else
+        launch_prof(pr, st, "b_slot", k_b_slot<64>, dim3((unsigned)blocks), dim3(256), 0, reps, R, base);
+}
+
+void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, double *acc,
+                      int nt)
+{
+    const size_t shm = sizeof(double) * (4 * nt + 256);
+    launch_prof(pr, st, "b_move_dU", k_b_move_dU, dim3((unsigned)(R * kMoveParts)), dim3(256), shm, reps, moves, acc);
+}
+
+size_t f_row1_shm(int nt, int K) { return sizeof(double) * ((size_t)(K + 3) * nt + 256 + 27 * (size_t)K); }
+
+void launch_b_frow(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, int nt, int K)
+{
+    launch_prof(pr, st, "b_frow", k_b_frow, dim3((unsigned)R), dim3(256), f_row1_shm(nt, K), reps, moves);
 }
 
 }  // namespace fmmkmc

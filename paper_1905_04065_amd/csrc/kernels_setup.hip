@@ -8,6 +8,7 @@
 //         form for fast evaluation at lattice sites.
 // Expansions are stored coefficient-major, [k][cell], so a wavefront of
 // consecutive cells reads each coefficient row with one coalesced access.
+#include "batch.hpp"
 #include "kernels.hpp"
 
 namespace fmmkmc {
@@ -234,14 +235,14 @@ void launch_downward(fmmkmc_ctx *c)
 // H = R K and the nonzero Chebyshev coefficients C = (G R) K.  Rows are split
 // over 16 lanes each (partial sums reduced in LDS); both operators are stored
 // column-major ([n][row]).
-__global__ __launch_bounds__(256) void k_far_refresh(int nt, int ncz, const double *__restrict__ R,
-                                                     const double *__restrict__ GR, const int32_t *__restrict__ cz,
-                                                     const double *__restrict__ K, double *__restrict__ H,
-                                                     double *__restrict__ C)
+__device__ __forceinline__ void far_refresh_body(int64_t blk, int nt, int ncz, const double *__restrict__ R,
+                                                 const double *__restrict__ GR, const int32_t *__restrict__ cz,
+                                                 const double *__restrict__ K, double *__restrict__ H,
+                                                 double *__restrict__ C)
 {
     __shared__ double part[16][17];
     const int lr = threadIdx.x & 15, ls = threadIdx.x >> 4;
-    const int row = blockIdx.x * 16 + lr;
+    const int row = (int)blk * 16 + lr;
     double acc = 0.0;
     if (row < nt + ncz) {
         const bool isH = row < nt;
@@ -262,14 +263,22 @@ __global__ __launch_bounds__(256) void k_far_refresh(int nt, int ncz, const doub
     }
 }
 
+__global__ __launch_bounds__(256) void k_far_refresh(int nt, int ncz, const double *__restrict__ R,
+                                                     const double *__restrict__ GR, const int32_t *__restrict__ cz,
+                                                     const double *__restrict__ K, double *__restrict__ H,
+                                                     double *__restrict__ C)
+{
+    far_refresh_body(blockIdx.x, nt, ncz, R, GR, cz, K, H, C);
+}
+
 // Chebyshev columns in two passes:
 //   A[i][b][c]  = sum_{a <= p-b-c} C[a][b][c] T_a(xi_i)
 //   Bz[i][j][c] = sum_{b <= p-c}   A[i][b][c] T_b(xi_j)
-__global__ __launch_bounds__(256) void k_cheb_a(int p, int n, const double *__restrict__ C,
-                                                const double *__restrict__ Tax, double *__restrict__ A)
+__device__ __forceinline__ void cheb_a_body(int64_t blk, int p, int n, const double *__restrict__ C,
+                                            const double *__restrict__ Tax, double *__restrict__ A)
 {
     const int q = p + 1;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = blk * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * q * q) return;
     const int cc = (int)(t % q), b = (int)((t / q) % q), i = (int)(t / (q * q));
     double acc = 0.0;
@@ -277,11 +286,17 @@ __global__ __launch_bounds__(256) void k_cheb_a(int p, int n, const double *__re
     A[t] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_cheb_b(int p, int n, const double *__restrict__ A,
-                                                const double *__restrict__ Tax, double *__restrict__ Bz)
+__global__ __launch_bounds__(256) void k_cheb_a(int p, int n, const double *__restrict__ C,
+                                                const double *__restrict__ Tax, double *__restrict__ A)
+{
+    cheb_a_body(blockIdx.x, p, n, C, Tax, A);
+}
+
+__device__ __forceinline__ void cheb_b_body(int64_t blk, int p, int n, const double *__restrict__ A,
+                                            const double *__restrict__ Tax, double *__restrict__ Bz)
 {
     const int q = p + 1;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = blk * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * n * q) return;
     const int cc = (int)(t % q);
     const int64_t ij = t / q;
@@ -289,6 +304,12 @@ __global__ __launch_bounds__(256) void k_cheb_b(int p, int n, const double *__re
     double acc = 0.0;
     for (int b = 0; b + cc <= p; ++b) acc += A[((int64_t)i * q + b) * q + cc] * Tax[j * q + b];
     Bz[t] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_cheb_b(int p, int n, const double *__restrict__ A,
+                                                const double *__restrict__ Tax, double *__restrict__ Bz)
+{
+    cheb_b_body(blockIdx.x, p, n, A, Tax, Bz);
 }
 
 void launch_far_refresh(fmmkmc_ctx *c)
@@ -318,6 +339,47 @@ void launch_shadow(fmmkmc_ctx *c)
     const int64_t tot = (int64_t)c->nt * c->M;
     launch(c, "shadow_f32", k_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), tot, c->psi_lv[c->L],
            c->psi32);
+}
+
+
+// ---- batched replicas: far-field refresh of the replicas that moved -----------
+
+__global__ __launch_bounds__(256) void k_b_far_refresh(const RepDev *__restrict__ reps, int R,
+                                                       const int64_t *__restrict__ base,
+                                                       const MoveDev *__restrict__ moves)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    if (!moves[r].valid) return;
+    const RepDev &d = reps[r];
+    far_refresh_body(blockIdx.x - base[r], d.nt, d.ncz, d.R, d.GR, d.cz, d.Kf, d.H, d.C);
+}
+
+__global__ __launch_bounds__(256) void k_b_cheb_a(const RepDev *__restrict__ reps, int R,
+                                                  const int64_t *__restrict__ base, const MoveDev *__restrict__ moves)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    if (!moves[r].valid) return;
+    const RepDev &d = reps[r];
+    cheb_a_body(blockIdx.x - base[r], d.p, d.g.n, d.C, d.Tax, d.A);
+}
+
+__global__ __launch_bounds__(256) void k_b_cheb_b(const RepDev *__restrict__ reps, int R,
+                                                  const int64_t *__restrict__ base, const MoveDev *__restrict__ moves)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    if (!moves[r].valid) return;
+    const RepDev &d = reps[r];
+    cheb_b_body(blockIdx.x - base[r], d.p, d.g.n, d.A, d.Tax, d.Bz);
+}
+
+void launch_b_far(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base_far,
+                  int64_t blocks_far, const int64_t *base_a, int64_t blocks_a, const int64_t *base_b,
+                  int64_t blocks_b, const MoveDev *moves)
+{
+    launch_prof(pr, st, "b_far_refresh", k_b_far_refresh, dim3((unsigned)blocks_far), dim3(256), 0, reps, R,
+                base_far, moves);
+    launch_prof(pr, st, "b_cheb_a", k_b_cheb_a, dim3((unsigned)blocks_a), dim3(256), 0, reps, R, base_a, moves);
+    launch_prof(pr, st, "b_cheb_b", k_b_cheb_b, dim3((unsigned)blocks_b), dim3(256), 0, reps, R, base_b, moves);
 }
 
 }  // namespace fmmkmc
