@@ -12,8 +12,15 @@ accepted move is a seeded uniform choice among the valid slots that does not
 look at dU.  Inputs are resident on the GPU before timing starts; the one-time
 setup (octree build) is timed separately and not part of a step.
 
+A second workload, batched replicas, runs after it unless --skip-batch: 256
+independent periodic systems with N_r log-uniform in [1000, 65536] at 50 %
+lattice occupancy, 6 hops, p = 10, advanced together (one launch per phase of a
+step over all replicas, the step replayed from a captured HIP graph), in mixed
+precision and FP64, beside the plain FP64 path (one replica at a time).
+
 Prints one JSON line.  Options: --steps K --warmup W --gpus 1 [--skip-cpu]
-[--precision fp64|mixed|both] [--quick] (a small periodic system for a smoke run).
+[--skip-batch] [--batch-only] [--precision fp64|mixed|both] [--copy-calibration]
+[--quick] (a small periodic system for a smoke run).
 """
 import argparse
 import json
@@ -204,6 +211,96 @@ def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed):
                 commit_us=1e6 * commit_wall / steps, kernels=ktimes, valid_slots=valid, U0=U0)
 
 
+def batch_contexts(precision, p=10, count=256):
+    """the replicas of the batched workload: N_r log-uniform in [1000, 65536],
+    lattice side n_r = ceil((2 N_r)^(1/3)) (about 50 % occupancy), depth by the
+    level rule, periodic, p = 10"""
+    from paper_1905_04065_amd import Context
+    Ns, ns, Ls = W.replica_sizes(count)
+    ctxs = []
+    for r in range(count):
+        sites, xyz, q = W.replica_system(r, Ns[r], ns[r])
+        c = Context(xyz, q, a=float(ns[r]), levels=int(Ls[r]), order=p, bc="periodic", precision=precision,
+                    lattice_n=int(ns[r]), device=0)
+        c.initialise()
+        ctxs.append(c)
+        if (r + 1) % 64 == 0:
+            log(f"[batch] {precision}: {r + 1}/{count} replicas set up")
+    return ctxs, Ns, ns
+
+
+def run_batched(precision, steps, warmup, seed, tune=True):
+    """config-5 steps of all replicas as one captured graph per step"""
+    import torch
+
+    from paper_1905_04065_amd import Batch
+    t0 = time.perf_counter()
+    ctxs, Ns, ns = batch_contexts(precision)
+    b = Batch(ctxs, W.HOPS6)
+    setup_s = time.perf_counter() - t0
+    info = b.tune(rounds=5) if tune else b.info()
+    R = len(ctxs)
+    rng = np.random.default_rng(seed)
+    b.step(rng.random((warmup, R)))
+    u = rng.random((steps, R))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    moved, site, dU = b.step(u)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-phase times over a few more steps as plain launches
+    b.set_profiling(True)
+    b.step(rng.random((3, R)))
+    phases = {}
+    for name in ["b_site", "b_slot", "b_count", "b_select", "b_move_dU", "b_frow", "b_sweep", "b_path", "b_book",
+                 "b_far_refresh", "b_cheb_a", "b_cheb_b", "b_finish"]:
+        ms, n = b.kernel_time(name)
+        if n:
+            phases[name] = ms / n * 1e3
+    b.set_profiling(False)
+    moved_frac = float((moved.cpu().numpy() >= 0).mean())
+    b.close()
+    for c in ctxs:
+        c.close()
+    return dict(ms_per_step=1e3 * wall / steps, slots_per_step=info["slots_per_step"], tuning=info,
+                setup_s=setup_s, phase_us=phases, replicas=R, moved_fraction=moved_frac)
+
+
+def run_unbatched_fp64(steps, seed):
+    """the plain path: each replica stepped through the single-context API
+    (proposal pass, selection on the host from the mask, accept), FP64"""
+    import torch
+    ctxs, Ns, ns = batch_contexts("fp64")
+    R = len(ctxs)
+    rng = np.random.default_rng(seed)
+    bufs = [(torch.empty((c.N, 6), dtype=torch.float64, device="cuda"),
+             torch.empty((c.N, 6), dtype=torch.uint8, device="cuda")) for c in ctxs]
+    cur = [W.replica_system(r, Ns[r], ns[r])[0].copy() for r in range(R)]
+
+    def one_step(u):
+        for r, c in enumerate(ctxs):
+            dU, mask = c.propose_lattice(W.HOPS6, dU=bufs[r][0], mask=bufs[r][1])
+            m = mask.cpu().numpy().reshape(-1)  # synchronises
+            vs = np.flatnonzero(m)
+            slot = vs[int(u[r] * len(vs))]
+            i, k = divmod(int(slot), 6)
+            t, _ = W.lattice_targets(cur[r][i:i + 1], int(ns[r]), W.HOPS6[k:k + 1], True)
+            c.accept(i, W.site_xyz([int(t[0, 0])], int(ns[r]))[0])
+            cur[r][i] = int(t[0, 0])
+
+    one_step(rng.random(R))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step(rng.random(R))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    slots = int(sum(c.N for c in ctxs)) * 6
+    for c in ctxs:
+        c.close()
+    return dict(ms_per_step=1e3 * wall / steps, slots_per_step=slots)
+
+
 def cpu_baseline(n, N, L, p, hops, seed, budget_s=20.0):
     """The oracle (O-fmm, FP64, OpenMP) on the host cores, on a bounded sample:
     all hops of the charges in a 2x2x2 block of fine cells, after the cells
@@ -263,6 +360,29 @@ def roofline_entry(kernel, kt, n, N, K, p, precision, copy_gbs, traffic):
     return e
 
 
+def batched_summary(args):
+    """256 replicas, p = 10, 6 hops, periodic: mixed and FP64 batched (graph
+    steps) against the plain FP64 path (one replica at a time, host selection)"""
+    seed = W.BASE_SEED + 5
+    steps = max(args.steps, 5)
+    log("[batch] mixed")
+    mixed = run_batched("mixed", steps, args.warmup, seed)
+    log("[batch] fp64")
+    fp64 = run_batched("fp64", steps, args.warmup, seed)
+    log("[batch] fp64 one replica at a time")
+    plain = run_unbatched_fp64(2, seed)
+    slots = mixed["slots_per_step"]
+    return {
+        "workload": f"{mixed['replicas']} periodic replicas, N_r log-uniform in [1000, 65536] (sum {slots // 6}), "
+                    "50 % lattice occupancy, 6 hops, p=10, one accepted move per replica per step",
+        "slots_per_step": slots,
+        "mixed_batched": {"proposals_per_s": slots / (mixed["ms_per_step"] / 1e3), **mixed},
+        "fp64_batched": {"proposals_per_s": slots / (fp64["ms_per_step"] / 1e3), **fp64},
+        "fp64_one_replica_at_a_time": {"proposals_per_s": slots / (plain["ms_per_step"] / 1e3), **plain},
+        "speedup_mixed_batched_vs_plain_fp64": plain["ms_per_step"] / mixed["ms_per_step"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,11 +393,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the 1 GiB device copy used to calibrate rocprofv3 byte counters")
     ap.add_argument("--quick", action="store_true", help="small periodic system (64^3, N=1e5, L=6)")
+    ap.add_argument("--skip-batch", action="store_true", help="leave out the batched-replica workload")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched-replica workload (JSON to stdout)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is "
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
+    if args.batch_only:
+        print(json.dumps(batched_summary(args)), flush=True)
+        return
     if args.quick:
         n, N, L, p, hops = 64, 100000, 6, 12, W.HOPS26
     else:
@@ -346,6 +471,8 @@ def main():
                         "commit_us": m["commit_us"],
                         "dtype": "f32 fine-level evaluation, f64 difference/far field/commit",
                         "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"]}
+    if not args.skip_batch:
+        out["batched"] = batched_summary(args)
     if not args.skip_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(n, N, L, p, hops, seed)

@@ -113,6 +113,7 @@ void release(fmmkmc_ctx *c)
     dfree(c->ijk_r);
     dfree(c->qsite);
     dfree(c->qsite32);
+    dfree(c->cell_rng);
     for (auto &p : c->phi_lv) dfree(p);
     for (auto &p : c->psi_lv) dfree(p);
     dfree(c->d_phi_ptrs);
@@ -474,17 +475,31 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
             HIPCHK(hipStreamSynchronize(s));
         }
         c->phisite = dalloc<double>(ns);
-        if (c->s2) {
+        {
+            // charge per site in site order (0 on a vacant site)
             std::vector<double> qs(ns, 0.0);
             std::vector<float> qs32(ns, 0.0f);
             for (int64_t i = 0; i < n; ++i) {
-                const int64_t st = c->hsite[i];
-                const int si = (int)(st / ((int64_t)c->lat_n * c->lat_n)), sj = (int)((st / c->lat_n) % c->lat_n),
-                          sk = (int)(st % c->lat_n);
-                const int64_t cm = s2_site(c->nc, si, sj, sk);
-                qs[cm] = c->hq[i];
-                qs32[cm] = (float)c->hq[i];
+                const int64_t so = site_order(c, c->hsite[i]);
+                qs[so] = c->hq[i];
+                qs32[so] = (float)c->hq[i];
             }
+            // per axis, the first and last site index of every fine cell (the
+            // cell of a site is the cell of its position, as for any point)
+            std::vector<int32_t> rng(2 * (size_t)c->nc, -1);
+            const double w = c->a / c->nc, h = lattice_h(c);
+            for (int i = 0; i < c->lat_n; ++i) {
+                const int cc = fine_coord((i + 0.5) * h, w, c->nc);
+                if (rng[2 * cc] < 0) rng[2 * cc] = i;
+                rng[2 * cc + 1] = i;
+            }
+            for (int cc = 0; cc < c->nc; ++cc)
+                if (rng[2 * cc] < 0) {  // a cell narrower than the lattice spacing may hold no plane
+                    rng[2 * cc] = 0;
+                    rng[2 * cc + 1] = -1;
+                }
+            c->cell_rng = dalloc<int32_t>(rng.size());
+            upload(c->cell_rng, rng.data(), rng.size(), s);
             c->qsite = dalloc<double>(ns);
             upload(c->qsite, qs.data(), ns, s);
             if (c->prec == FMMKMC_MIXED) {

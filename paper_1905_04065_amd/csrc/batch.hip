@@ -461,6 +461,7 @@ RepDev make_rep(const fmmkmc_ctx *c, int K, double *dU, uint8_t *mask)
     d.site_rank = c->site_rank;
     d.qsite = c->qsite;
     d.qsite32 = c->qsite32;
+    d.cell_rng = c->cell_rng;
     d.phisite = c->phisite;
     d.order = c->order;
     d.ijk_r = c->ijk_r;

@@ -29,6 +29,7 @@ struct RepDev {
     int32_t *site_charge, *site_rank;
     double *qsite;
     float *qsite32;
+    int32_t *cell_rng;
     double *phisite;
     // by rank
     int32_t *order, *ijk_r;

@@ -86,8 +86,9 @@ struct fmmkmc_ctx {
     int32_t *rank_of = nullptr;      // lattice: rank of each charge (device copy of hrank)
     double *q_r = nullptr;
     int32_t *ijk_r = nullptr;
-    double *qsite = nullptr;         // 2x2x2 lattice: charge per site, cell-major order
+    double *qsite = nullptr;         // lattice: charge per site (0 if vacant), site order
     float *qsite32 = nullptr;
+    int32_t *cell_rng = nullptr;     // lattice: [nc][2] first and last site index of each fine cell, per axis
 
     // expansions (device), coefficient-major [k][cells]
     std::vector<double *> phi_lv, psi_lv;  // index = level 1..L

@@ -70,7 +70,7 @@ struct Book {
     int64_t old_sord, new_sord;  // site order (cell-major on the 2x2x2 path)
     int32_t new_ijk;
     int32_t rank;
-    int s2;               // per-site charges are kept (2x2x2 path)
+    int s2;               // lattice with 2x2x2 sites per fine cell (cell-major site order)
     int same_cell;        // the move stays inside one fine cell: slots unchanged
 };
 

@@ -300,7 +300,7 @@ __device__ __forceinline__ void book_body(const Book &b, double *x, double *y, d
         site_rank[b.new_sord] = b.rank;
         site[b.i] = (int32_t)b.new_site;
         ijk_r[b.rank] = b.new_ijk;
-        if (b.s2) {
+        if (qsite) {
             qsite[b.old_sord] = 0.0;
             qsite[b.new_sord] = b.q;
             if (qsite32) {

@@ -130,66 +130,104 @@ __device__ inline double far_site(int n, int i, int j, int k, const double *__re
     return acc;
 }
 
-// one lane per lattice site (lattice order); the occupant of a site, if any,
-// is left out of its own potential, so occupied sites get phi_occ.
+// constexpr square root (Newton from above; exact enough for 1/sqrt of small integers)
+__host__ __device__ constexpr double csqrt(double x)
+{
+    if (x <= 0) return 0.0;
+    double r = x > 1 ? x : 1.0;
+    for (int it = 0; it < 64; ++it) r = 0.5 * (r + x / r);
+    return r;
+}
+
+// 1/sqrt(k) for the squared integer site offsets of the near field
+constexpr int kInvTab = 512;
+struct InvSqrtTab {
+    double v[kInvTab];
+    constexpr InvSqrtTab() : v{}
+    {
+        for (int i = 1; i < kInvTab; ++i) v[i] = 1.0 / csqrt((double)i);
+    }
+};
+
+// One lane per lattice site (lattice order).  The near field of a site is the
+// charge of every site in the 27 cells around its cell; per axis those cells
+// are three runs of consecutive lattice planes (cell_rng), so the 27 cells
+// form a box of sites whose offsets from the lane's site are integers: the
+// charges are read straight from the per-site array (no slot lists) and
+// 1/|d| = 1/(h sqrt(d^2)) comes from a table of integer d^2.  The site's own
+// occupant (d^2 = 0) is left out, so occupied sites get phi_occ.
 template <int P, bool MIXED>
 __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
-                                                          const float *__restrict__ psi32,
-                                                          const double *__restrict__ Bz,
-                                                          const double *__restrict__ Tax,
-                                                          const double *__restrict__ x, const double *__restrict__ y,
-                                                          const double *__restrict__ z, const double *__restrict__ q,
-                                                          const int32_t *__restrict__ cnt,
-                                                          const int32_t *__restrict__ slots,
-                                                          const int32_t *__restrict__ site_charge,
-                                                          const int32_t *__restrict__ site_rank,
-                                                          double *__restrict__ phisite, double *__restrict__ phi_r)
+                                                  const float *__restrict__ psi32, const double *__restrict__ Bz,
+                                                  const double *__restrict__ Tax, const double *__restrict__ qsite,
+                                                  const float *__restrict__ qsite32,
+                                                  const int32_t *__restrict__ cell_rng,
+                                                  const int32_t *__restrict__ site_rank,
+                                                  double *__restrict__ phisite, double *__restrict__ phi_r)
 {
+    using Real = typename std::conditional<MIXED, float, double>::type;
+    constexpr InvSqrtTab IT{};
+    __shared__ Real sInv[kInvTab];
+    for (int e = threadIdx.x; e < kInvTab; e += blockDim.x) sInv[e] = (Real)IT.v[e];
+    __syncthreads();
     const int64_t s = blk * blockDim.x + threadIdx.x;
-    const int n = g.n;
+    const int n = g.n, nc = g.nc;
     if (s >= (int64_t)n * n * n) return;
     const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
     const double px = (si + 0.5) * g.h, py = (sj + 0.5) * g.h, pz = (sk + 0.5) * g.h;
-    const int ex = site_charge[s];
-    const int cx = fine_coord(px, g.w, g.nc), cy = fine_coord(py, g.w, g.nc), cz = fine_coord(pz, g.w, g.nc);
-    const int64_t cell = cell_id(g.nc, cx, cy, cz);
+    const int cx = fine_coord(px, g.w, nc), cy = fine_coord(py, g.w, nc), cz = fine_coord(pz, g.w, nc);
+    const int64_t cell = cell_id(nc, cx, cy, cz);
     const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
     double phi;
     if (MIXED)
         phi = psi[cell] + (double)l2p<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
     else
         phi = l2p<P, double>(psi + cell, M, ux, uy, uz);
-    double nearv = 0.0;
-    float nearf = 0.0f;
-    for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
+    const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
+    Real nearv = Real(0);
+    for (int dx = -1; dx <= 1; ++dx) {
+        int ax = cx + dx, shx = 0;  // shift in lattice planes of a wrapped cell
+        if (ax < 0 || ax >= nc) {
+            if (!g.periodic) continue;
+            shx = ax < 0 ? -n : n;
+            ax -= ax < 0 ? -nc : nc;
+        }
+        const int ilo = cell_rng[2 * ax], ihi = cell_rng[2 * ax + 1];
+        for (int dy = -1; dy <= 1; ++dy) {
+            int ay = cy + dy, shy = 0;
+            if (ay < 0 || ay >= nc) {
+                if (!g.periodic) continue;
+                shy = ay < 0 ? -n : n;
+                ay -= ay < 0 ? -nc : nc;
+            }
+            const int jlo = cell_rng[2 * ay], jhi = cell_rng[2 * ay + 1];
             for (int dz = -1; dz <= 1; ++dz) {
-                int ax = cx + dx, ay = cy + dy, az = cz + dz;
-                double shx = 0, shy = 0, shz = 0;
-                if (ax < 0 || ax >= g.nc || ay < 0 || ay >= g.nc || az < 0 || az >= g.nc) {
+                int az = cz + dz, shz = 0;
+                if (az < 0 || az >= nc) {
                     if (!g.periodic) continue;
-                    shx = g.a * floordiv(ax, g.nc);
-                    shy = g.a * floordiv(ay, g.nc);
-                    shz = g.a * floordiv(az, g.nc);
-                    ax = posmod(ax, g.nc);
-                    ay = posmod(ay, g.nc);
-                    az = posmod(az, g.nc);
+                    shz = az < 0 ? -n : n;
+                    az -= az < 0 ? -nc : nc;
                 }
-                const int64_t nb = cell_id(g.nc, ax, ay, az);
-                const int cn = cnt[nb];
-                for (int t = 0; t < cn; ++t) {
-                    const int j = slots[nb * g.cap + t];
-                    if (j == ex) continue;  // a site's occupant has no copy among its 27 neighbour cells
-                    const double ex_ = px - (x[j] + shx), ey_ = py - (y[j] + shy), ez_ = pz - (z[j] + shz);
-                    if (MIXED) {
-                        const float fx = (float)ex_, fy = (float)ey_, fz = (float)ez_;
-                        nearf += (float)q[j] * __frsqrt_rn(fx * fx + fy * fy + fz * fz);
-                    } else {
-                        nearv += q[j] / sqrt(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
+                const int klo = cell_rng[2 * az], khi = cell_rng[2 * az + 1];
+                for (int i = ilo; i <= ihi; ++i) {
+                    const int di = si - (i + shx);
+                    for (int j = jlo; j <= jhi; ++j) {
+                        const int dj = sj - (j + shy);
+                        const Real *row = Qs + ((int64_t)i * n + j) * n;
+                        for (int k = klo; k <= khi; ++k) {
+                            const Real qv = row[k];
+                            const int dk = sk - (k + shz);
+                            const int d2 = di * di + dj * dj + dk * dk;
+                            if (d2 == 0 || qv == Real(0)) continue;
+                            const Real inv = d2 < kInvTab ? sInv[d2] : Real(1) / sqrt((Real)d2);
+                            nearv += qv * inv;
+                        }
                     }
                 }
             }
-    phi += MIXED ? (double)nearf : nearv;
+        }
+    }
+    phi += (double)nearv / g.h;
     if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
     const int32_t rk = site_rank[s];
     if (rk >= 0) phi_r[rk] = phi;
@@ -201,16 +239,14 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
                                                           const float *__restrict__ psi32,
                                                           const double *__restrict__ Bz,
                                                           const double *__restrict__ Tax,
-                                                          const double *__restrict__ x, const double *__restrict__ y,
-                                                          const double *__restrict__ z, const double *__restrict__ q,
-                                                          const int32_t *__restrict__ cnt,
-                                                          const int32_t *__restrict__ slots,
-                                                          const int32_t *__restrict__ site_charge,
+                                                          const double *__restrict__ qsite,
+                                                          const float *__restrict__ qsite32,
+                                                          const int32_t *__restrict__ cell_rng,
                                                           const int32_t *__restrict__ site_rank,
                                                           double *__restrict__ phisite, double *__restrict__ phi_r)
 {
-    site_general_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, Bz, Tax, x, y, z, q, cnt, slots, site_charge,
-                                site_rank, phisite, phi_r);
+    site_general_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, Bz, Tax, qsite, qsite32, cell_rng, site_rank,
+                                phisite, phi_r);
 }
 
 // ---- lattice with 2 x 2 x 2 sites per fine cell ----------------------------
@@ -224,14 +260,6 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
 // the 27-cell block are compile-time constants; only the powers h^n and 1/h
 // are applied at run time.  No tables are read.
 
-// constexpr square root (Newton from above; exact enough for 1/|d|, |d|^2 <= 27)
-__host__ __device__ constexpr double csqrt(double x)
-{
-    if (x <= 0) return 0.0;
-    double r = x > 1 ? x : 1.0;
-    for (int it = 0; it < 64; ++it) r = 0.5 * (r + x / r);
-    return r;
-}
 
 template <int P>
 struct S2Weights {
@@ -491,14 +519,12 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
         dim3 grid((unsigned)((ns + 255) / 256));
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, true>, grid, dim3(256), g, c->M,
-                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->x, c->y, c->z,
-                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->site_rank,
-                                           c->phisite, c->phi_r));
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->qsite, c->qsite32,
+                                           c->cell_rng, c->site_rank, c->phisite, c->phi_r));
         } else {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, false>, grid, dim3(256), g, c->M,
-                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->x, c->y, c->z,
-                                           c->q, c->cell_cnt, c->cell_slots, c->site_charge, c->site_rank,
-                                           c->phisite, c->phi_r));
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->qsite, c->qsite32,
+                                           c->cell_rng, c->site_rank, c->phisite, c->phi_r));
         }
     }
 }
@@ -1193,8 +1219,8 @@ __global__ __launch_bounds__(256) void k_b_site(const RepDev *__restrict__ reps,
         site_s2_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
                                d.phisite, d.phi_r);
     else
-        site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.x, d.y, d.z, d.q, d.cnt,
-                                    d.slots, d.site_charge, d.site_rank, d.phisite, d.phi_r);
+        site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.qsite, d.qsite32, d.cell_rng,
+                                    d.site_rank, d.phisite, d.phi_r);
 }
 
 template <int TC>

@@ -141,69 +141,116 @@ __global__ __launch_bounds__(256) void k_m2m(int nt, int ncp, const double *__re
     }
 }
 
-// M2L + L2L for one level.  Lanes of a block share the parity class (the
-// position of the cell within its parent), hence the same 189 interaction-list
-// offsets.  M2L matrices are for unit cell width; per-level scaling by
-// w^-deg(n) on input and w^-(deg(k)+1) on output.
+// M2L + L2L for one level.  A block takes C target cells of one parity class
+// (the position of a cell within its parent), which share the 189
+// interaction-list offsets, and one thread per output coefficient k (KPT per
+// thread when (p+1)^2 > 256).  For each offset the source coefficients of the
+// C cells are staged in LDS (scaled by w^-deg(n): the M2L matrices are for unit
+// cell width), and a thread runs down its column of the matrix with coalesced
+// loads, using each staged coefficient C times; outputs get w^-(deg(k)+1), the
+// parent's local expansion is added through the L2L matrix of the parity
+// class, and the block writes its C x (p+1)^2 results through LDS.
+template <int C, int KPT>
 __global__ __launch_bounds__(256) void k_m2l(int nt, int nc, int periodic, int with_parent,
                                              const double *__restrict__ m2l, const int32_t *__restrict__ m2l_index,
                                              const double *__restrict__ scale_in, const double *__restrict__ scale_out,
                                              const double *__restrict__ l2l, const double *__restrict__ phi,
                                              const double *__restrict__ psi_parent, double *__restrict__ psi)
 {
-    const int pcls = blockIdx.y;  // parity class 0..7
+    extern __shared__ double stage[];  // [nt][C]
+    const int pcls = blockIdx.y;
     const int px = pcls >> 2, py = (pcls >> 1) & 1, pz = pcls & 1;
     const int h = nc / 2;
     const int64_t Mh = (int64_t)h * h * h, M = Mh * 8;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Mh) return;
-    const int ix = (int)(t / ((int64_t)h * h)), iy = (int)((t / h) % h), iz = (int)(t % h);
-    const int cx = 2 * ix + px, cy = 2 * iy + py, cz = 2 * iz + pz;
-    const int64_t cell = cell_id(nc, cx, cy, cz);
-    const int64_t Mparent = Mh;
-    const int64_t parent = cell_id(h, ix, iy, iz);
-    for (int k0 = 0; k0 < nt; k0 += KB) {
-        double acc[KB];
+    const int64_t t0 = (int64_t)blockIdx.x * C;
+    const int ncell = (int)(Mh - t0 < C ? Mh - t0 : C);
+    double acc[KPT][C];
 #pragma unroll
-        for (int u = 0; u < KB; ++u) acc[u] = 0.0;
-        for (int dx = -2 - px; dx <= 3 - px; ++dx)
-            for (int dy = -2 - py; dy <= 3 - py; ++dy)
-                for (int dz = -2 - pz; dz <= 3 - pz; ++dz) {
-                    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
-                    int sx = cx + dx, sy = cy + dy, sz = cz + dz;
-                    const bool outside = sx < 0 || sx >= nc || sy < 0 || sy >= nc || sz < 0 || sz >= nc;
-                    if (outside && !periodic) continue;
-                    sx = posmod(sx, nc);
-                    sy = posmod(sy, nc);
-                    sz = posmod(sz, nc);
-                    const int64_t src = cell_id(nc, sx, sy, sz);
-                    // the matrix converts source at offset -d to target: d = target - source
-                    const int o = m2l_index[(-dx + 3) * 49 + (-dy + 3) * 7 + (-dz + 3)];
-                    const double *mat = m2l + (int64_t)o * nt * nt;
-                    for (int n = 0; n < nt; ++n) {
-                        const double v = phi[(int64_t)n * M + src] * scale_in[n];
-                        const double *row = mat + (int64_t)n * nt + k0;
+    for (int u = 0; u < KPT; ++u)
 #pragma unroll
-                        for (int u = 0; u < KB; ++u)
-                            if (k0 + u < nt) acc[u] += row[u] * v;
+        for (int c = 0; c < C; ++c) acc[u][c] = 0.0;
+    for (int dx = -2 - px; dx <= 3 - px; ++dx)
+        for (int dy = -2 - py; dy <= 3 - py; ++dy)
+            for (int dz = -2 - pz; dz <= 3 - pz; ++dz) {
+                if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+                for (int e = threadIdx.x; e < nt * C; e += blockDim.x) {
+                    const int n = e / C, c = e - n * C;
+                    double v = 0.0;
+                    if (c < ncell) {
+                        const int64_t t = t0 + c;
+                        const int ix = (int)(t / ((int64_t)h * h)), iy = (int)((t / h) % h), iz = (int)(t % h);
+                        int sx = 2 * ix + px + dx, sy = 2 * iy + py + dy, sz = 2 * iz + pz + dz;
+                        const bool outside = sx < 0 || sx >= nc || sy < 0 || sy >= nc || sz < 0 || sz >= nc;
+                        if (!outside || periodic) {
+                            sx = posmod(sx, nc);
+                            sy = posmod(sy, nc);
+                            sz = posmod(sz, nc);
+                            v = phi[(int64_t)n * M + cell_id(nc, sx, sy, sz)] * scale_in[n];
+                        }
+                    }
+                    stage[e] = v;
+                }
+                __syncthreads();
+                // the matrix converts a source at offset -d to the target: d = target - source
+                const double *mat = m2l + (int64_t)m2l_index[(-dx + 3) * 49 + (-dy + 3) * 7 + (-dz + 3)] * nt * nt;
+#pragma unroll
+                for (int u = 0; u < KPT; ++u) {
+                    const int k = threadIdx.x + u * 256;
+                    if (k < nt) {
+                        for (int n = 0; n < nt; ++n) {
+                            const double tv = mat[(int64_t)n * nt + k];
+                            const double *sr = stage + n * C;
+#pragma unroll
+                            for (int c = 0; c < C; ++c) acc[u][c] += tv * sr[c];
+                        }
                     }
                 }
+                __syncthreads();
+            }
 #pragma unroll
-        for (int u = 0; u < KB; ++u)
-            if (k0 + u < nt) acc[u] *= scale_out[k0 + u];
-        if (with_parent) {
-            const double *mat = l2l + (int64_t)pcls * nt * nt;
-            for (int n = 0; n < nt; ++n) {
-                const double v = psi_parent[(int64_t)n * Mparent + parent];
-                const double *row = mat + (int64_t)n * nt + k0;
+    for (int u = 0; u < KPT; ++u) {
+        const int k = threadIdx.x + u * 256;
+        const double so = k < nt ? scale_out[k] : 0.0;
 #pragma unroll
-                for (int u = 0; u < KB; ++u)
-                    if (k0 + u < nt) acc[u] += row[u] * v;
+        for (int c = 0; c < C; ++c) acc[u][c] *= so;
+    }
+    if (with_parent) {
+        for (int e = threadIdx.x; e < nt * C; e += blockDim.x) {
+            const int n = e / C, c = e - n * C;
+            double v = 0.0;
+            if (c < ncell) v = psi_parent[(int64_t)n * Mh + t0 + c];  // parent index = class index
+            stage[e] = v;
+        }
+        __syncthreads();
+        const double *mat = l2l + (int64_t)pcls * nt * nt;
+#pragma unroll
+        for (int u = 0; u < KPT; ++u) {
+            const int k = threadIdx.x + u * 256;
+            if (k < nt) {
+                for (int n = 0; n < nt; ++n) {
+                    const double tv = mat[(int64_t)n * nt + k];
+                    const double *sr = stage + n * C;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[u][c] += tv * sr[c];
+                }
             }
         }
+        __syncthreads();
+    }
+    // results through LDS: [k][c], then coalesced over the block's cells
+    for (int u = 0; u < KPT; ++u) {
+        const int k = threadIdx.x + u * 256;
+        if (k < nt)
 #pragma unroll
-        for (int u = 0; u < KB; ++u)
-            if (k0 + u < nt) psi[(int64_t)(k0 + u) * M + cell] = acc[u];
+            for (int c = 0; c < C; ++c) stage[k * C + c] = acc[u][c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nt * C; e += blockDim.x) {
+        const int k = e / C, c = e - k * C;
+        if (c >= ncell) continue;
+        const int64_t t = t0 + c;
+        const int ix = (int)(t / ((int64_t)h * h)), iy = (int)((t / h) % h), iz = (int)(t % h);
+        psi[(int64_t)k * M + cell_id(nc, 2 * ix + px, 2 * iy + py, 2 * iz + pz)] = stage[e];
     }
 }
 
@@ -224,9 +271,24 @@ void launch_downward(fmmkmc_ctx *c)
         const int nc = 1 << (l - 1);
         const int64_t Mh = (int64_t)(nc / 2) * (nc / 2) * (nc / 2);
         const double *sin_ = c->scale + (int64_t)(2 * l) * c->nt, *sout = c->scale + (int64_t)(2 * l + 1) * c->nt;
-        launch(c, "m2l", k_m2l, dim3((unsigned)((Mh + 255) / 256), 8), dim3(256), c->nt, nc,
-               c->bc == FMMKMC_PERIODIC ? 1 : 0, l > start ? 1 : 0, c->m2l, c->m2l_index, sin_, sout, c->l2l[l],
-               c->phi_lv[l], l > start ? c->psi_lv[l - 1] : nullptr, c->psi_lv[l]);
+        const double *par = l > start ? c->psi_lv[l - 1] : nullptr;
+        const int wp = l > start ? 1 : 0, per = c->bc == FMMKMC_PERIODIC ? 1 : 0;
+        if (c->nt <= 196) {  // p <= 13: 32 cells per block, <= 50 KB of LDS
+            constexpr int C = 32;
+            launch_shm(c, "m2l", k_m2l<C, 1>, dim3((unsigned)((Mh + C - 1) / C), 8), dim3(256),
+                       sizeof(double) * c->nt * C, c->nt, nc, per, wp, c->m2l, c->m2l_index, sin_, sout,
+                       c->l2l[l], c->phi_lv[l], par, c->psi_lv[l]);
+        } else {
+            constexpr int C = 16;
+            if (c->nt <= 256)
+                launch_shm(c, "m2l", k_m2l<C, 1>, dim3((unsigned)((Mh + C - 1) / C), 8), dim3(256),
+                           sizeof(double) * c->nt * C, c->nt, nc, per, wp, c->m2l, c->m2l_index, sin_, sout,
+                           c->l2l[l], c->phi_lv[l], par, c->psi_lv[l]);
+            else
+                launch_shm(c, "m2l", k_m2l<C, 2>, dim3((unsigned)((Mh + C - 1) / C), 8), dim3(256),
+                           sizeof(double) * c->nt * C, c->nt, nc, per, wp, c->m2l, c->m2l_index, sin_, sout,
+                           c->l2l[l], c->phi_lv[l], par, c->psi_lv[l]);
+        }
     }
 }
 
