@@ -484,20 +484,20 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
                 qs[so] = c->hq[i];
                 qs32[so] = (float)c->hq[i];
             }
-            // per axis, the first and last site index of every fine cell (the
-            // cell of a site is the cell of its position, as for any point)
-            std::vector<int32_t> rng(2 * (size_t)c->nc, -1);
+            // per axis, the first and last lattice plane of every fine cell (the
+            // cell of a site is the cell of its position, as for any point):
+            // first = planes in lower cells, last = planes in this and lower
+            // cells - 1, so a cell holding no plane has an empty range at the
+            // right place and runs of consecutive cells are [first, last]
+            std::vector<int32_t> rng(2 * (size_t)c->nc, 0), per(c->nc, 0);
             const double w = c->a / c->nc, h = lattice_h(c);
-            for (int i = 0; i < c->lat_n; ++i) {
-                const int cc = fine_coord((i + 0.5) * h, w, c->nc);
-                if (rng[2 * cc] < 0) rng[2 * cc] = i;
-                rng[2 * cc + 1] = i;
+            for (int i = 0; i < c->lat_n; ++i) ++per[fine_coord((i + 0.5) * h, w, c->nc)];
+            int below = 0;
+            for (int cc = 0; cc < c->nc; ++cc) {
+                rng[2 * cc] = below;
+                below += per[cc];
+                rng[2 * cc + 1] = below - 1;
             }
-            for (int cc = 0; cc < c->nc; ++cc)
-                if (rng[2 * cc] < 0) {  // a cell narrower than the lattice spacing may hold no plane
-                    rng[2 * cc] = 0;
-                    rng[2 * cc + 1] = -1;
-                }
             c->cell_rng = dalloc<int32_t>(rng.size());
             upload(c->cell_rng, rng.data(), rng.size(), s);
             c->qsite = dalloc<double>(ns);

@@ -58,6 +58,53 @@ struct RecTables {
     }
 };
 
+// L2P (the same sum as l2p() in solid.hpp) with the orders m >= 1 in a rolled
+// loop: one column's coefficients are live at a time, so the compiler cannot
+// hoist all (p+1)^2 loads at once and the caller keeps a small register
+// footprint; the recurrence reciprocals come from RecTables (uniform indices).
+template <int P, typename T, bool SKIP0 = false>
+__device__ inline T l2p_cols(const T *L, long stride, T x, T y, T z)
+{
+    constexpr RecTables RT{};
+    const T r2 = x * x + y * y + z * z;
+    T acc0 = SKIP0 ? T(0) : L[0];
+    T cm2 = T(1), cm1 = z;
+    if (P >= 1) acc0 += L[slot0(1) * stride] * z;
+#pragma unroll
+    for (int n = 2; n <= P; ++n) {
+        const T c = ((T)(2 * n - 1) * z * cm1 - r2 * cm2) * (T)RT.rinv[n][0];
+        acc0 += L[slot0(n) * stride] * c;
+        cm2 = cm1;
+        cm1 = c;
+    }
+    T acc1 = T(0);
+    T dr = T(1), di = T(0);
+#pragma unroll 1
+    for (int m = 1; m <= P; ++m) {
+        const T f = -(T)RT.half_inv[m];
+        const T ndr = f * (x * dr - y * di), ndi = f * (x * di + y * dr);
+        dr = ndr;
+        di = ndi;
+        T ar = dr, ai = di;
+        acc1 += L[(long)slot_re(m, m) * stride] * ar + L[(long)slot_im(m, m) * stride] * ai;
+        if (m + 1 > P) break;
+        T br = z * ar, bi = z * ai;
+        acc1 += L[(long)slot_re(m + 1, m) * stride] * br + L[(long)slot_im(m + 1, m) * stride] * bi;
+#pragma unroll 2
+        for (int n = m + 2; n <= P; ++n) {
+            const T w = (T)RT.rinv[n][m];
+            const T zn = (T)(2 * n - 1) * z;
+            const T cr = (zn * br - r2 * ar) * w, ci = (zn * bi - r2 * ai) * w;
+            acc1 += L[(long)slot_re(n, m) * stride] * cr + L[(long)slot_im(n, m) * stride] * ci;
+            ar = br;
+            ai = bi;
+            br = cr;
+            bi = ci;
+        }
+    }
+    return acc0 + T(2) * acc1;
+}
+
 // Column m (degrees n = m..p) of the regular harmonics at offset d, as L2P
 // weights Wt (Psi(d) = sum_k L_k Wt[k]) and, if Km is not null, as the
 // real-stored multipole of a unit charge at d (Km[k] = conj(R_k(d))).  Lanes

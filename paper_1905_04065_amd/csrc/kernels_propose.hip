@@ -180,47 +180,64 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
     const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
     double phi;
     if (MIXED)
-        phi = psi[cell] + (double)l2p<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
+        phi = psi[cell] + (double)l2p_cols<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
     else
-        phi = l2p<P, double>(psi + cell, M, ux, uy, uz);
+        phi = l2p_cols<P, double>(psi + cell, M, ux, uy, uz);
     const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
-    Real nearv = Real(0);
-    for (int dx = -1; dx <= 1; ++dx) {
-        int ax = cx + dx, shx = 0;  // shift in lattice planes of a wrapped cell
-        if (ax < 0 || ax >= nc) {
-            if (!g.periodic) continue;
-            shx = ax < 0 ? -n : n;
-            ax -= ax < 0 ? -nc : nc;
+    // per axis, the planes of cells c-1, c, c+1 are at most two runs of
+    // consecutive indices (two when the block wraps around a periodic face);
+    // run r of an axis: planes [lo_r, hi_r] shifted by sh_r planes (empty if hi_r < lo_r)
+    struct Runs {
+        int lo0, hi0, sh0, lo1, hi1, sh1;
+    };
+    auto runs = [&](int c) {
+        Runs r;
+        const int a0 = c - 1 < 0 ? 0 : c - 1, a1 = c + 1 >= nc ? nc - 1 : c + 1;
+        r.lo0 = cell_rng[2 * a0];
+        r.hi0 = cell_rng[2 * a1 + 1];
+        r.sh0 = 0;
+        r.lo1 = 0;
+        r.hi1 = -1;
+        r.sh1 = 0;
+        if (g.periodic && c - 1 < 0) {
+            r.lo1 = cell_rng[2 * (nc - 1)];
+            r.hi1 = cell_rng[2 * (nc - 1) + 1];
+            r.sh1 = -n;
+        } else if (g.periodic && c + 1 >= nc) {
+            r.lo1 = cell_rng[0];
+            r.hi1 = cell_rng[1];
+            r.sh1 = n;
         }
-        const int ilo = cell_rng[2 * ax], ihi = cell_rng[2 * ax + 1];
-        for (int dy = -1; dy <= 1; ++dy) {
-            int ay = cy + dy, shy = 0;
-            if (ay < 0 || ay >= nc) {
-                if (!g.periodic) continue;
-                shy = ay < 0 ? -n : n;
-                ay -= ay < 0 ? -nc : nc;
-            }
-            const int jlo = cell_rng[2 * ay], jhi = cell_rng[2 * ay + 1];
-            for (int dz = -1; dz <= 1; ++dz) {
-                int az = cz + dz, shz = 0;
-                if (az < 0 || az >= nc) {
-                    if (!g.periodic) continue;
-                    shz = az < 0 ? -n : n;
-                    az -= az < 0 ? -nc : nc;
-                }
-                const int klo = cell_rng[2 * az], khi = cell_rng[2 * az + 1];
-                for (int i = ilo; i <= ihi; ++i) {
-                    const int di = si - (i + shx);
-                    for (int j = jlo; j <= jhi; ++j) {
-                        const int dj = sj - (j + shy);
-                        const Real *row = Qs + ((int64_t)i * n + j) * n;
+        return r;
+    };
+    const Runs rx = runs(cx), ry = runs(cy), rz = runs(cz);
+    Real nearv = Real(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int ilo = a ? rx.lo1 : rx.lo0, ihi = a ? rx.hi1 : rx.hi0, shx = a ? rx.sh1 : rx.sh0;
+        for (int i = ilo; i <= ihi; ++i) {
+            const int di = si - (i + shx);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int jlo = b ? ry.lo1 : ry.lo0, jhi = b ? ry.hi1 : ry.hi0, shy = b ? ry.sh1 : ry.sh0;
+                for (int j = jlo; j <= jhi; ++j) {
+                    const int dj = sj - (j + shy);
+                    const int dij = di * di + dj * dj;
+                    const Real *row = Qs + ((int64_t)i * n + j) * n;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int klo = e ? rz.lo1 : rz.lo0, khi = e ? rz.hi1 : rz.hi0;
+                        const int off = sk - (e ? rz.sh1 : rz.sh0);
                         for (int k = klo; k <= khi; ++k) {
-                            const Real qv = row[k];
-                            const int dk = sk - (k + shz);
-                            const int d2 = di * di + dj * dj + dk * dk;
-                            if (d2 == 0 || qv == Real(0)) continue;
-                            const Real inv = d2 < kInvTab ? sInv[d2] : Real(1) / sqrt((Real)d2);
-                            nearv += qv * inv;
+                            const int dk = off - k;
+                            const int d2 = dij + dk * dk;
+                            // 1/sqrt(0) is stored as 0: the site's own occupant drops out
+                            Real inv;
+                            if (d2 < kInvTab)
+                                inv = sInv[d2];
+                            else
+                                inv = Real(1) / sqrt((Real)d2);
+                            nearv += row[k] * inv;
                         }
                     }
                 }
