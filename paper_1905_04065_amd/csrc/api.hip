@@ -500,6 +500,21 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
             }
             c->cell_rng = dalloc<int32_t>(rng.size());
             upload(c->cell_rng, rng.data(), rng.size(), s);
+            // widest run of planes in three consecutive cells: bounds every offset of a near field
+            int span = 0;
+            for (int cc = 0; cc < c->nc; ++cc) {
+                int planes = 0;
+                for (int d = -1; d <= 1; ++d) {
+                    int a2 = cc + d;
+                    if (a2 < 0 || a2 >= c->nc) {
+                        if (c->bc != FMMKMC_PERIODIC) continue;
+                        a2 = (a2 + c->nc) % c->nc;
+                    }
+                    planes += per[a2];
+                }
+                span = std::max(span, planes);
+            }
+            c->near_tab_ok = 3 * (span - 1) * (span - 1) < kInvTab ? 1 : 0;
             c->qsite = dalloc<double>(ns);
             upload(c->qsite, qs.data(), ns, s);
             if (c->prec == FMMKMC_MIXED) {
@@ -567,6 +582,7 @@ Geo make_geo(const fmmkmc_ctx *c)
     g.n = c->lat_n;
     g.periodic = c->bc == FMMKMC_PERIODIC ? 1 : 0;
     g.cap = c->cap;
+    g.tab_ok = c->near_tab_ok;
     return g;
 }
 

@@ -27,7 +27,11 @@ struct Geo {
     int n;         // lattice sites per axis (lattice mode), else 0
     int periodic;  // 1 periodic, 0 free space
     int cap;       // slots per fine cell
+    int tab_ok;    // lattice: every squared site offset of a near field is below kInvTab
 };
+
+// entries of the 1/sqrt(k) table of the lattice near field (integer squared offsets)
+constexpr int kInvTab = 512;
 
 struct Profiler {
     bool on = false;
@@ -69,6 +73,7 @@ struct fmmkmc_ctx {
     bool s2 = false;      // lattice with 2x2x2 sites per fine cell
     bool initialised = false;
     bool dev_ahead = false;  // batched steps moved charges: host mirrors are stale
+    int near_tab_ok = 0;     // lattice: see Geo::tab_ok
     double U = 0;
     std::string err;
     fmmkmc::Profiler prof;

@@ -139,8 +139,7 @@ __host__ __device__ constexpr double csqrt(double x)
     return r;
 }
 
-// 1/sqrt(k) for the squared integer site offsets of the near field
-constexpr int kInvTab = 512;
+// 1/sqrt(k) for the squared integer site offsets of the near field (kInvTab entries)
 struct InvSqrtTab {
     double v[kInvTab];
     constexpr InvSqrtTab() : v{}
@@ -228,16 +227,21 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
                     for (int e = 0; e < 2; ++e) {
                         const int klo = e ? rz.lo1 : rz.lo0, khi = e ? rz.hi1 : rz.hi0;
                         const int off = sk - (e ? rz.sh1 : rz.sh0);
-                        for (int k = klo; k <= khi; ++k) {
-                            const int dk = off - k;
-                            const int d2 = dij + dk * dk;
-                            // 1/sqrt(0) is stored as 0: the site's own occupant drops out
-                            Real inv;
-                            if (d2 < kInvTab)
-                                inv = sInv[d2];
-                            else
-                                inv = Real(1) / sqrt((Real)d2);
-                            nearv += row[k] * inv;
+                        // 1/sqrt(0) is stored as 0: the site's own occupant drops out
+                        if (g.tab_ok) {
+#pragma unroll 4
+                            for (int k = klo; k <= khi; ++k) {
+                                const int dk = off - k;
+                                nearv += row[k] * sInv[dij + dk * dk];
+                            }
+                        } else {
+                            for (int k = klo; k <= khi; ++k) {
+                                const int dk = off - k;
+                                const int d2 = dij + dk * dk;
+                                const Real inv = d2 < kInvTab ? sInv[d2 < kInvTab ? d2 : 0]
+                                                              : Real(1) / sqrt((Real)d2);
+                                nearv += row[k] * inv;
+                            }
                         }
                     }
                 }
