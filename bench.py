@@ -229,7 +229,7 @@ def batch_contexts(precision, p=10, count=256):
     return ctxs, Ns, ns
 
 
-def run_batched(precision, steps, warmup, seed, tune=True):
+def run_batched(precision, steps, warmup, seed, tune=True, keep=False):
     """config-5 steps of all replicas as one captured graph per step"""
     import torch
 
@@ -260,22 +260,30 @@ def run_batched(precision, steps, warmup, seed, tune=True):
     b.set_profiling(False)
     moved_frac = float((moved.cpu().numpy() >= 0).mean())
     b.close()
+    out = dict(ms_per_step=1e3 * wall / steps, slots_per_step=info["slots_per_step"], tuning=info,
+               setup_s=setup_s, phase_us=phases, replicas=R, moved_fraction=moved_frac)
+    if keep:
+        return out, ctxs
     for c in ctxs:
         c.close()
-    return dict(ms_per_step=1e3 * wall / steps, slots_per_step=info["slots_per_step"], tuning=info,
-                setup_s=setup_s, phase_us=phases, replicas=R, moved_fraction=moved_frac)
+    return out
 
 
-def run_unbatched_fp64(steps, seed):
+def run_unbatched_fp64(ctxs, steps, seed):
     """the plain path: each replica stepped through the single-context API
-    (proposal pass, selection on the host from the mask, accept), FP64"""
+    (proposal pass, selection on the host from the mask, accept), FP64; the
+    contexts continue from wherever earlier (batched) steps left them"""
     import torch
-    ctxs, Ns, ns = batch_contexts("fp64")
+    Ns, ns, _ = W.replica_sizes(len(ctxs))
     R = len(ctxs)
     rng = np.random.default_rng(seed)
     bufs = [(torch.empty((c.N, 6), dtype=torch.float64, device="cuda"),
              torch.empty((c.N, 6), dtype=torch.uint8, device="cuda")) for c in ctxs]
-    cur = [W.replica_system(r, Ns[r], ns[r])[0].copy() for r in range(R)]
+    cur = []
+    for r, c in enumerate(ctxs):
+        xyz = c.positions().cpu().numpy()
+        ijk = np.floor(xyz).astype(np.int64)  # unit spacing: site (i+1/2, ...) -> i
+        cur.append((ijk[:, 0] * ns[r] + ijk[:, 1]) * ns[r] + ijk[:, 2])
 
     def one_step(u):
         for r, c in enumerate(ctxs):
@@ -368,9 +376,11 @@ def batched_summary(args):
     log("[batch] mixed")
     mixed = run_batched("mixed", steps, args.warmup, seed)
     log("[batch] fp64")
-    fp64 = run_batched("fp64", steps, args.warmup, seed)
+    fp64, ctxs = run_batched("fp64", steps, args.warmup, seed, keep=True)
     log("[batch] fp64 one replica at a time")
-    plain = run_unbatched_fp64(2, seed)
+    plain = run_unbatched_fp64(ctxs, 2, seed)
+    for c in ctxs:
+        c.close()
     slots = mixed["slots_per_step"]
     return {
         "workload": f"{mixed['replicas']} periodic replicas, N_r log-uniform in [1000, 65536] (sum {slots // 6}), "
