@@ -273,6 +273,8 @@ struct fmmkmc_batch {
     bool mixed = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t aux = nullptr;  // side stream: the F rows run beside the sweep
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<fmmkmc_ctx *> ctx;
     std::vector<int32_t> offsets;
     std::vector<RepDev> host_reps;  // what the device descriptors hold
@@ -352,12 +354,17 @@ void record_step(fmmkmc_batch *b)
     launch_prof(b->prof, s, "b_select", k_b_select, dim3((unsigned)R), dim3(256), 0, b->reps, R, b->count.d,
                 b->counts, b->u, b->step, b->moves);
     launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt);
-    launch_b_frow(b->prof, s, b->reps, R, b->moves, b->nt, b->K);
+    // the F rows depend only on the moves: on the side stream, beside the sweep
+    HIPCHK(hipEventRecord(b->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
+    launch_b_frow(b->prof, b->aux, b->reps, R, b->moves, b->nt, b->K);
+    HIPCHK(hipEventRecord(b->ev_join, b->aux));
     launch_b_sweep(b->prof, s, b->reps, R, b->sweep.d, b->sweep.blocks, b->p, b->moves, b->sweep_block);
     launch_b_path(b->prof, s, b->reps, R, b->path.d, b->path.blocks, b->moves);
     launch_b_book(b->prof, s, b->reps, R, b->moves);
     launch_b_far(b->prof, s, b->reps, R, b->far.d, b->far.blocks, b->cheb_a.d, b->cheb_a.blocks, b->cheb_b.d,
                  b->cheb_b.blocks, b->moves);
+    HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
     launch_prof(b->prof, s, "b_finish", k_b_finish, dim3(1), dim3(256), 0, (const MoveDev *)b->moves, R,
                 (const double *)b->acc, b->U, b->step, b->out_i, b->out_site, b->out_dU);
 }
@@ -376,8 +383,15 @@ void capture(fmmkmc_batch *b)
     const bool was = b->prof.on;
     b->prof.on = false;
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    record_step(b);
     hipGraph_t g = nullptr;
+    try {
+        record_step(b);
+    } catch (...) {
+        (void)hipStreamEndCapture(b->stream, &g);  // leave the stream usable
+        if (g) (void)hipGraphDestroy(g);
+        b->prof.on = was;
+        throw;
+    }
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
     b->prof.on = was;
     HIPCHK(e);
@@ -426,6 +440,11 @@ void release_batch(fmmkmc_batch *b)
         (void)hipEventDestroy(pd.b);
     }
     b->prof.pending.clear();
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
+    b->ev_fork = b->ev_join = nullptr;
+    b->aux = nullptr;
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     b->stream = nullptr;
     b->own_stream = false;
@@ -573,6 +592,9 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             b->own_stream = true;
         }
         const hipStream_t s = b->stream;
+        HIPCHK(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
         std::vector<RepDev> reps(n);
         std::vector<double> U(n);
         b->dU.assign(n, nullptr);
