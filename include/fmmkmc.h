@@ -157,17 +157,36 @@ typedef struct fmmkmc_batch fmmkmc_batch;
 int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *offsets, void *stream,
                         fmmkmc_batch **out);
 
-/* n_steps KMC steps on every replica r.  Step s: dU of every (charge, hop) slot;
- * then the move taken is valid slot number floor(u[s n + r] * V) of the V valid
- * slots in slot order (i * K + k), u uniform in [0, 1) (a selection that does
- * not look at dU; u: n_steps x n DEVICE doubles); then that move is accepted
- * (dU recomputed from the FP64 expansions, every expansion updated, U += dU).
- * A replica with no valid slot does not move.  Outputs (DEVICE arrays of
- * n_steps x n, each may be NULL): moved[s n + r] the charge moved (-1 if none),
- * site[s n + r] its new lattice site (lattice order), dU[s n + r] the accepted
- * dU (NaN if none).  Returns after the steps are complete; the contexts' energies
- * are updated and their single-context calls see the new configuration. */
-int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *moved, int64_t *site, double *dU);
+/* Propensities of the selection (Alg. 1, r = r(dU) per proposed hop):
+ *   kind 0 (the default): 1 for every valid slot, a choice that does not look
+ *          at dU (one uniform per replica and step, no time increment);
+ *   kind 1: nu exp(-beta dU), the Boltzmann factor of the full KMC runs (Sec. 6);
+ *   kind 2: nu min(1, exp(-beta dU)), the Metropolis form.
+ * Kinds 1 and 2 take two uniforms per replica and step and return Delta t.
+ * The exponent -beta dU is capped at 600 (rates stay finite when summed).
+ * Errors: EINVAL (kind not 0..2; for kinds 1, 2: nu <= 0, beta < 0 or either
+ * not finite), EHIP.  The step graph is captured again at the next step. */
+int fmmkmc_batch_set_rates(fmmkmc_batch *b, int kind, double nu, double beta);
+
+/* n_steps KMC steps on every replica r (Alg. 1).  Step s: dU of every
+ * (charge, hop) slot; the propensities r_j of the slots j = i * K + k in slot
+ * order (masked slots: 0), cumulative sums R_j and total Q; the move taken is
+ * the slot with R_{j-1} < T <= R_j, where
+ *   kind 0: T = floor(u V) + 1, V = Q the number of valid slots, i.e. valid
+ *           slot number floor(u V); u = u[s n + r];
+ *   kinds 1, 2: T = Q zeta with zeta = 1 - u[2 (s n + r)], and the time
+ *           increment Delta t = -log(xi) / Q with xi = 1 - u[2 (s n + r) + 1];
+ * u: DEVICE doubles, uniform in [0, 1), n_steps x n (kind 0) or n_steps x n x 2.
+ * Then that move is accepted (dU recomputed from the FP64 expansions, every
+ * expansion updated, U += dU).  A replica with Q = 0 does not move.  Outputs
+ * (DEVICE arrays of n_steps x n, each may be NULL): moved[s n + r] the charge
+ * moved (-1 if none), site[s n + r] its new lattice site (lattice order),
+ * dU[s n + r] the accepted dU (NaN if none), dt[s n + r] Delta t (kinds 1, 2;
+ * +inf if Q = 0; NaN for kind 0).  Returns after the steps are complete; the
+ * contexts' energies are updated and their single-context calls see the new
+ * configuration. */
+int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *moved, int64_t *site, double *dU,
+                      double *dt);
 
 /* Copy replica r's dU and mask of the last proposal pass (N_r x K device arrays;
  * mask may be NULL). */

@@ -66,7 +66,8 @@ def load_library():
         "fmmkmc_last_error": (C.c_char_p, [vp]),
         "fmmkmc_destroy": (i32, [vp]),
         "fmmkmc_batch_create": (i32, [i32, vp, i32, vp, vp, C.POINTER(vp)]),
-        "fmmkmc_batch_step": (i32, [vp, i32, vp, vp, vp, vp]),
+        "fmmkmc_batch_set_rates": (i32, [vp, i32, d, d]),
+        "fmmkmc_batch_step": (i32, [vp, i32, vp, vp, vp, vp, vp]),
         "fmmkmc_batch_proposals": (i32, [vp, i32, vp, vp]),
         "fmmkmc_batch_tune": (i32, [vp, i32]),
         "fmmkmc_batch_info": (i32, [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
@@ -294,17 +295,28 @@ class Batch:
         except Exception:
             pass
 
-    def step(self, u):
-        """len(u) // R steps with the uniforms u (n_steps x R); returns device
-        tensors (moved charge, new site, dU), each n_steps x R."""
+    rate_kind = 0
+
+    def set_rates(self, kind, nu=1.0, beta=1.0):
+        """propensity of a hop: 0 uniform over valid hops, 1 nu exp(-beta dU),
+        2 nu min(1, exp(-beta dU))"""
+        self._check(self._L.fmmkmc_batch_set_rates(self._h, int(kind), float(nu), float(beta)))
+        self.rate_kind = int(kind)
+
+    def step(self, u, with_dt=False):
+        """KMC steps with the uniforms u: n_steps x R (rate kind 0) or
+        n_steps x R x 2 (kinds 1, 2: zeta, xi per replica and step); returns
+        device tensors (moved charge, new site, dU[, dt]), each n_steps x R."""
         torch = self._torch
-        u = torch.as_tensor(u, dtype=torch.float64, device=self.device).reshape(-1, self.R).contiguous()
+        per = 1 if self.rate_kind == 0 else 2
+        u = torch.as_tensor(u, dtype=torch.float64, device=self.device).reshape(-1, self.R * per).contiguous()
         n = u.shape[0]
         moved = torch.empty((n, self.R), dtype=torch.int64, device=self.device)
         site = torch.empty((n, self.R), dtype=torch.int64, device=self.device)
         dU = torch.empty((n, self.R), dtype=torch.float64, device=self.device)
-        self._check(self._L.fmmkmc_batch_step(self._h, n, _ptr(u), _ptr(moved), _ptr(site), _ptr(dU)))
-        return moved, site, dU
+        dt = torch.empty((n, self.R), dtype=torch.float64, device=self.device)
+        self._check(self._L.fmmkmc_batch_step(self._h, n, _ptr(u), _ptr(moved), _ptr(site), _ptr(dU), _ptr(dt)))
+        return (moved, site, dU, dt) if with_dt else (moved, site, dU)
 
     def proposals(self, r):
         """dU and mask (N_r x K device tensors) of replica r's last proposal pass"""

@@ -5,8 +5,9 @@
 // Phases of a step, each one launch over every replica (block ranges per
 // replica, see batch.hpp):
 //   b_site, b_slot      the proposal pass (Sec. 3: dU of every hop)
-//   b_count, b_select   the move: valid slot number floor(u V) in slot order,
-//                       then the accept arguments built on the device
+//   b_count, b_select   the move (Alg. 1): slot j with R_{j-1} < T <= R_j over
+//                       the cumulative propensities in slot order, then the
+//                       accept arguments built on the device
 //   b_move_dU           dU of the move recomputed (footnote to Sec. 3.1)
 //   b_frow              the moved charge's row of the hop table
 //   b_sweep, b_path     every fine-level local expansion, the multipole path
@@ -30,19 +31,40 @@ namespace {
 
 constexpr int kSelChunk = 1024;  // slots per counting block (256 lanes x 4)
 
-// valid slots in each chunk of kSelChunk consecutive slots of a replica
-__global__ __launch_bounds__(256) void k_b_count(const RepDev *__restrict__ reps, int R,
-                                                 const int64_t *__restrict__ base, int32_t *__restrict__ counts)
+// Propensity of a valid slot (Alg. 1: r = r(dU)); masked slots have none.
+//   kind 0: 1 (a uniform choice among the valid slots, which does not look at dU)
+//   kind 1: nu exp(-beta dU), the Boltzmann factor the full KMC runs of Sec. 6 use
+//   kind 2: nu min(1, exp(-beta dU)), the Metropolis form
+// The exponent is capped at 600 so that a sum over any realistic number of
+// slots stays finite.
+struct Rates {
+    int kind;
+    double nu, beta;
+};
+
+__device__ inline double slot_rate(const Rates &rt, uint8_t valid, double dU)
 {
-    __shared__ int red[256];
+    if (!valid) return 0.0;
+    if (rt.kind == 0) return 1.0;
+    const double x = -rt.beta * dU;
+    if (rt.kind == 2) return x >= 0.0 ? rt.nu : rt.nu * exp(x);
+    return rt.nu * exp(x < 600.0 ? x : 600.0);
+}
+
+// summed propensity of each chunk of kSelChunk consecutive slots of a replica
+__global__ __launch_bounds__(256) void k_b_count(const RepDev *__restrict__ reps, int R,
+                                                 const int64_t *__restrict__ base, Rates rt,
+                                                 double *__restrict__ wsum)
+{
+    __shared__ double red[256];
     const int r = find_rep(base, R, blockIdx.x);
     const RepDev &d = reps[r];
     const int64_t S = d.N * d.K, s0 = (blockIdx.x - base[r]) * (int64_t)kSelChunk;
-    int c = 0;
+    double c = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t s = s0 + j * 256 + threadIdx.x;
-        if (s < S && d.mask[s]) ++c;
+        if (s < S) c += slot_rate(rt, d.mask[s], d.dU[s]);
     }
     red[threadIdx.x] = c;
     __syncthreads();
@@ -50,25 +72,27 @@ __global__ __launch_bounds__(256) void k_b_count(const RepDev *__restrict__ reps
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) wsum[blockIdx.x] = red[0];
 }
 
-// exclusive prefix sum over the 256 lanes of a block; *total gets the sum
-__device__ int64_t block_excl_scan(int64_t v, int64_t *sm, int64_t *total)
+// prefix sums over the 256 lanes of a block: lane t covers (*lo, *hi] with
+// *lo the inclusive sum of lane t - 1 (0 for lane 0), so the lanes' intervals
+// tile (0, *total] exactly
+__device__ void block_scan(double v, double *sm, double *lo, double *hi, double *total)
 {
     const int t = threadIdx.x;
     sm[t] = v;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        const int64_t x = t >= off ? sm[t - off] : 0;
+        const double x = t >= off ? sm[t - off] : 0.0;
         __syncthreads();
         sm[t] += x;
         __syncthreads();
     }
-    const int64_t incl = sm[t];
+    *hi = sm[t];
+    *lo = t > 0 ? sm[t - 1] : 0.0;
     *total = sm[255];
     __syncthreads();
-    return incl - v;
 }
 
 // the accept arguments of moving charge i by hop k (the device-side
@@ -147,80 +171,138 @@ __device__ void prepare_move(const RepDev &d, int64_t slot, MoveDev &m)
     b.same_cell = old_cell == new_cell ? 1 : 0;
 }
 
-// one block per replica: the valid slot number floor(u V) in slot order
+// One block per replica: the first slot j (slot order i * K + k) whose
+// cumulative propensity R_j reaches the target T, R_{j-1} < T <= R_j (Alg. 1):
+//   kind 0: T = floor(u V) + 1 with V valid slots (the valid slot number floor(u V));
+//   kinds 1, 2: T = Q zeta with Q the total propensity and zeta = 1 - u in (0, 1].
+// Then the accept arguments of that move.  The chunk sums and the in-chunk
+// scan add in different orders, so a target within rounding of a chunk edge
+// falls back on the chunk's last slot with a propensity.
 __global__ __launch_bounds__(256) void k_b_select(const RepDev *__restrict__ reps, int R,
                                                   const int64_t *__restrict__ cbase,
-                                                  const int32_t *__restrict__ counts, const double *__restrict__ u,
-                                                  const int32_t *__restrict__ step, MoveDev *__restrict__ moves)
+                                                  const double *__restrict__ wsum, Rates rt,
+                                                  const double *__restrict__ u, const int32_t *__restrict__ step,
+                                                  MoveDev *__restrict__ moves, double *__restrict__ Qout)
 {
-    __shared__ int64_t sm[256];
-    __shared__ int64_t s_chunk, s_rank, s_slot;
+    __shared__ double sm[256];
+    __shared__ int64_t s_chunk, s_slot;
+    __shared__ double s_target;
     const int r = blockIdx.x;
     const RepDev &d = reps[r];
     const int t = threadIdx.x;
     const int64_t c0 = cbase[r], nch = cbase[r + 1] - c0;
-    // chunks split into 256 contiguous ranges, one per lane
     const int64_t per = (nch + 255) / 256;
     const int64_t k0 = (int64_t)t * per < nch ? (int64_t)t * per : nch;
     const int64_t k1 = k0 + per < nch ? k0 + per : nch;
-    int64_t mine = 0;
-    for (int64_t k = k0; k < k1; ++k) mine += counts[c0 + k];
-    int64_t V;
-    const int64_t excl = block_excl_scan(mine, sm, &V);
-    if (V == 0) {
+    double mine = 0.0;
+    for (int64_t k = k0; k < k1; ++k) mine += wsum[c0 + k];
+    double lo, hi, Q;
+    block_scan(mine, sm, &lo, &hi, &Q);
+    if (t == 0) Qout[r] = Q;
+    if (!(Q > 0.0)) {
         if (t == 0) moves[r].valid = 0;
         return;  // uniform across the block
     }
-    const double uu = u[(int64_t)(*step) * R + r];
-    int64_t want = (int64_t)floor(uu * (double)V);
-    want = want < 0 ? 0 : (want >= V ? V - 1 : want);
-    if (want >= excl && want < excl + mine) {
-        int64_t acc = excl;
+    const int per_step = rt.kind == 0 ? 1 : 2;  // uniforms per replica and step
+    const double uu = u[((int64_t)(*step) * R + r) * per_step];
+    double T;
+    if (rt.kind == 0) {
+        double want = floor(uu * Q);
+        want = want < 0.0 ? 0.0 : (want > Q - 1.0 ? Q - 1.0 : want);
+        T = want + 1.0;
+    } else {
+        T = Q * (1.0 - uu);
+    }
+    // keep T in (0, Q] whatever u holds (also NaN), so exactly one lane owns it
+    if (!(T > 0.0)) T = __DBL_DENORM_MIN__;
+    if (!(T <= Q)) T = Q;
+    if (t == 0) {
+        s_chunk = -1;
+        s_target = T;
+    }
+    __syncthreads();
+    if (T > lo && T <= hi) {
+        double acc = lo;
+        int64_t last = -1;
         for (int64_t k = k0; k < k1; ++k) {
-            const int c = counts[c0 + k];
-            if (want < acc + c) {
+            const double w = wsum[c0 + k];
+            if (w > 0.0) last = k;
+            if (w > 0.0 && T <= acc + w) {
                 s_chunk = k;
-                s_rank = want - acc;
+                s_target = T - acc;
                 break;
             }
-            acc += c;
+            acc += w;
+        }
+        if (s_chunk < 0) {  // rounding: the target lies past the running sum of this lane's chunks
+            s_chunk = last;
+            s_target = wsum[c0 + last];
         }
     }
     __syncthreads();
+    if (s_chunk < 0) {  // not reached for T in (0, Q]; a guard against reading outside the replica
+        if (t == 0) moves[r].valid = 0;
+        return;
+    }
     // within the chunk: 4 consecutive slots per lane
     const int64_t S = d.N * d.K, b0 = s_chunk * kSelChunk + 4 * t;
-    int cnt = 0;
+    double w4[4], mine2 = 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (b0 + j < S && d.mask[b0 + j]) ++cnt;
-    int64_t tot;
-    const int64_t ex2 = block_excl_scan(cnt, sm, &tot);
-    const int64_t rk = s_rank;
-    if (rk >= ex2 && rk < ex2 + cnt) {
-        int64_t acc = ex2;
+    for (int j = 0; j < 4; ++j) {
+        w4[j] = b0 + j < S ? slot_rate(rt, d.mask[b0 + j], d.dU[b0 + j]) : 0.0;
+        mine2 += w4[j];
+    }
+    double lo2, hi2, tot2;
+    block_scan(mine2, sm, &lo2, &hi2, &tot2);
+    const double T2 = s_target < tot2 ? s_target : tot2;  // rounding at the chunk's end
+    if (t == 0) s_slot = -1;
+    __syncthreads();
+    if (T2 > lo2 && T2 <= hi2) {
+        double acc = lo2;
+        int jl = -1;
         for (int j = 0; j < 4; ++j) {
-            if (b0 + j < S && d.mask[b0 + j]) {
-                if (acc == rk) {
-                    s_slot = b0 + j;
-                    break;
-                }
-                ++acc;
+            if (w4[j] > 0.0) {
+                jl = j;
+                if (T2 <= acc + w4[j]) break;
             }
+            acc += w4[j];
         }
+        s_slot = b0 + jl;
     }
     __syncthreads();
-    if (t == 0) prepare_move(d, s_slot, moves[r]);
+    if (t == 0) {
+        int64_t slot = s_slot;
+        if (slot < 0) {  // rounding: the last slot of the chunk with a propensity
+            for (int64_t e = s_chunk * kSelChunk + kSelChunk - 1; e >= s_chunk * kSelChunk; --e)
+                if (e < S && slot_rate(rt, d.mask[e], d.dU[e]) > 0.0) {
+                    slot = e;
+                    break;
+                }
+        }
+        if (slot >= 0)
+            prepare_move(d, slot, moves[r]);
+        else
+            moves[r].valid = 0;  // not reached: the chunk holds a slot with a propensity
+    }
 }
 
 // U += dU (parts added in order, as the single-context accept does), outputs, next step
 __global__ __launch_bounds__(256) void k_b_finish(const MoveDev *__restrict__ moves, int R,
                                                   const double *__restrict__ acc, double *__restrict__ U,
                                                   int32_t *__restrict__ step, int64_t *__restrict__ out_i,
-                                                  int64_t *__restrict__ out_site, double *__restrict__ out_dU)
+                                                  int64_t *__restrict__ out_site, double *__restrict__ out_dU,
+                                                  Rates rt, const double *__restrict__ u,
+                                                  const double *__restrict__ Q, double *__restrict__ out_dt)
 {
     const int st = *step;
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
         const MoveDev &m = moves[r];
+        // time increment of Alg. 1: -log(xi) / Q with xi = 1 - u in (0, 1]; with no
+        // propensity (Q = 0) no event happens: +inf; kind 0 has no rates: NaN
+        const int64_t o = (int64_t)st * R + r;
+        double dt = __builtin_nan("");
+        if (rt.kind != 0) dt = Q[r] > 0.0 ? -log(1.0 - u[2 * o + 1]) / Q[r] : __builtin_inf();
+        out_dt[o] = dt;
         double dU = __builtin_nan("");
         int64_t i = -1, site = -1;
         if (m.valid) {
@@ -230,7 +312,6 @@ __global__ __launch_bounds__(256) void k_b_finish(const MoveDev *__restrict__ mo
             i = m.i;
             site = m.new_site;
         }
-        const int64_t o = (int64_t)st * R + r;
         out_i[o] = i;
         out_site[o] = site;
         out_dU[o] = dU;
@@ -284,12 +365,14 @@ struct fmmkmc_batch {
     RepDev *reps = nullptr;
     MoveDev *moves = nullptr, *null_moves = nullptr;
     double *acc = nullptr, *U = nullptr;
-    int32_t *step = nullptr, *counts = nullptr;
+    int32_t *step = nullptr;
+    double *wsum = nullptr, *Q = nullptr;  // chunk propensities, total per replica
     std::vector<double *> dU;
     std::vector<uint8_t *> mask;
-    double *u = nullptr;
+    Rates rates{0, 1.0, 1.0};
+    double *u = nullptr;  // uniforms of the steps: 1 (kind 0) or 2 per replica and step
     int64_t *out_i = nullptr, *out_site = nullptr;
-    double *out_dU = nullptr;
+    double *out_dU = nullptr, *out_dt = nullptr;
     int cap_steps = 0;
     // phases
     Phase site, slot, count, sweep, path, far, cheb_a, cheb_b;
@@ -350,9 +433,9 @@ void record_step(fmmkmc_batch *b)
     launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->p, b->mixed);
     launch_b_slot(b->prof, s, b->reps, R, b->slot.d, b->slot.blocks, b->slot_tc);
     launch_prof(b->prof, s, "b_count", k_b_count, dim3((unsigned)b->count.blocks), dim3(256), 0, b->reps, R,
-                b->count.d, b->counts);
+                b->count.d, b->rates, b->wsum);
     launch_prof(b->prof, s, "b_select", k_b_select, dim3((unsigned)R), dim3(256), 0, b->reps, R, b->count.d,
-                b->counts, b->u, b->step, b->moves);
+                b->wsum, b->rates, b->u, b->step, b->moves, b->Q);
     launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt);
     // the F rows depend only on the moves: on the side stream, beside the sweep
     HIPCHK(hipEventRecord(b->ev_fork, s));
@@ -366,7 +449,8 @@ void record_step(fmmkmc_batch *b)
                  b->cheb_b.blocks, b->moves);
     HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
     launch_prof(b->prof, s, "b_finish", k_b_finish, dim3(1), dim3(256), 0, (const MoveDev *)b->moves, R,
-                (const double *)b->acc, b->U, b->step, b->out_i, b->out_site, b->out_dU);
+                (const double *)b->acc, b->U, b->step, b->out_i, b->out_site, b->out_dU, b->rates,
+                (const double *)b->u, (const double *)b->Q, b->out_dt);
 }
 
 void drop_graph(fmmkmc_batch *b)
@@ -409,10 +493,12 @@ void ensure_steps(fmmkmc_batch *b, int n_steps)
     dfree(b->out_i);
     dfree(b->out_site);
     dfree(b->out_dU);
-    b->u = dalloc<double>(m);
+    dfree(b->out_dt);
+    b->u = dalloc<double>(2 * m);
     b->out_i = dalloc<int64_t>(m);
     b->out_site = dalloc<int64_t>(m);
     b->out_dU = dalloc<double>(m);
+    b->out_dt = dalloc<double>(m);
     b->cap_steps = cap;
     drop_graph(b);  // the captured launches hold the old pointers
 }
@@ -426,13 +512,15 @@ void release_batch(fmmkmc_batch *b)
     dfree(b->acc);
     dfree(b->U);
     dfree(b->step);
-    dfree(b->counts);
+    dfree(b->wsum);
+    dfree(b->Q);
     for (auto &p : b->dU) dfree(p);
     for (auto &p : b->mask) dfree(p);
     dfree(b->u);
     dfree(b->out_i);
     dfree(b->out_site);
     dfree(b->out_dU);
+    dfree(b->out_dt);
     for (Phase *ph : {&b->site, &b->slot, &b->count, &b->sweep, &b->path, &b->far, &b->cheb_a, &b->cheb_b})
         dfree(ph->d);
     for (auto &pd : b->prof.pending) {
@@ -642,7 +730,8 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
         set_phase(b->cheb_b, nb, s);
         set_slot_phase(b);
         set_sweep_phase(b);
-        b->counts = dalloc<int32_t>(b->count.blocks);
+        b->wsum = dalloc<double>(b->count.blocks);
+        b->Q = dalloc<double>(n);
         hipLaunchKernelGGL(k_b_null_moves, dim3((n + 63) / 64), dim3(64), 0, s, (const RepDev *)b->reps, n,
                            b->null_moves);
         HIPCHK(hipGetLastError());
@@ -662,7 +751,23 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
     return FMMKMC_OK;
 }
 
-int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *moved, int64_t *site, double *dU)
+int fmmkmc_batch_set_rates(fmmkmc_batch *b, int kind, double nu, double beta)
+{
+    if (!b) return FMMKMC_EINVAL;
+    if (kind < 0 || kind > 2) return bfail(b, FMMKMC_EINVAL, "rate kind must be 0, 1 or 2");
+    if (kind != 0 && !(nu > 0.0 && std::isfinite(nu) && beta >= 0.0 && std::isfinite(beta)))
+        return bfail(b, FMMKMC_EINVAL, "need nu > 0 and beta >= 0, both finite");
+    BATCH_GUARD(b, {
+        HIPCHK(hipSetDevice(b->device));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->rates = Rates{kind, nu, beta};
+        drop_graph(b);  // the captured launches hold the old rate arguments
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *moved, int64_t *site, double *dU,
+                      double *dt)
 {
     if (!b) return FMMKMC_EINVAL;
     if (n_steps < 0 || (n_steps > 0 && !u)) return bfail(b, FMMKMC_EINVAL, "need n_steps >= 0 and u");
@@ -674,7 +779,8 @@ int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *mo
         ensure_steps(b, n_steps);
         const hipStream_t s = b->stream;
         const size_t m = (size_t)n_steps * b->R;
-        HIPCHK(hipMemcpyAsync(b->u, u, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+        const size_t nu = b->rates.kind == 0 ? 1 : 2;
+        HIPCHK(hipMemcpyAsync(b->u, u, sizeof(double) * m * nu, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_b_set_step, dim3(1), dim3(64), 0, s, b->step, 0);
         HIPCHK(hipGetLastError());
         if (b->prof.on) {
@@ -687,6 +793,7 @@ int fmmkmc_batch_step(fmmkmc_batch *b, int n_steps, const double *u, int64_t *mo
         if (moved) HIPCHK(hipMemcpyAsync(moved, b->out_i, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, s));
         if (site) HIPCHK(hipMemcpyAsync(site, b->out_site, sizeof(int64_t) * m, hipMemcpyDeviceToDevice, s));
         if (dU) HIPCHK(hipMemcpyAsync(dU, b->out_dU, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+        if (dt) HIPCHK(hipMemcpyAsync(dt, b->out_dt, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
         std::vector<double> U(b->R);
         HIPCHK(hipMemcpyAsync(U.data(), b->U, sizeof(double) * b->R, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

@@ -176,3 +176,117 @@ def test_single_context_accept_after_batched_steps():
     assert abs(d1 - d2) <= 1e-12 * max(1.0, abs(d2))
     assert c.energy == pytest.approx(ref.energy, rel=1e-12)
     batch.close()
+
+
+def rate_reference(kind, nu, beta, dU, valid):
+    """propensities of Alg. 1 in FP64 numpy, masked slots 0"""
+    r = np.zeros_like(dU)
+    x = -beta * dU[valid]
+    if kind == 1:
+        r[valid] = nu * np.exp(np.minimum(x, 600.0))
+    else:
+        r[valid] = np.where(x >= 0.0, nu, nu * np.exp(x))
+    return r
+
+
+@pytest.mark.parametrize("kind,precision", [(1, "fp64"), (2, "mixed")])
+def test_propensity_weighted_selection(kind, precision):
+    """Alg. 1 on the device: each step's move is the slot j with
+    R_{j-1} < Q zeta <= R_j over the propensities of that step's proposal pass,
+    and Delta t = -log(xi) / Q.  The reference sums the same dU (the batch's
+    own proposals of the step) with numpy; the cumulative sums add in another
+    order, so the chosen slot must hold T within rounding of its interval."""
+    from paper_1905_04065_amd import Batch
+    hops = W.HOPS6
+    K = len(hops)
+    nu, beta = 2.5, 1.7
+    reps = [replica(r, N, precision, 6) for r, N in enumerate(SIZES[:4])]
+    ctxs = [make_ctx(rp) for rp in reps]
+    R = len(reps)
+    batch = Batch(ctxs, hops)
+    batch.set_rates(kind, nu, beta)
+    rng = np.random.default_rng(W.BASE_SEED + 53)
+    curs = [rp["sites"].copy() for rp in reps]
+    n_steps = 10
+    uu = rng.random((n_steps, R, 2))
+    worst_t, worst_dt = 0.0, 0.0
+    for s in range(n_steps):
+        moved, site, dU, dt = (x.cpu().numpy() for x in batch.step(uu[s:s + 1], with_dt=True))
+        for r, rp in enumerate(reps):
+            pdU, pm = batch.proposals(r)  # the pass this step selected from
+            pdU = pdU.cpu().numpy().reshape(-1)
+            v = pm.cpu().numpy().reshape(-1).astype(bool)
+            t, vv = W.lattice_targets(curs[r], rp["n"], hops, True)
+            assert np.array_equal(v, vv.reshape(-1))
+            rates = rate_reference(kind, nu, beta, pdU, v)
+            cum = np.cumsum(rates)
+            Q = cum[-1]
+            T = Q * (1.0 - uu[s, r, 0])
+            i = int(moved[0, r])
+            assert i >= 0
+            j = [slot for slot in range(i * K, i * K + K)
+                 if v[slot] and t.reshape(-1)[slot] == site[0, r]]
+            assert len(j) == 1, (s, r, i, site[0, r])
+            j = j[0]
+            lo, hi = (cum[j - 1] if j > 0 else 0.0), cum[j]
+            slack = 1e-12 * Q
+            assert lo - slack < T <= hi + slack, (s, r, j, lo, T, hi)
+            worst_t = max(worst_t, max(lo - T, T - hi, 0.0) / Q)
+            dt_ref = -math.log(1.0 - uu[s, r, 1]) / Q
+            worst_dt = max(worst_dt, abs(dt[0, r] - dt_ref) / dt_ref)
+            assert dt[0, r] == pytest.approx(dt_ref, rel=1e-12)
+            # the accepted dU is the selected proposal's, recomputed in FP64 (relative
+            # error on the scale of the pass's dU, as in the parity tests)
+            tol = 1e-10 if precision == "fp64" else 1e-5
+            assert abs(dU[0, r] - pdU[j]) <= tol * max(abs(pdU[j]), float(np.mean(np.abs(pdU[v]))))
+            curs[r][i] = site[0, r]
+    for r in range(R):
+        np.testing.assert_allclose(ctxs[r].positions().cpu().numpy(), W.site_xyz(curs[r], reps[r]["n"]),
+                                   rtol=0, atol=1e-12)
+    print(f"  kind {kind}, {precision}: {n_steps} steps x {R} replicas, T outside its interval by "
+          f"{worst_t:.2e} Q at most, dt within {worst_dt:.2e}", flush=True)
+    batch.close()
+
+
+def test_rates_at_zero_beta_are_a_uniform_choice():
+    """beta = 0: every valid hop has propensity nu, so T = V nu zeta picks valid
+    slot number ceil(V zeta) - 1 and Delta t = -log(xi) / (nu V) (closed form;
+    the partial sums nu k are exact in FP64)"""
+    from paper_1905_04065_amd import Batch
+    hops = W.HOPS6
+    K = len(hops)
+    reps = [replica(r, N, "fp64", 6) for r, N in enumerate(SIZES[:3])]
+    ctxs = [make_ctx(rp) for rp in reps]
+    R = len(reps)
+    batch = Batch(ctxs, hops)
+    batch.set_rates(1, 3.0, 0.0)
+    uu = np.random.default_rng(W.BASE_SEED + 54).random((4, R, 2))
+    curs = [rp["sites"].copy() for rp in reps]
+    for s in range(4):
+        moved, site, dU, dt = (x.cpu().numpy() for x in batch.step(uu[s:s + 1], with_dt=True))
+        for r, rp in enumerate(reps):
+            t, v = W.lattice_targets(curs[r], rp["n"], hops, True)
+            vs = np.nonzero(v.reshape(-1))[0]
+            V = len(vs)
+            T = (3.0 * V) * (1.0 - uu[s, r, 0])
+            k = int(np.searchsorted(3.0 * np.arange(1, V + 1), T, side="left"))  # first R_k >= T
+            slot = vs[k]
+            assert moved[0, r] == slot // K and site[0, r] == t.reshape(-1)[slot], (s, r)
+            assert dt[0, r] == pytest.approx(-math.log(1.0 - uu[s, r, 1]) / (3.0 * V), rel=1e-13)
+            curs[r][slot // K] = site[0, r]
+    # back to kind 0: one uniform per step, no time increment
+    batch.set_rates(0)
+    moved, site, dU, dt = (x.cpu().numpy() for x in batch.step(np.full((1, R), 0.5), with_dt=True))
+    assert np.all(np.isnan(dt)) and np.all(moved >= 0)
+    batch.close()
+
+
+def test_set_rates_rejects_bad_arguments():
+    from paper_1905_04065_amd import Batch, FmmKmcError
+    rp = replica(0, 600, "fp64", 6)
+    batch = Batch([make_ctx(rp)], W.HOPS6)
+    for args in [(3, 1.0, 1.0), (-1, 1.0, 1.0), (1, 0.0, 1.0), (1, 1.0, -1.0), (2, float("inf"), 1.0),
+                 (1, 1.0, float("nan"))]:
+        with pytest.raises(FmmKmcError):
+            batch.set_rates(*args)
+    batch.close()
