@@ -433,23 +433,26 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
             az += az < 0 ? nc : (az >= nc ? -nc : 0);
             return cell_id(nc, ax, ay, az) * 8;
         };
-        // a cell's 8 charges are contiguous and 64-byte aligned: vector loads
+        // a cell's 8 charges are contiguous and 64-byte aligned: vector loads.
+        // The wrapped address is always inside the table, so the loads are
+        // unconditional (no branch per load) and an absent cell is zeroed after.
         auto load8 = [&](int64_t base, bool ok, Real *o) {
             if constexpr (MIXED) {
                 const float4 *q4 = (const float4 *)(Qs + base);
-                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                const float4 a0 = ok ? q4[0] : z4, a1 = ok ? q4[1] : z4;
+                const float4 a0 = q4[0], a1 = q4[1];
                 o[0] = a0.x, o[1] = a0.y, o[2] = a0.z, o[3] = a0.w;
                 o[4] = a1.x, o[5] = a1.y, o[6] = a1.z, o[7] = a1.w;
             } else {
                 const double2 *q2 = (const double2 *)(Qs + base);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const double2 a = ok ? q2[t] : make_double2(0.0, 0.0);
+                    const double2 a = q2[t];
                     o[2 * t] = a.x;
                     o[2 * t + 1] = a.y;
                 }
             }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) o[v] = ok ? o[v] : Real(0);
         };
         Real near_[8] = {};
         Real qn[8];
