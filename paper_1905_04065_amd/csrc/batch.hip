@@ -29,7 +29,8 @@ using namespace fmmkmc;
 
 namespace {
 
-constexpr int kSelChunk = 1024;  // slots per counting block (256 lanes x 4)
+constexpr int kSelLane = 32;                // consecutive slots per lane
+constexpr int kSelChunk = 256 * kSelLane;  // slots per counting block
 
 // Propensity of a valid slot (Alg. 1: r = r(dU)); masked slots have none.
 //   kind 0: 1 (a uniform choice among the valid slots, which does not look at dU)
@@ -51,7 +52,46 @@ __device__ inline double slot_rate(const Rates &rt, uint8_t valid, double dU)
     return rt.nu * exp(x < 600.0 ? x : 600.0);
 }
 
+// Propensities of the kSelLane slots b0, b0 + 1, ... of a replica (0 past its
+// end).  Kind 0 reads only the mask; whole runs use vector loads (the batch's
+// own dU and mask arrays, 256-byte aligned, and b0 a multiple of kSelLane).
+__device__ inline void lane_rates(const RepDev &d, const Rates &rt, int64_t b0, double (&w)[kSelLane])
+{
+    const int64_t S = d.N * d.K;
+    uint8_t v[kSelLane];
+    double u[kSelLane];
+    if (b0 + kSelLane <= S) {
+        const uint4 *m4 = (const uint4 *)(d.mask + b0);
+#pragma unroll
+        for (int h = 0; h < kSelLane / 16; ++h) {
+            const uint4 x = m4[h];
+            const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[16 * h + k] = (uint8_t)(wd[k >> 2] >> (8 * (k & 3)));
+        }
+        if (rt.kind != 0) {
+            const double2 *u2 = (const double2 *)(d.dU + b0);
+#pragma unroll
+            for (int h = 0; h < kSelLane / 2; ++h) {
+                const double2 x = u2[h];
+                u[2 * h] = x.x;
+                u[2 * h + 1] = x.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kSelLane; ++k) {
+            const bool in = b0 + k < S;
+            v[k] = in ? d.mask[b0 + k] : 0;
+            u[k] = (in && rt.kind != 0) ? d.dU[b0 + k] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kSelLane; ++k) w[k] = slot_rate(rt, v[k], rt.kind != 0 ? u[k] : 0.0);
+}
+
 // summed propensity of each chunk of kSelChunk consecutive slots of a replica
+// (each lane adds its kSelLane slots in order, then a tree over the lanes)
 __global__ __launch_bounds__(256) void k_b_count(const RepDev *__restrict__ reps, int R,
                                                  const int64_t *__restrict__ base, Rates rt,
                                                  double *__restrict__ wsum)
@@ -59,17 +99,16 @@ __global__ __launch_bounds__(256) void k_b_count(const RepDev *__restrict__ reps
     __shared__ double red[256];
     const int r = find_rep(base, R, blockIdx.x);
     const RepDev &d = reps[r];
-    const int64_t S = d.N * d.K, s0 = (blockIdx.x - base[r]) * (int64_t)kSelChunk;
+    const int64_t b0 = (blockIdx.x - base[r]) * (int64_t)kSelChunk + (int64_t)threadIdx.x * kSelLane;
+    double w[kSelLane];
+    lane_rates(d, rt, b0, w);
     double c = 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t s = s0 + j * 256 + threadIdx.x;
-        if (s < S) c += slot_rate(rt, d.mask[s], d.dU[s]);
-    }
+    for (int k = 0; k < kSelLane; ++k) c += w[k];
     red[threadIdx.x] = c;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
     if (threadIdx.x == 0) wsum[blockIdx.x] = red[0];
@@ -244,14 +283,13 @@ __global__ __launch_bounds__(256) void k_b_select(const RepDev *__restrict__ rep
         if (t == 0) moves[r].valid = 0;
         return;
     }
-    // within the chunk: 4 consecutive slots per lane
-    const int64_t S = d.N * d.K, b0 = s_chunk * kSelChunk + 4 * t;
-    double w4[4], mine2 = 0.0;
+    // within the chunk: kSelLane consecutive slots per lane, added in the same
+    // order as in k_b_count
+    const int64_t b0 = s_chunk * kSelChunk + (int64_t)t * kSelLane;
+    double w[kSelLane], mine2 = 0.0;
+    lane_rates(d, rt, b0, w);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        w4[j] = b0 + j < S ? slot_rate(rt, d.mask[b0 + j], d.dU[b0 + j]) : 0.0;
-        mine2 += w4[j];
-    }
+    for (int k = 0; k < kSelLane; ++k) mine2 += w[k];
     double lo2, hi2, tot2;
     block_scan(mine2, sm, &lo2, &hi2, &tot2);
     const double T2 = s_target < tot2 ? s_target : tot2;  // rounding at the chunk's end
@@ -260,12 +298,17 @@ __global__ __launch_bounds__(256) void k_b_select(const RepDev *__restrict__ rep
     if (T2 > lo2 && T2 <= hi2) {
         double acc = lo2;
         int jl = -1;
-        for (int j = 0; j < 4; ++j) {
-            if (w4[j] > 0.0) {
-                jl = j;
-                if (T2 <= acc + w4[j]) break;
+#pragma unroll
+        for (int k = 0; k < kSelLane; ++k) {
+            if (w[k] > 0.0 && jl < 0) {
+                if (T2 <= acc + w[k]) jl = k;
             }
-            acc += w4[j];
+            acc += w[k];
+        }
+        if (jl < 0) {  // rounding: the last slot of this lane with a propensity
+#pragma unroll
+            for (int k = 0; k < kSelLane; ++k)
+                if (w[k] > 0.0) jl = k;
         }
         s_slot = b0 + jl;
     }
@@ -273,8 +316,9 @@ __global__ __launch_bounds__(256) void k_b_select(const RepDev *__restrict__ rep
     if (t == 0) {
         int64_t slot = s_slot;
         if (slot < 0) {  // rounding: the last slot of the chunk with a propensity
+            const int64_t S = d.N * d.K;
             for (int64_t e = s_chunk * kSelChunk + kSelChunk - 1; e >= s_chunk * kSelChunk; --e)
-                if (e < S && slot_rate(rt, d.mask[e], d.dU[e]) > 0.0) {
+                if (e < S && slot_rate(rt, d.mask[e], rt.kind != 0 ? d.dU[e] : 0.0) > 0.0) {
                     slot = e;
                     break;
                 }

@@ -377,7 +377,8 @@ __global__ __launch_bounds__(256) void k_b_sweep(const RepDev *__restrict__ reps
     const RepDev &d = reps[r];
     const int64_t cell = (blockIdx.x - base[r]) * blockDim.x + threadIdx.x;
     if (cell >= d.M) return;
-    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, mv.mv, d.psi, d.psi32);
+    const Move m = mv.mv;  // a copy: the source loop then reads registers, not the descriptor in memory
+    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, m, d.psi, d.psi32);
 }
 
 __global__ void k_b_path(const RepDev *__restrict__ reps, int R, const int64_t *__restrict__ base,
