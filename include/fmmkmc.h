@@ -214,6 +214,61 @@ const char *fmmkmc_batch_last_error(fmmkmc_batch *b);
 /* Free the batch (not its contexts). */
 int fmmkmc_batch_destroy(fmmkmc_batch *b);
 
+/* ---- slab between grounded plates ---------------------------------------
+ * Dirichlet boundaries of Sec. 2.2.2: the potential is zero on the planes
+ * z = 0 and z = a/2 (the plates); x and y are periodic with period a; a
+ * uniform external field E_z along z (Sec. 6.3: an applied potential
+ * difference) adds -E_z q z to the energy of each charge.  As in the paper, the
+ * slab is extended by its first mirror image (charge -q at (x, y, a - z)) and
+ * the doubled system is treated with the periodic algorithm (conducting
+ * boundary), whose potential vanishes on both planes by symmetry.  Energies are
+ * those of the physical charges: half the periodic energy of the doubled
+ * system plus the field term.  A hop moves a charge and its mirror together;
+ * its dU is (dU_i + dU_m + X) / 2 - E_z q dz, with dU_i and dU_m the periodic
+ * single-move values (each with the partner at its old place) and X the pair
+ * correction q_i q_m [G(r_i'-r_m') - G(r_i'-r_m) - G(r_i-r_m') + G(r_i-r_m)],
+ * G the periodic pair potential, tabulated per (site height, hop) with an Ewald
+ * sum.  Lattice proposals only; slabs do not join batches. */
+typedef struct fmmkmc_slab fmmkmc_slab;
+
+/* prm as for fmmkmc_create (bc is ignored: the doubled system is periodic;
+ * lattice_n must be even and > 0, levels >= 3); n physical charges at HOST
+ * positions xyz (n x 3, lattice sites with 0 <= z < a/2) with HOST charges q
+ * (any total charge); ez: the field E_z.  Errors: EINVAL, EDOMAIN (a charge
+ * outside 0 <= z < a/2), and those of fmmkmc_create. */
+int fmmkmc_slab_create(const fmmkmc_params *prm, int64_t n, const double *xyz, const double *q, double ez,
+                       fmmkmc_slab **out);
+
+/* Build the expansions of the doubled system; *U_out (host, may be NULL) gets
+ * the energy of the physical charges. */
+int fmmkmc_slab_initialise(fmmkmc_slab *s, double *U_out);
+
+/* dU of every hop of every physical charge, as fmmkmc_propose_lattice (K x 3
+ * HOST offsets in -1..1, DEVICE dU and mask of n x K).  The hop set must be
+ * closed under (dx, dy, dz) -> (dx, dy, -dz).  A hop is masked (NaN, mask 0)
+ * when its target is occupied or lies outside 0 <= z < a/2 (hops do not wrap
+ * in z); x and y wrap.  Errors: EINVAL, ESTATE, EHIP. */
+int fmmkmc_slab_propose_lattice(fmmkmc_slab *s, int K, const int32_t *offsets, double *dU, uint8_t *mask);
+
+/* Move physical charge i to new_xyz (host, a free lattice site with
+ * 0 <= z < a/2) together with its mirror; *dU_out (host) gets the dU of the
+ * move, recomputed on the FP64 path.  Errors: as fmmkmc_accept, EDOMAIN for a
+ * target outside the slab; if the mirror's move fails after the charge moved,
+ * the slab must be initialised again (ESTATE until then). */
+int fmmkmc_slab_accept(fmmkmc_slab *s, int64_t i, const double new_xyz[3], double *dU_out);
+
+/* Energy of the physical charges (host). */
+int fmmkmc_slab_energy(fmmkmc_slab *s, double *U);
+
+/* Positions of the physical charges (n x 3 DEVICE array). */
+int fmmkmc_slab_positions(fmmkmc_slab *s, double *xyz);
+
+/* Text of the last error on this slab (NULL: of the last failed create). */
+const char *fmmkmc_slab_last_error(fmmkmc_slab *s);
+
+/* Free the slab and its doubled system. */
+int fmmkmc_slab_destroy(fmmkmc_slab *s);
+
 #ifdef __cplusplus
 }
 #endif

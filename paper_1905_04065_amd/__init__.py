@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Batch", "Context", "FmmKmcError", "library_path", "load_library"]
+__all__ = ["Batch", "Context", "FmmKmcError", "Slab", "library_path", "load_library"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -75,6 +75,14 @@ def load_library():
         "fmmkmc_batch_kernel_time": (i32, [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64)]),
         "fmmkmc_batch_last_error": (C.c_char_p, [vp]),
         "fmmkmc_batch_destroy": (i32, [vp]),
+        "fmmkmc_slab_create": (i32, [C.POINTER(_Params), i64, vp, vp, d, C.POINTER(vp)]),
+        "fmmkmc_slab_initialise": (i32, [vp, C.POINTER(d)]),
+        "fmmkmc_slab_propose_lattice": (i32, [vp, i32, vp, vp, vp]),
+        "fmmkmc_slab_accept": (i32, [vp, i64, vp, C.POINTER(d)]),
+        "fmmkmc_slab_energy": (i32, [vp, C.POINTER(d)]),
+        "fmmkmc_slab_positions": (i32, [vp, vp]),
+        "fmmkmc_slab_last_error": (C.c_char_p, [vp]),
+        "fmmkmc_slab_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -343,3 +351,81 @@ class Batch:
         ms, n = C.c_double(), C.c_int64()
         self._check(self._L.fmmkmc_batch_kernel_time(self._h, name.encode(), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+class Slab:
+    """Charges between two grounded plates (potential 0 at z = 0 and z = a/2),
+    periodic in x and y, in a uniform field ez along z (Sec. 2.2.2 Dirichlet
+    boundaries, by the first mirror image and the periodic algorithm)."""
+
+    def __init__(self, xyz, q, a, levels, order, lattice_n, ez=0.0, precision="fp64", cell_capacity=0, device=0,
+                 stream=None):
+        torch = _torch()
+        self._L = load_library()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        xyz = _host_f64(xyz, (-1, 3))
+        q = _host_f64(q, (-1,))
+        if len(q) != len(xyz):
+            raise ValueError("xyz and q lengths differ")
+        self.N = len(q)
+        prm = _Params(float(a), 1, int(levels), int(order), 1 if precision == "mixed" else 0, int(lattice_n),
+                      int(cell_capacity), int(device), C.c_void_p(stream.cuda_stream))
+        h = C.c_void_p()
+        rc = self._L.fmmkmc_slab_create(C.byref(prm), self.N, xyz.ctypes.data_as(C.c_void_p),
+                                        q.ctypes.data_as(C.c_void_p), float(ez), C.byref(h))
+        if rc != OK:
+            raise FmmKmcError(rc, self._L.fmmkmc_slab_last_error(None).decode())
+        self._h = h
+        self.a, self.lattice_n, self.ez = float(a), int(lattice_n), float(ez)
+
+    def _check(self, rc):
+        if rc != OK:
+            raise FmmKmcError(rc, self._L.fmmkmc_slab_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fmmkmc_slab_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def initialise(self):
+        U = C.c_double()
+        self._check(self._L.fmmkmc_slab_initialise(self._h, C.byref(U)))
+        return U.value
+
+    def propose_lattice(self, offsets):
+        """dU and mask (N x K device tensors) of every hop of every charge"""
+        torch = _torch()
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+        K = off.shape[0]
+        dU = torch.empty((self.N, K), dtype=torch.float64, device=self.device)
+        mask = torch.empty((self.N, K), dtype=torch.uint8, device=self.device)
+        self._check(self._L.fmmkmc_slab_propose_lattice(self._h, K, off.ctypes.data_as(C.c_void_p), _ptr(dU),
+                                                        _ptr(mask)))
+        return dU, mask
+
+    def accept(self, i, new_xyz):
+        p = np.ascontiguousarray(np.asarray(new_xyz, dtype=np.float64).reshape(3))
+        d = C.c_double()
+        self._check(self._L.fmmkmc_slab_accept(self._h, int(i), p.ctypes.data_as(C.c_void_p), C.byref(d)))
+        return d.value
+
+    @property
+    def energy(self):
+        U = C.c_double()
+        self._check(self._L.fmmkmc_slab_energy(self._h, C.byref(U)))
+        return U.value
+
+    def positions(self):
+        torch = _torch()
+        out = torch.empty((self.N, 3), dtype=torch.float64, device=self.device)
+        self._check(self._L.fmmkmc_slab_positions(self._h, _ptr(out)))
+        return out
