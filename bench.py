@@ -386,6 +386,81 @@ def roofline_entry(kernel, kt, n, N, K, p, precision, copy_gbs, traffic):
     return e
 
 
+def run_slab(steps, warmup, seed, precision="fp64", n=128, N=500000, L=7, p=12, ez=0.1):
+    """Charges between grounded plates (mirror images, Sec. 2.2.2) in a uniform
+    field: N physical charges on the lower half of the n^3 lattice (50 %
+    occupancy; the doubled system has the size of the periodic workload), 26
+    hops, one accepted move (a charge and its mirror) per step."""
+    import torch
+
+    from paper_1905_04065_amd import Slab
+
+    rng = np.random.default_rng(seed)
+    half = n // 2
+    sites = rng.choice(n * n * half, N, replace=False)
+    ijk = np.stack([sites // (n * half), (sites // half) % n, sites % half], 1)
+    q = np.where(np.arange(N) < N // 2, 1.0, -1.0)
+    rng.shuffle(q)
+    hops = W.HOPS26
+    K = len(hops)
+    log(f"[slab] create n={n} N={N} (doubled {2 * N}) L={L} p={p} K={K}")
+    t0 = time.perf_counter()
+    s = Slab((ijk + 0.5).astype(np.float64), q, a=float(n), levels=L, order=p, lattice_n=n, ez=ez,
+             precision=precision)
+    s.initialise()
+    dU, mask = s.propose_lattice(hops)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    occ = set(map(tuple, ijk))
+    cur = ijk.copy()
+
+    def choose():
+        while True:
+            i = int(rng.integers(N))
+            t = cur[i] + hops[int(rng.integers(K))]
+            t[0] %= n
+            t[1] %= n
+            if 0 <= t[2] < half and tuple(t) not in occ:
+                return i, t
+
+    def move(i, t):
+        s.accept(i, t + 0.5)
+        occ.discard(tuple(cur[i]))
+        occ.add(tuple(t))
+        cur[i] = t
+
+    def step():
+        s.propose_lattice(hops)
+        move(*choose())
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    step_ms = 1e3 * (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dU, mask = s.propose_lattice(hops)
+    torch.cuda.synchronize()
+    propose_us = 1e6 * (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        move(*choose())
+    torch.cuda.synchronize()
+    commit_us = 1e6 * (time.perf_counter() - t0) / steps
+    valid = int(mask.sum().item())
+    s.close()
+    slots = N * K
+    return {"workload": f"slab between grounded plates: N={N} +-1 charges on the lower half of a {n}^3 lattice "
+                        f"(doubled by mirror images to {2 * N}), field E_z={ez}, {K} hops, L={L}, p={p}, {precision}, "
+                        "one accepted move (charge and mirror) per step, host-driven",
+            "proposals_per_s": slots / (step_ms / 1e3), "ms_per_step": step_ms, "slots_per_step": slots,
+            "valid_slots": valid, "propose_us": propose_us, "commit_us": commit_us, "setup_s": setup_s}
+
+
 def batched_summary(args):
     """256 replicas, p = 10, 6 hops, periodic: mixed and FP64 batched (graph
     steps) against the plain FP64 path (one replica at a time, host selection)"""
@@ -421,7 +496,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the 1 GiB device copy used to calibrate rocprofv3 byte counters")
     ap.add_argument("--quick", action="store_true", help="small periodic system (64^3, N=1e5, L=6)")
-    ap.add_argument("--skip-batch", action="store_true", help="leave out the batched-replica workload")
+    ap.add_argument("--skip-batch", action="store_true",
+                    help="leave out the batched-replica and grounded-slab workloads")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-replica workload (JSON to stdout)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -507,6 +583,7 @@ def main():
                         "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"]}
     if not args.skip_batch:
         out["batched"] = batched_summary(args)
+        out["slab"] = run_slab(max(args.steps, 5), args.warmup, W.BASE_SEED + 6)
     if not args.skip_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(n, N, L, p, hops, seed)
