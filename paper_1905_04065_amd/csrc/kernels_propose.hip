@@ -346,14 +346,18 @@ __host__ __device__ constexpr int s2_d2(int u, int nb, int v)
 // The two halves of the work have different shapes: the class sums stream
 // (p+1)^2 coefficients per cell from HBM, the near field walks 27 neighbour
 // cells through L2.  Fused in one lane they need the registers of both and run
-// at one wave per SIMD; here waves 0-1 of a block do the class sums of its 128
-// cells and waves 2-3 the near field and far-field sites of the same cells, so
-// a wave holds the registers of one half only and both kinds of load are in
-// flight on a CU at once.  Results meet in LDS and all waves write the block's
-// 1024 sites contiguously.
-constexpr int S2_CELLS = 128;  // cells per block
+// at one wave per SIMD; here half of a block's NW waves do the class sums of
+// its 32 NW cells and the other half the near field and far-field sites of the
+// same cells, so a wave holds the registers of one half only and both kinds of
+// load are in flight on a CU at once.  Results meet in LDS and all waves write
+// the block's sites contiguously.  With NW = 8 the class-sum waves are 0, 1, 6,
+// 7 and the near-field waves 2..5: the waves of a block go to the CU's four
+// SIMDs in turn, so every SIMD gets one of each (with NW = 4, waves 0-1 and
+// 2-3, the near field sits on two SIMDs only; 8 waves measured 10 % faster).
+template <int NW>
+constexpr int s2_cells() { return 32 * NW; }  // cells per block
 
-template <int P, bool MIXED>
+template <int P, bool MIXED, int NW>
 __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
                                              const float *__restrict__ psi32, const double *__restrict__ qsite,
                                              const float *__restrict__ qsite32,
@@ -368,17 +372,21 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
     // neighbours, [nb][u][v], unit spacing
     __shared__ Real sT[27 * 64];
     // per cell and site: local-expansion part, near + far-field part (row of 9: no bank conflicts)
-    __shared__ double sFar[S2_CELLS * 9], sNear[S2_CELLS * 9];
+    constexpr int CELLS = s2_cells<NW>();
+    __shared__ double sFar[CELLS * 9], sNear[CELLS * 9];
     for (int e = threadIdx.x; e < 27 * 64; e += blockDim.x) {
         const int nb = e / 64, u = (e / 8) % 8, v = e % 8;
         sT[e] = (Real)IS.v[s2_d2(u, nb, v)];
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6;
-    const int lc = (wave & 1) * 64 + (threadIdx.x & 63);
-    const int64_t c0 = blk * S2_CELLS, cell = c0 + lc;
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves per block");
+    const bool class_wave = wave < 2 || (NW == 8 && wave >= 6);
+    const int ci = wave < 2 ? wave : (class_wave ? wave - 4 : wave - 2);  // index within the role
+    const int lc = ci * 64 + (threadIdx.x & 63);
+    const int64_t c0 = blk * CELLS, cell = c0 + lc;
     const int nc = g.nc;
-    if (wave < 2) {
+    if (class_wave) {
         if (cell < M) {
             const Real *Ps = MIXED ? (const Real *)psi32 : (const Real *)psi;
             // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part
@@ -502,7 +510,7 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
         for (int u = 0; u < 8; ++u) sNear[lc * 9 + u] = (double)near_[u] * inv_h + fs[u];
     }
     __syncthreads();
-    const int nsite = (int)((M - c0 < S2_CELLS ? M - c0 : S2_CELLS) * 8);
+    const int nsite = (int)((M - c0 < CELLS ? M - c0 : CELLS) * 8);
     for (int e = threadIdx.x; e < nsite; e += blockDim.x) {
         const int l = e >> 3, u = e & 7;
         const double phi = sFar[l * 9 + u] + sNear[l * 9 + u];
@@ -513,7 +521,7 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
 }
 
 template <int P, bool MIXED>
-__global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const double *__restrict__ psi,
+__global__ __launch_bounds__(512) void k_site_phi_s2(Geo g, int64_t M, const double *__restrict__ psi,
                                                      const float *__restrict__ psi32,
                                                      const double *__restrict__ qsite,
                                                      const float *__restrict__ qsite32,
@@ -521,20 +529,20 @@ __global__ __launch_bounds__(256) void k_site_phi_s2(Geo g, int64_t M, const dou
                                                      const double *__restrict__ Bz, const double *__restrict__ Tax,
                                                      double *__restrict__ phisite, double *__restrict__ phi_r)
 {
-    site_s2_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, qsite, qsite32, site_rank, Bz, Tax, phisite, phi_r);
+    site_s2_body<P, MIXED, 8>(blockIdx.x, g, M, psi, psi32, qsite, qsite32, site_rank, Bz, Tax, phisite, phi_r);
 }
 
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
 {
     const bool mixed = c->prec == FMMKMC_MIXED;
     if (c->s2) {
-        dim3 grid((unsigned)((c->M + S2_CELLS - 1) / S2_CELLS));
+        dim3 grid((unsigned)((c->M + s2_cells<8>() - 1) / s2_cells<8>()));
         if (mixed) {
-            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, true>, grid, dim3(256), g, c->M,
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, true>, grid, dim3(512), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->qsite, c->qsite32, c->site_rank, c->far.Bz,
                                            c->far.Tax, c->phisite, c->phi_r));
         } else {
-            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, false>, grid, dim3(256), g, c->M,
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, false>, grid, dim3(512), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->qsite, c->qsite32, c->site_rank, c->far.Bz,
                                            c->far.Tax, c->phisite, c->phi_r));
         }
@@ -1240,7 +1248,7 @@ __global__ __launch_bounds__(256) void k_b_site(const RepDev *__restrict__ reps,
     const RepDev &d = reps[r];
     const int64_t blk = blockIdx.x - base[r];
     if (d.s2)
-        site_s2_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
+        site_s2_body<P, MIXED, 4>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
                                d.phisite, d.phi_r);
     else
         site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.qsite, d.qsite32, d.cell_rng,
