@@ -813,18 +813,17 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
         // after the commit kernels are queued behind it (one synchronisation per accept)
         double *dUd = c->acc_buf;
         launch_move_dU(c, g, i, np, dUd);
-        // the moved charge's row of the lattice proposal table depends only on
-        // its new site: computed on the side stream while the sweep runs, after
-        // every earlier proposal (which reads the table) has finished
+        // The work beside the sweep goes to the side stream, after dU of the
+        // move and every earlier proposal (they read the old state): the moved
+        // charge's row of the lattice proposal table (it depends only on the new
+        // site), the multipole path, the bookkeeping and the far-field refresh.
+        // None of it touches the fine-level expansions or what the sweep reads.
         const bool need_row = c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty();
         const int Krow = (int)c->F_offsets.size() / 3;
         bool row_launched = false;
-        if (need_row) {
-            HIPCHK(hipEventRecord(c->ev_fork, c->stream));
-            HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-            row_launched = launch_f_row1(c, g, Krow, c->hrank[i], new_site, c->aux);
-            if (row_launched) HIPCHK(hipEventRecord(c->ev_join, c->aux));
-        }
+        HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+        HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        if (need_row) row_launched = launch_f_row1(c, g, Krow, c->hrank[i], new_site, c->aux);
         // C2 + C3
         CommitArgs a;
         a.i = i;
@@ -858,8 +857,10 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
             a.new_ijk = pack_ijk(c, new_site);
             a.rank = c->hrank[i];
         }
-        launch_commit(c, g, a);
-        if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c);
+        launch_commit(c, g, a, c->aux);
+        if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c, c->aux);
+        HIPCHK(hipEventRecord(c->ev_join, c->aux));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
         // host mirrors
         c->hx[i] = np[0];
         c->hy[i] = np[1];
@@ -881,12 +882,7 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
             c->hsite_charge[new_site] = (int32_t)i;
             c->hsite[i] = (int32_t)new_site;
         }
-        if (need_row) {
-            if (row_launched)
-                HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
-            else
-                launch_f_rows(c, g, 1, Krow, c->hrank[i]);  // reads the updated site table
-        }
+        if (need_row && !row_launched) launch_f_rows(c, g, 1, Krow, c->hrank[i]);  // reads the updated site table
         double parts[kMoveParts];
         HIPCHK(hipMemcpyAsync(parts, dUd, sizeof(parts), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

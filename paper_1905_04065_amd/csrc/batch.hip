@@ -3,7 +3,8 @@
 // accept), the whole step captured once as a HIP graph.
 //
 // Phases of a step, each one launch over every replica (block ranges per
-// replica, see batch.hpp):
+// replica, see batch.hpp); b_frow, b_path, b_book and the far field run on a
+// side stream beside b_sweep:
 //   b_site, b_slot      the proposal pass (Sec. 3: dU of every hop)
 //   b_count, b_select   the move (Alg. 1): slot j with R_{j-1} < T <= R_j over
 //                       the cumulative propensities in slot order, then the
@@ -481,16 +482,18 @@ void record_step(fmmkmc_batch *b)
     launch_prof(b->prof, s, "b_select", k_b_select, dim3((unsigned)R), dim3(256), 0, b->reps, R, b->count.d,
                 b->wsum, b->rates, b->u, b->step, b->moves, b->Q);
     launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt);
-    // the F rows depend only on the moves: on the side stream, beside the sweep
+    // beside the sweep, on the side stream: the F rows (they depend only on the
+    // moves), the multipole paths, the bookkeeping and the far field; none of
+    // it touches the fine-level expansions or what the sweep reads
     HIPCHK(hipEventRecord(b->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
     launch_b_frow(b->prof, b->aux, b->reps, R, b->moves, b->nt, b->K);
+    launch_b_path(b->prof, b->aux, b->reps, R, b->path.d, b->path.blocks, b->moves);
+    launch_b_book(b->prof, b->aux, b->reps, R, b->moves);
+    launch_b_far(b->prof, b->aux, b->reps, R, b->far.d, b->far.blocks, b->cheb_a.d, b->cheb_a.blocks, b->cheb_b.d,
+                 b->cheb_b.blocks, b->moves);
     HIPCHK(hipEventRecord(b->ev_join, b->aux));
     launch_b_sweep(b->prof, s, b->reps, R, b->sweep.d, b->sweep.blocks, b->p, b->moves, b->sweep_block);
-    launch_b_path(b->prof, s, b->reps, R, b->path.d, b->path.blocks, b->moves);
-    launch_b_book(b->prof, s, b->reps, R, b->moves);
-    launch_b_far(b->prof, s, b->reps, R, b->far.d, b->far.blocks, b->cheb_a.d, b->cheb_a.blocks, b->cheb_b.d,
-                 b->cheb_b.blocks, b->moves);
     HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
     launch_prof(b->prof, s, "b_finish", k_b_finish, dim3(1), dim3(256), 0, (const MoveDev *)b->moves, R,
                 (const double *)b->acc, b->U, b->step, b->out_i, b->out_site, b->out_dU, b->rates,

@@ -92,7 +92,7 @@ Geo make_geo(const fmmkmc_ctx *c);
 void launch_p2m(fmmkmc_ctx *c, const Geo &g);
 void launch_upward(fmmkmc_ctx *c);
 void launch_downward(fmmkmc_ctx *c);
-void launch_far_refresh(fmmkmc_ctx *c);
+void launch_far_refresh(fmmkmc_ctx *c, hipStream_t st = nullptr);  // st: nullptr = the context stream
 void launch_shadow(fmmkmc_ctx *c);
 // propose
 void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz, const int64_t *pidx,
@@ -117,6 +117,8 @@ void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], d
 // F row of one charge (rank, lattice site s) on stream st; false (nothing
 // launched) when its tables exceed the kernel's LDS, then use launch_f_rows
 bool launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t s, hipStream_t st);
-void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a);
+// sweep on the context stream; path and bookkeeping on side (they touch neither
+// the fine-level expansions nor anything the sweep reads)
+void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a, hipStream_t side);
 
 }  // namespace fmmkmc

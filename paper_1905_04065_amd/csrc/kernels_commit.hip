@@ -319,7 +319,7 @@ __global__ void k_book(Book b, double *x, double *y, double *z, int32_t *cell, i
     book_body(b, x, y, z, cell, slot, site, ijk_r, cnt, slots, cap, site_charge, site_rank, qsite, qsite32);
 }
 
-void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
+void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a, hipStream_t side)
 {
     Move mv;
     mv.ox = a.old_pos[0];
@@ -339,7 +339,8 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
     FMMKMC_DISPATCH_P(c->p, launch(c, "sweep", k_sweep<P_>, dim3((unsigned)((c->M + 255) / 256), n_groups(P_)),
                                    dim3(256), g, c->M, mv, c->psi_lv[c->L], p32));
     const int per = (c->p + 1) * (c->p + 2) / 2;
-    launch(c, "path", k_path, dim3((c->L * per + 255) / 256), dim3(256), g, c->L, c->p, mv, c->d_phi_ptrs);
+    launch_on(c, side, "path", k_path, dim3((c->L * per + 255) / 256), dim3(256), 0, g, c->L, c->p, mv,
+              c->d_phi_ptrs);
     Book b;
     b.i = a.i;
     b.nx = a.new_pos[0];
@@ -360,8 +361,8 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a)
     b.rank = a.rank;
     b.s2 = c->s2 ? 1 : 0;
     b.same_cell = a.old_cell == a.new_cell ? 1 : 0;
-    launch(c, "book", k_book, dim3(1), dim3(64), b, c->x, c->y, c->z, c->cell, c->slot, c->site, c->ijk_r,
-           c->cell_cnt, c->cell_slots, c->cap, c->site_charge, c->site_rank, c->qsite, c->qsite32);
+    launch_on(c, side, "book", k_book, dim3(1), dim3(64), 0, b, c->x, c->y, c->z, c->cell, c->slot, c->site,
+              c->ijk_r, c->cell_cnt, c->cell_slots, c->cap, c->site_charge, c->site_rank, c->qsite, c->qsite32);
 }
 
 

@@ -374,17 +374,18 @@ __global__ __launch_bounds__(256) void k_cheb_b(int p, int n, const double *__re
     cheb_b_body(blockIdx.x, p, n, A, Tax, Bz);
 }
 
-void launch_far_refresh(fmmkmc_ctx *c)
+void launch_far_refresh(fmmkmc_ctx *c, hipStream_t st)
 {
+    if (!st) st = c->stream;
     const int q = c->p + 1, rows = c->nt + c->far.ncz;
-    launch(c, "far_refresh", k_far_refresh, dim3((rows + 15) / 16), dim3(256), c->nt, c->far.ncz, c->far.R,
-           c->far.GR, c->far.cz, c->far.K, c->far.H, c->far.C);
+    launch_on(c, st, "far_refresh", k_far_refresh, dim3((rows + 15) / 16), dim3(256), 0, c->nt, c->far.ncz,
+              c->far.R, c->far.GR, c->far.cz, c->far.K, c->far.H, c->far.C);
     if (c->lat_n > 0) {
         const int64_t ta = (int64_t)c->lat_n * q * q, tb = (int64_t)c->lat_n * c->lat_n * q;
-        launch(c, "cheb_a", k_cheb_a, dim3((unsigned)((ta + 255) / 256)), dim3(256), c->p, c->lat_n, c->far.C,
-               c->far.Tax, c->far.A);
-        launch(c, "cheb_b", k_cheb_b, dim3((unsigned)((tb + 255) / 256)), dim3(256), c->p, c->lat_n, c->far.A,
-               c->far.Tax, c->far.Bz);
+        launch_on(c, st, "cheb_a", k_cheb_a, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, c->p, c->lat_n,
+                  c->far.C, c->far.Tax, c->far.A);
+        launch_on(c, st, "cheb_b", k_cheb_b, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, c->p, c->lat_n,
+                  c->far.A, c->far.Tax, c->far.Bz);
     }
 }
 
