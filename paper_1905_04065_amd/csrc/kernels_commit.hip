@@ -67,23 +67,39 @@ __device__ inline double rsqrt_nr(double x)
 // recurrences of I become
 //   T_0^0 = 1,  T_m^m = -(xh + i yh) T_{m-1}^{m-1},  T_{m+1}^m = zh T_m^m,
 //   T_n^m = zh T_{n-1}^m - c_n^m T_{n-2}^m,  c_n^m = ((n-1)^2 - m^2) / ((2n-1)(2n-3)),
-// with constant coefficients, so a term costs two operations and its
-// accumulation one fused multiply-add with q rho^(n+1); (2n-1)!! is applied
-// once per cell when the sums are added to the expansion.
+// with constant coefficients.  The columns are carried rescaled once more,
+// U_n^m = T_n^m / s_n^m with s_m = s_{m+1} = 1 and s_n = c_n^m s_{n-2}, which
+// turns the three-term step into U_n = (g_n^m zh) U_{n-1} - U_{n-2} with
+// g_n^m = s_{n-1} / s_n: one multiply shared by the real and imaginary parts
+// and one fused multiply-add each.  The accumulation is one fused multiply-add
+// with q rho^(n+1); (2n-1)!! s_n^m is applied once per cell when the sums are
+// added to the expansion.
 template <int P>
 struct ScaledIrregular {
-    double c[P + 1][P + 1];
-    double dfact[P + 1];  // (2n-1)!!
-    constexpr ScaledIrregular() : c{}, dfact{}
+    double g[P + 1][P + 1];      // s_{n-1} / s_n for n >= m + 2
+    double scale[P + 1][P + 1];  // (2n-1)!! s_n^m
+    constexpr ScaledIrregular() : g{}, scale{}
     {
-        for (int n = 2; n <= P; ++n)
-            for (int m = 0; m + 2 <= n; ++m)
-                c[n][m] = (double)((n - 1) * (n - 1) - m * m) / (double)((2 * n - 1) * (2 * n - 3));
-        double f = 1.0;
-        dfact[0] = 1.0;
-        for (int n = 1; n <= P; ++n) {
-            f *= (double)(2 * n - 1);
-            dfact[n] = f;
+        for (int m = 0; m <= P; ++m) {
+            double s2 = 1.0, s1 = 1.0;  // s_{n-2}, s_{n-1}
+            double f = 1.0;
+            for (int n = 1; n <= m; ++n) f *= (double)(2 * n - 1);
+            for (int n = m; n <= P; ++n) {
+                if (n > m) f *= (double)(2 * n - 1);
+                double sn = 1.0;
+                if (n >= m + 2) {
+                    const double c = (double)((n - 1) * (n - 1) - m * m) / (double)((2 * n - 1) * (2 * n - 3));
+                    sn = c * s2;
+                    g[n][m] = s1 / sn;
+                }
+                scale[n][m] = f * sn;
+                if (n >= m + 1) {
+                    s2 = s1;
+                    s1 = sn;
+                } else {
+                    s1 = sn;
+                }
+            }
         }
     }
 };
@@ -146,8 +162,8 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv,
                     if (cplxcol) acc[o + 3] = fma(w[m + 1], bi, acc[o + 3]);
 #pragma unroll
                     for (int n = m + 2; n <= P; ++n) {
-                        const double cnm = SI.c[n][m];
-                        const double cr = fma(zh, br, -cnm * ar), ci = fma(zh, bi, -cnm * ai);
+                        const double gz = zh * SI.g[n][m];
+                        const double cr = fma(gz, br, -ar), ci = fma(gz, bi, -ai);
                         const int tt = n - m;
                         acc[o + (cplxcol ? 2 * tt : tt)] = fma(w[n], cr, acc[o + (cplxcol ? 2 * tt : tt)]);
                         if (cplxcol) acc[o + 2 * tt + 1] = fma(w[n], ci, acc[o + 2 * tt + 1]);
@@ -166,7 +182,7 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv,
 #pragma unroll
         for (int n = m; n <= P; ++n) {
             const int t = n - m;
-            const double f = SI.dfact[n];
+            const double f = SI.scale[n][m];
             if (m == 0) {
                 const int64_t at = (int64_t)slot0(n) * M + cell;
                 const double v = fma(f, acc[o + t], psi[at]);
