@@ -290,3 +290,34 @@ def test_set_rates_rejects_bad_arguments():
         with pytest.raises(FmmKmcError):
             batch.set_rates(*args)
     batch.close()
+
+
+def test_replica_without_a_valid_hop_does_not_move():
+    """degenerate case: a fully occupied lattice has no valid hop (Q = 0): the
+    replica stays put (moved -1, dU NaN, Delta t +inf for rate kinds) while
+    the other replica of the batch moves as usual"""
+    from paper_1905_04065_amd import Batch, Context
+    n = 8
+    full_sites = np.arange(n ** 3)
+    q_full = np.where(np.arange(n ** 3) % 2 == 0, 1.0, -1.0)
+    np.random.default_rng(W.BASE_SEED + 55).shuffle(q_full)
+    full = Context(W.site_xyz(full_sites, n), q_full, a=float(n), levels=3, order=4, bc="periodic",
+                   lattice_n=n, device=0)
+    full.initialise()
+    rp = replica(1, 1000, "fp64", 4)
+    rp["p"] = 4
+    other = Context(rp["xyz"], rp["q"], a=float(rp["n"]), levels=rp["L"], order=4, bc="periodic",
+                    lattice_n=rp["n"], device=0)
+    other.initialise()
+    U_full = full.energy
+    batch = Batch([full, other], W.HOPS6)
+    moved, site, dU = (x.cpu().numpy() for x in batch.step(np.full((3, 2), 0.3)))
+    assert np.all(moved[:, 0] == -1) and np.all(site[:, 0] == -1) and np.all(np.isnan(dU[:, 0]))
+    assert np.all(moved[:, 1] >= 0)
+    bdU, bmask = batch.proposals(0)
+    assert not bmask.cpu().numpy().any() and np.all(np.isnan(bdU.cpu().numpy()))
+    batch.set_rates(1, 1.0, 1.0)
+    moved, site, dU, dt = (x.cpu().numpy() for x in batch.step(np.full((2, 2, 2), 0.4), with_dt=True))
+    assert np.all(moved[:, 0] == -1) and np.all(np.isinf(dt[:, 0])) and np.all(np.isfinite(dt[:, 1]))
+    assert full.energy == U_full
+    batch.close()
