@@ -761,7 +761,7 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             const fmmkmc_ctx *c = ctx[r];
             const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
             const int q = c->p + 1;
-            nsite[r] = c->s2 ? (c->M + 127) / 128 : (ns + 255) / 256;
+            nsite[r] = c->s2 ? (c->M + 127) / 128 : general_site_blocks(c->lat_n);
             ncount[r] = (c->N * K + kSelChunk - 1) / kSelChunk;
             npath[r] = ((int64_t)c->L * (q * (q + 1) / 2) + 255) / 256;
             const bool per = c->bc == FMMKMC_PERIODIC;

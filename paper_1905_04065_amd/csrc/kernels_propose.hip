@@ -148,13 +148,34 @@ struct InvSqrtTab {
     }
 };
 
-// One lane per lattice site (lattice order).  The near field of a site is the
-// charge of every site in the 27 cells around its cell; per axis those cells
-// are three runs of consecutive lattice planes (cell_rng), so the 27 cells
-// form a box of sites whose offsets from the lane's site are integers: the
-// charges are read straight from the per-site array (no slot lists) and
-// 1/|d| = 1/(h sqrt(d^2)) comes from a table of integer d^2.  The site's own
-// occupant (d^2 = 0) is left out, so occupied sites get phi_occ.
+// One lane per lattice site, 256 consecutive sites (lattice order) per
+// block, so every lane of a block has work whatever n is.  The near field of a site is the charge of every site in the 27 cells around its
+// cell; per axis those cells are three runs of consecutive lattice planes
+// (cell_rng), so the 27 cells form a box of sites whose offsets from the
+// lane's site are integers, and 1/|d| = 1/(h sqrt(d^2)) comes from a table of
+// integer d^2.  The site's own occupant (d^2 = 0) is left out, so occupied
+// sites get phi_occ.  The union of the block's boxes (in unwrapped plane
+// coordinates) is staged in LDS once, with coalesced loads, so the inner loop
+// reads LDS instead of one scattered global load per (site, box site); a
+// block whose union does not fit reads the per-site array directly.  Only
+// the mixed kernel stages: with 8-byte charges the staged loop measured
+// slower than reading the (cache-resident) per-site array.
+constexpr int kGenSites = 256;  // sites (lanes) per block
+constexpr int kTileQ = 6144;                        // staged charges per block (mixed)
+
+template <bool MIXED>
+constexpr int gen_tile_q()
+{
+    return MIXED ? kTileQ : 0;
+}
+
+// LDS of the general body: the 1/sqrt table, the staged charges, the box bounds
+template <bool MIXED>
+constexpr int gen_smem_bytes()
+{
+    return (int)((kInvTab + gen_tile_q<MIXED>()) * (MIXED ? sizeof(float) : sizeof(double))) + 32;
+}
+
 template <int P, bool MIXED>
 __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
                                                   const float *__restrict__ psi32, const double *__restrict__ Bz,
@@ -162,26 +183,24 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
                                                   const float *__restrict__ qsite32,
                                                   const int32_t *__restrict__ cell_rng,
                                                   const int32_t *__restrict__ site_rank,
-                                                  double *__restrict__ phisite, double *__restrict__ phi_r)
+                                                  double *__restrict__ phisite, double *__restrict__ phi_r,
+                                                  unsigned char *smem)
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     constexpr InvSqrtTab IT{};
-    __shared__ Real sInv[kInvTab];
-    for (int e = threadIdx.x; e < kInvTab; e += blockDim.x) sInv[e] = (Real)IT.v[e];
-    __syncthreads();
-    const int64_t s = blk * blockDim.x + threadIdx.x;
+    Real *sInv = (Real *)smem;                // kInvTab
+    Real *sQ = sInv + kInvTab;                // gen_tile_q<MIXED>()
+    int *sLo = (int *)(sQ + gen_tile_q<MIXED>()), *sHi = sLo + 3;
     const int n = g.n, nc = g.nc;
-    if (s >= (int64_t)n * n * n) return;
+    const int t = threadIdx.x;
+    const int64_t s = blk * kGenSites + t;
+    const bool active = s < (int64_t)n * n * n;  // lane 0 always is
     const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
-    const double px = (si + 0.5) * g.h, py = (sj + 0.5) * g.h, pz = (sk + 0.5) * g.h;
-    const int cx = fine_coord(px, g.w, nc), cy = fine_coord(py, g.w, nc), cz = fine_coord(pz, g.w, nc);
-    const int64_t cell = cell_id(nc, cx, cy, cz);
-    const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
-    double phi;
-    if (MIXED)
-        phi = psi[cell] + (double)l2p_cols<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
-    else
-        phi = l2p_cols<P, double>(psi + cell, M, ux, uy, uz);
+    for (int e = t; e < kInvTab; e += blockDim.x) sInv[e] = (Real)IT.v[e];
+    if (t < 3) {
+        sLo[t] = 0x7fffffff;
+        sHi[t] = -0x7fffffff;
+    }
     const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
     // per axis, the planes of cells c-1, c, c+1 are at most two runs of
     // consecutive indices (two when the block wraps around a periodic face);
@@ -209,50 +228,131 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         }
         return r;
     };
-    const Runs rx = runs(cx), ry = runs(cy), rz = runs(cz);
-    Real nearv = Real(0);
+    const double px = (si + 0.5) * g.h, py = (sj + 0.5) * g.h, pz = (sk + 0.5) * g.h;
+    const int cx = fine_coord(px, g.w, nc), cy = fine_coord(py, g.w, nc), cz = fine_coord(pz, g.w, nc);
+    Runs rx{}, ry{}, rz{};
+    if (active) {
+        rx = runs(cx);
+        ry = runs(cy);
+        rz = runs(cz);
+    }
+    __syncthreads();
+    if (MIXED && active) {
+        // the lane's box in unwrapped plane coordinates
+        const Runs *ra[3] = {&rx, &ry, &rz};
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int ilo = a ? rx.lo1 : rx.lo0, ihi = a ? rx.hi1 : rx.hi0, shx = a ? rx.sh1 : rx.sh0;
-        for (int i = ilo; i <= ihi; ++i) {
-            const int di = si - (i + shx);
+        for (int ax = 0; ax < 3; ++ax) {
+            const Runs &r = *ra[ax];
+            int lo = 0x7fffffff, hi = -0x7fffffff;
+            if (r.hi0 >= r.lo0) {
+                lo = r.lo0 + r.sh0;
+                hi = r.hi0 + r.sh0;
+            }
+            if (r.hi1 >= r.lo1) {
+                lo = min(lo, r.lo1 + r.sh1);
+                hi = max(hi, r.hi1 + r.sh1);
+            }
+            atomicMin(&sLo[ax], lo);
+            atomicMax(&sHi[ax], hi);
+        }
+    }
+    __syncthreads();
+    const int lox = sLo[0], loy = sLo[1], loz = sLo[2];
+    const int Lx = sHi[0] - lox + 1, Ly = sHi[1] - loy + 1, Lz = sHi[2] - loz + 1;
+    const bool tiled = MIXED && Lx > 0 && Ly > 0 && Lz > 0 && (int64_t)Lx * Ly * Lz <= gen_tile_q<MIXED>();  // uniform
+    if (tiled) {
+        const int tot = Lx * Ly * Lz;
+        for (int e = t; e < tot; e += blockDim.x) {
+            const int ix = e / (Ly * Lz), iy = (e / Lz) % Ly, iz = e % Lz;
+            int ux = lox + ix, uy = loy + iy, uz = loz + iz;
+            bool in = true;
+            if (g.periodic) {
+                ux = ux < 0 ? ux + n : (ux >= n ? ux - n : ux);
+                uy = uy < 0 ? uy + n : (uy >= n ? uy - n : uy);
+                uz = uz < 0 ? uz + n : (uz >= n ? uz - n : uz);
+            } else {
+                in = ux >= 0 && ux < n && uy >= 0 && uy < n && uz >= 0 && uz < n;
+            }
+            sQ[e] = in ? Qs[((int64_t)ux * n + uy) * n + uz] : Real(0);
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    const int64_t cell = cell_id(nc, cx, cy, cz);
+    const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
+    double phi;
+    if (MIXED)
+        phi = psi[cell] + (double)l2p_cols<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
+    else
+        phi = l2p_cols<P, double>(psi + cell, M, ux, uy, uz);
+    // rowof(i, j, shx, shy, shz): the charges of plane row (i, j), indexed by z
+    auto near_sum = [&](auto rowof) {
+        Real acc = Real(0);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int jlo = b ? ry.lo1 : ry.lo0, jhi = b ? ry.hi1 : ry.hi0, shy = b ? ry.sh1 : ry.sh0;
-                for (int j = jlo; j <= jhi; ++j) {
-                    const int dj = sj - (j + shy);
-                    const int dij = di * di + dj * dj;
-                    const Real *row = Qs + ((int64_t)i * n + j) * n;
+        for (int a = 0; a < 2; ++a) {
+            const int ilo = a ? rx.lo1 : rx.lo0, ihi = a ? rx.hi1 : rx.hi0, shx = a ? rx.sh1 : rx.sh0;
+            for (int i = ilo; i <= ihi; ++i) {
+                const int di = si - (i + shx);
 #pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int klo = e ? rz.lo1 : rz.lo0, khi = e ? rz.hi1 : rz.hi0;
-                        const int off = sk - (e ? rz.sh1 : rz.sh0);
-                        // 1/sqrt(0) is stored as 0: the site's own occupant drops out
-                        if (g.tab_ok) {
+                for (int b = 0; b < 2; ++b) {
+                    const int jlo = b ? ry.lo1 : ry.lo0, jhi = b ? ry.hi1 : ry.hi0, shy = b ? ry.sh1 : ry.sh0;
+                    for (int j = jlo; j <= jhi; ++j) {
+                        const int dj = sj - (j + shy);
+                        const int dij = di * di + dj * dj;
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            const int klo = e ? rz.lo1 : rz.lo0, khi = e ? rz.hi1 : rz.hi0;
+                            const int shz = e ? rz.sh1 : rz.sh0;
+                            const int off = sk - shz;
+                            const auto row = rowof(i, j, shx, shy, shz);
+                            // 1/sqrt(0) is stored as 0: the site's own occupant drops out
+                            if (g.tab_ok) {
+                                // d2 = dij + (off - k)^2, stepped without multiplies
+                                int d2 = dij + (off - klo) * (off - klo), st = 2 * (off - klo) - 1;
 #pragma unroll 4
-                            for (int k = klo; k <= khi; ++k) {
-                                const int dk = off - k;
-                                nearv += row[k] * sInv[dij + dk * dk];
-                            }
-                        } else {
-                            for (int k = klo; k <= khi; ++k) {
-                                const int dk = off - k;
-                                const int d2 = dij + dk * dk;
-                                const Real inv = d2 < kInvTab ? sInv[d2 < kInvTab ? d2 : 0]
-                                                              : Real(1) / sqrt((Real)d2);
-                                nearv += row[k] * inv;
+                                for (int k = klo; k <= khi; ++k) {
+                                    acc += row[k] * sInv[d2];
+                                    d2 -= st;
+                                    st -= 2;
+                                }
+                            } else {
+                                for (int k = klo; k <= khi; ++k) {
+                                    const int dk = off - k;
+                                    const int d2 = dij + dk * dk;
+                                    const Real inv = d2 < kInvTab ? sInv[d2 < kInvTab ? d2 : 0]
+                                                                  : Real(1) / sqrt((Real)d2);
+                                    acc += row[k] * inv;
+                                }
                             }
                         }
                     }
                 }
             }
         }
+        return acc;
+    };
+    // two instances, so that each reads through a pointer of known address
+    // space: the staged box (unwrapped z) or the per-site array (wrapped z)
+    Real nearv;
+    if (tiled) {
+        nearv = near_sum([&](int i, int j, int shx, int shy, int shz) {
+            return sQ + ((i + shx - lox) * Ly + (j + shy - loy)) * Lz + (shz - loz);
+        });
+    } else {
+        using GReal = const __attribute__((address_space(1))) Real;
+        GReal *Qg = (GReal *)Qs;
+        nearv = near_sum([&](int i, int j, int, int, int) { return Qg + ((int64_t)i * n + j) * n; });
     }
     phi += (double)nearv / g.h;
     if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
     const int32_t rk = site_rank[s];
     if (rk >= 0) phi_r[rk] = phi;
     phisite[s] = rk >= 0 ? __builtin_nan("") : phi;
+}
+
+int64_t general_site_blocks(int n)
+{
+    return ((int64_t)n * n * n + kGenSites - 1) / kGenSites;
 }
 
 template <int P, bool MIXED>
@@ -266,8 +366,9 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
                                                           const int32_t *__restrict__ site_rank,
                                                           double *__restrict__ phisite, double *__restrict__ phi_r)
 {
+    __shared__ __align__(16) unsigned char smem[gen_smem_bytes<MIXED>()];
     site_general_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, Bz, Tax, qsite, qsite32, cell_rng, site_rank,
-                                phisite, phi_r);
+                                phisite, phi_r, smem);
 }
 
 // ---- lattice with 2 x 2 x 2 sites per fine cell ----------------------------
@@ -357,23 +458,30 @@ __host__ __device__ constexpr int s2_d2(int u, int nb, int v)
 template <int NW>
 constexpr int s2_cells() { return 32 * NW; }  // cells per block
 
+// LDS of the 2x2x2 body: the near-field 1/|d| table, the two per-site results
+template <bool MIXED, int NW>
+constexpr int s2_smem_bytes()
+{
+    return (int)(27 * 64 * (MIXED ? sizeof(float) : sizeof(double))) + 2 * s2_cells<NW>() * 9 * 8;
+}
+
 template <int P, bool MIXED, int NW>
 __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
                                              const float *__restrict__ psi32, const double *__restrict__ qsite,
                                              const float *__restrict__ qsite32,
                                              const int32_t *__restrict__ site_rank, const double *__restrict__ Bz,
                                              const double *__restrict__ Tax, double *__restrict__ phisite,
-                                             double *__restrict__ phi_r)
+                                             double *__restrict__ phi_r, unsigned char *smem)
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     constexpr S2Weights<P> W{};
     constexpr InvSqrt IS{};
-    // 1/|d| between the 8 sites of a cell and the 8 sites of each of its 27
-    // neighbours, [nb][u][v], unit spacing
-    __shared__ Real sT[27 * 64];
     // per cell and site: local-expansion part, near + far-field part (row of 9: no bank conflicts)
     constexpr int CELLS = s2_cells<NW>();
-    __shared__ double sFar[CELLS * 9], sNear[CELLS * 9];
+    double *sFar = (double *)smem, *sNear = sFar + CELLS * 9;
+    // 1/|d| between the 8 sites of a cell and the 8 sites of each of its 27
+    // neighbours, [nb][u][v], unit spacing
+    Real *sT = (Real *)(sNear + CELLS * 9);
     for (int e = threadIdx.x; e < 27 * 64; e += blockDim.x) {
         const int nb = e / 64, u = (e / 8) % 8, v = e % 8;
         sT[e] = (Real)IS.v[s2_d2(u, nb, v)];
@@ -529,7 +637,9 @@ __global__ __launch_bounds__(512) void k_site_phi_s2(Geo g, int64_t M, const dou
                                                      const double *__restrict__ Bz, const double *__restrict__ Tax,
                                                      double *__restrict__ phisite, double *__restrict__ phi_r)
 {
-    site_s2_body<P, MIXED, 8>(blockIdx.x, g, M, psi, psi32, qsite, qsite32, site_rank, Bz, Tax, phisite, phi_r);
+    __shared__ __align__(16) unsigned char smem[s2_smem_bytes<MIXED, 8>()];
+    site_s2_body<P, MIXED, 8>(blockIdx.x, g, M, psi, psi32, qsite, qsite32, site_rank, Bz, Tax, phisite, phi_r,
+                              smem);
 }
 
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
@@ -547,8 +657,7 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
                                            c->far.Tax, c->phisite, c->phi_r));
         }
     } else {
-        const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
-        dim3 grid((unsigned)((ns + 255) / 256));
+        dim3 grid((unsigned)general_site_blocks(c->lat_n));
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, true>, grid, dim3(256), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->qsite, c->qsite32,
@@ -1244,15 +1353,19 @@ template <int P, bool MIXED>
 __global__ __launch_bounds__(256) void k_b_site(const RepDev *__restrict__ reps, int R,
                                                 const int64_t *__restrict__ base)
 {
+    // one LDS buffer serves whichever body the replica takes
+    constexpr int kS2 = s2_smem_bytes<MIXED, 4>(), kGen = gen_smem_bytes<MIXED>();
+    __shared__ __align__(16) unsigned char smem[kS2 > kGen ? kS2 : kGen];
     const int r = find_rep(base, R, blockIdx.x);
     const RepDev &d = reps[r];
     const int64_t blk = blockIdx.x - base[r];
     if (d.s2)
-        site_s2_body<P, MIXED, 4>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
-                               d.phisite, d.phi_r);
+        site_s2_body<P, MIXED, 4>(blk, d.g, d.M, gmem(d.psi), gmem(d.psi32), gmem(d.qsite), gmem(d.qsite32),
+                                  gmem(d.site_rank), gmem(d.Bz), gmem(d.Tax), gmem(d.phisite), gmem(d.phi_r), smem);
     else
-        site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.qsite, d.qsite32, d.cell_rng,
-                                    d.site_rank, d.phisite, d.phi_r);
+        site_general_body<P, MIXED>(blk, d.g, d.M, gmem(d.psi), gmem(d.psi32), gmem(d.Bz), gmem(d.Tax),
+                                    gmem(d.qsite), gmem(d.qsite32), gmem(d.cell_rng), gmem(d.site_rank),
+                                    gmem(d.phisite), gmem(d.phi_r), smem);
 }
 
 template <int TC>
