@@ -56,16 +56,6 @@ struct MoveDev {
     Book bk;
 };
 
-// The replica table holds device pointers that the compiler cannot prove to
-// address global memory, so it would access them with flat instructions
-// (which share a counter with LDS reads and so serialise against them).  A
-// round trip through the global address space lets it use global ones.
-template <class T>
-__device__ __forceinline__ T *gmem(T *p)
-{
-    return (T *)(__attribute__((address_space(1))) T *)p;
-}
-
 // replica owning block b of a batched launch: base[r] <= b < base[r + 1]
 __device__ inline int find_rep(const int64_t *__restrict__ base, int R, int64_t b)
 {

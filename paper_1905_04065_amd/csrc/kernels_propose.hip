@@ -1360,12 +1360,11 @@ __global__ __launch_bounds__(256) void k_b_site(const RepDev *__restrict__ reps,
     const RepDev &d = reps[r];
     const int64_t blk = blockIdx.x - base[r];
     if (d.s2)
-        site_s2_body<P, MIXED, 4>(blk, d.g, d.M, gmem(d.psi), gmem(d.psi32), gmem(d.qsite), gmem(d.qsite32),
-                                  gmem(d.site_rank), gmem(d.Bz), gmem(d.Tax), gmem(d.phisite), gmem(d.phi_r), smem);
+        site_s2_body<P, MIXED, 4>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
+                                  d.phisite, d.phi_r, smem);
     else
-        site_general_body<P, MIXED>(blk, d.g, d.M, gmem(d.psi), gmem(d.psi32), gmem(d.Bz), gmem(d.Tax),
-                                    gmem(d.qsite), gmem(d.qsite32), gmem(d.cell_rng), gmem(d.site_rank),
-                                    gmem(d.phisite), gmem(d.phi_r), smem);
+        site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.qsite, d.qsite32, d.cell_rng,
+                                    d.site_rank, d.phisite, d.phi_r, smem);
 }
 
 template <int TC>
