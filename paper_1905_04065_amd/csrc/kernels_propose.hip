@@ -161,7 +161,7 @@ struct InvSqrtTab {
 // the mixed kernel stages: with 8-byte charges the staged loop measured
 // slower than reading the (cache-resident) per-site array.
 constexpr int kGenSites = 256;  // sites (lanes) per block
-constexpr int kTileQ = 6144;                        // staged charges per block (mixed)
+constexpr int kTileQ = 8192;                        // staged charges per block (mixed)
 
 template <bool MIXED>
 constexpr int gen_tile_q()
@@ -236,30 +236,32 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         ry = runs(cy);
         rz = runs(cz);
     }
-    __syncthreads();
-    if (MIXED && active) {
-        // the lane's box in unwrapped plane coordinates
+    // The lane's box in unwrapped plane coordinates: the second run of an axis
+    // (the wrapped cell) adjoins the first, so the box is [blo, bhi] per axis.
+    int blo[3] = {0, 0, 0}, bhi[3] = {-1, -1, -1};
+    {
         const Runs *ra[3] = {&rx, &ry, &rz};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             const Runs &r = *ra[ax];
-            int lo = 0x7fffffff, hi = -0x7fffffff;
-            if (r.hi0 >= r.lo0) {
-                lo = r.lo0 + r.sh0;
-                hi = r.hi0 + r.sh0;
-            }
-            if (r.hi1 >= r.lo1) {
-                lo = min(lo, r.lo1 + r.sh1);
-                hi = max(hi, r.hi1 + r.sh1);
-            }
-            atomicMin(&sLo[ax], lo);
-            atomicMax(&sHi[ax], hi);
+            blo[ax] = r.hi1 >= r.lo1 ? min(r.lo0 + r.sh0, r.lo1 + r.sh1) : r.lo0 + r.sh0;
+            bhi[ax] = r.hi1 >= r.lo1 ? max(r.hi0 + r.sh0, r.hi1 + r.sh1) : r.hi0 + r.sh0;
+        }
+    }
+    __syncthreads();
+    if (MIXED && active) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            atomicMin(&sLo[ax], blo[ax]);
+            atomicMax(&sHi[ax], bhi[ax]);
         }
     }
     __syncthreads();
     const int lox = sLo[0], loy = sLo[1], loz = sLo[2];
     const int Lx = sHi[0] - lox + 1, Ly = sHi[1] - loy + 1, Lz = sHi[2] - loz + 1;
-    const bool tiled = MIXED && Lx > 0 && Ly > 0 && Lz > 0 && (int64_t)Lx * Ly * Lz <= gen_tile_q<MIXED>();  // uniform
+    // uniform over the block; the staged loop reads the 1/sqrt table unguarded
+    const bool tiled =
+        MIXED && g.tab_ok && Lx > 0 && Ly > 0 && Lz > 0 && (int64_t)Lx * Ly * Lz <= gen_tile_q<MIXED>();
     if (tiled) {
         const int tot = Lx * Ly * Lz;
         for (int e = t; e < tot; e += blockDim.x) {
@@ -331,14 +333,36 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         }
         return acc;
     };
-    // two instances, so that each reads through a pointer of known address
-    // space: the staged box (unwrapped z) or the per-site array (wrapped z)
     Real nearv;
     if (tiled) {
-        nearv = near_sum([&](int i, int j, int shx, int shy, int shz) {
-            return sQ + ((i + shx - lox) * Ly + (j + shy - loy)) * Lz + (shz - loz);
-        });
+        // the staged box: one contiguous range per axis, squared offsets stepped
+        // without multiplies (d^2 falls by 2d - 1 when d falls by 1)
+        nearv = Real(0);
+        const int nz = bhi[2] - blo[2] + 1;
+        const int dz0 = sk - blo[2], stz0 = 2 * dz0 - 1;
+        const int dx0 = si - blo[0], dy0 = sj - blo[1];
+        const Real *plane = sQ + ((blo[0] - lox) * Ly + (blo[1] - loy)) * Lz + (blo[2] - loz);
+        int dx2 = dx0 * dx0 + dz0 * dz0, stx = 2 * dx0 - 1;
+        for (int x = blo[0]; x <= bhi[0]; ++x, plane += Ly * Lz) {
+            const Real *row = plane;
+            int d2y = dx2 + dy0 * dy0, sty = 2 * dy0 - 1;
+            for (int y = blo[1]; y <= bhi[1]; ++y, row += Lz) {
+                int d2 = d2y, st = stz0;
+#pragma unroll 4
+                for (int z = 0; z < nz; ++z) {
+                    nearv += row[z] * sInv[d2];
+                    d2 -= st;
+                    st -= 2;
+                }
+                d2y -= sty;
+                sty -= 2;
+            }
+            dx2 -= stx;
+            stx -= 2;
+        }
     } else {
+        // the per-site array (wrapped z), read through a pointer of known
+        // address space so the loop uses global rather than flat loads
         using GReal = const __attribute__((address_space(1))) Real;
         GReal *Qg = (GReal *)Qs;
         nearv = near_sum([&](int i, int j, int, int, int) { return Qg + ((int64_t)i * n + j) * n; });
