@@ -148,25 +148,28 @@ struct InvSqrtTab {
     }
 };
 
-// One lane per lattice site, 256 consecutive sites (lattice order) per
-// block, so every lane of a block has work whatever n is.  The near field of a site is the charge of every site in the 27 cells around its
-// cell; per axis those cells are three runs of consecutive lattice planes
-// (cell_rng), so the 27 cells form a box of sites whose offsets from the
-// lane's site are integers, and 1/|d| = 1/(h sqrt(d^2)) comes from a table of
-// integer d^2.  The site's own occupant (d^2 = 0) is left out, so occupied
-// sites get phi_occ.  The union of the block's boxes (in unwrapped plane
-// coordinates) is staged in LDS once, with coalesced loads, so the inner loop
-// reads LDS instead of one scattered global load per (site, box site); a
-// block whose union does not fit reads the per-site array directly.  Only
-// the mixed kernel stages: with 8-byte charges the staged loop measured
-// slower than reading the (cache-resident) per-site array.
-constexpr int kGenSites = 256;  // sites (lanes) per block
-constexpr int kTileQ = 8192;                        // staged charges per block (mixed)
+// One lane per lattice site, 256 consecutive sites (lattice order) per block,
+// so every lane of a block has work whatever n is.  The near field of a site
+// is the charge of every site in the 27 cells around its cell; per axis those
+// cells are consecutive lattice planes (cell_rng), one run, or two when the box
+// wraps around a periodic face, so the 27 cells form a box of sites whose
+// offsets from the lane's site are integers, and 1/|d| = 1/(h sqrt(d^2)) comes
+// from a table of integer d^2.  The site's own occupant (d^2 = 0) is left out,
+// so occupied sites get phi_occ.  The union of the block's boxes (in unwrapped
+// plane coordinates, where each lane's box is one range per axis) is staged in
+// LDS once, with coalesced loads, so the inner loop reads LDS instead of one
+// scattered global load per (site, box site); a block whose union does not fit
+// reads the per-site array directly.  The FP64 tile is smaller: at 8192
+// doubles (two blocks per CU) the staged kernel measured slower than without
+// staging.
+constexpr int kGenSites = 256;   // sites (lanes) per block
+constexpr int kTileQ = 8192;     // staged charges per block (mixed)
+constexpr int kTileQ64 = 6144;   // staged charges per block (FP64)
 
 template <bool MIXED>
 constexpr int gen_tile_q()
 {
-    return MIXED ? kTileQ : 0;
+    return MIXED ? kTileQ : kTileQ64;
 }
 
 // LDS of the general body: the 1/sqrt table, the staged charges, the box bounds
@@ -249,7 +252,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         }
     }
     __syncthreads();
-    if (MIXED && active) {
+    if (gen_tile_q<MIXED>() > 0 && active) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             atomicMin(&sLo[ax], blo[ax]);
@@ -261,7 +264,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
     const int Lx = sHi[0] - lox + 1, Ly = sHi[1] - loy + 1, Lz = sHi[2] - loz + 1;
     // uniform over the block; the staged loop reads the 1/sqrt table unguarded
     const bool tiled =
-        MIXED && g.tab_ok && Lx > 0 && Ly > 0 && Lz > 0 && (int64_t)Lx * Ly * Lz <= gen_tile_q<MIXED>();
+        gen_tile_q<MIXED>() > 0 && g.tab_ok && Lx > 0 && Ly > 0 && Lz > 0 && (int64_t)Lx * Ly * Lz <= gen_tile_q<MIXED>();
     if (tiled) {
         const int tot = Lx * Ly * Lz;
         for (int e = t; e < tot; e += blockDim.x) {
