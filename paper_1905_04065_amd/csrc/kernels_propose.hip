@@ -164,7 +164,16 @@ struct InvSqrtTab {
 // staging.
 constexpr int kGenSites = 256;   // sites (lanes) per block
 constexpr int kTileQ = 8192;     // staged charges per block (mixed)
-constexpr int kTileQ64 = 6144;   // staged charges per block (FP64)
+constexpr bool kFixedRows64 = false;  // FP64 rows at fixed length too
+constexpr int kTileQ64 = kFixedRows64 ? 5632 : 6144;  // staged charges per block (FP64)
+constexpr int kTilePad = 16;     // zeros after the staged box: fixed-length rows read past a lane's box
+
+// staged rows read at a fixed, unrolled length (with a zero-weight table half)
+template <bool MIXED>
+constexpr bool gen_fixed_rows()
+{
+    return MIXED || kFixedRows64;
+}
 
 template <bool MIXED>
 constexpr int gen_tile_q()
@@ -176,7 +185,9 @@ constexpr int gen_tile_q()
 template <bool MIXED>
 constexpr int gen_smem_bytes()
 {
-    return (int)((kInvTab + gen_tile_q<MIXED>()) * (MIXED ? sizeof(float) : sizeof(double))) + 32;
+    return (int)(((gen_fixed_rows<MIXED>() ? 2 : 1) * kInvTab + gen_tile_q<MIXED>() + kTilePad) *
+                 (MIXED ? sizeof(float) : sizeof(double))) +
+           32;
 }
 
 template <int P, bool MIXED>
@@ -191,19 +202,22 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     constexpr InvSqrtTab IT{};
-    Real *sInv = (Real *)smem;                // kInvTab
-    Real *sQ = sInv + kInvTab;                // gen_tile_q<MIXED>()
-    int *sLo = (int *)(sQ + gen_tile_q<MIXED>()), *sHi = sLo + 3;
+    // 1/sqrt table, then (fixed-length rows) kInvTab zeros: the weight of a padded row entry
+    constexpr int kTab = (gen_fixed_rows<MIXED>() ? 2 : 1) * kInvTab;
+    Real *sInv = (Real *)smem;                // kTab
+    Real *sQ = sInv + kTab;                   // gen_tile_q<MIXED>() + kTilePad
+    int *sLo = (int *)(sQ + gen_tile_q<MIXED>() + kTilePad), *sHi = sLo + 3, *sNz = sHi + 3;
     const int n = g.n, nc = g.nc;
     const int t = threadIdx.x;
     const int64_t s = blk * kGenSites + t;
     const bool active = s < (int64_t)n * n * n;  // lane 0 always is
     const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
-    for (int e = t; e < kInvTab; e += blockDim.x) sInv[e] = (Real)IT.v[e];
+    for (int e = t; e < kTab; e += blockDim.x) sInv[e] = e < kInvTab ? (Real)IT.v[e] : Real(0);
     if (t < 3) {
         sLo[t] = 0x7fffffff;
         sHi[t] = -0x7fffffff;
     }
+    if (t == 0) *sNz = 0;
     const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
     // per axis, the planes of cells c-1, c, c+1 are at most two runs of
     // consecutive indices (two when the block wraps around a periodic face);
@@ -258,38 +272,26 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
             atomicMin(&sLo[ax], blo[ax]);
             atomicMax(&sHi[ax], bhi[ax]);
         }
+        atomicMax(sNz, bhi[2] - blo[2] + 1);
     }
     __syncthreads();
     const int lox = sLo[0], loy = sLo[1], loz = sLo[2];
     const int Lx = sHi[0] - lox + 1, Ly = sHi[1] - loy + 1, Lz = sHi[2] - loz + 1;
-    // uniform over the block; the staged loop reads the 1/sqrt table unguarded
-    const bool tiled =
-        gen_tile_q<MIXED>() > 0 && g.tab_ok && Lx > 0 && Ly > 0 && Lz > 0 && (int64_t)Lx * Ly * Lz <= gen_tile_q<MIXED>();
-    if (tiled) {
-        const int tot = Lx * Ly * Lz;
-        for (int e = t; e < tot; e += blockDim.x) {
-            const int ix = e / (Ly * Lz), iy = (e / Lz) % Ly, iz = e % Lz;
-            int ux = lox + ix, uy = loy + iy, uz = loz + iz;
-            bool in = true;
-            if (g.periodic) {
-                ux = ux < 0 ? ux + n : (ux >= n ? ux - n : ux);
-                uy = uy < 0 ? uy + n : (uy >= n ? uy - n : uy);
-                uz = uz < 0 ? uz + n : (uz >= n ? uz - n : uz);
-            } else {
-                in = ux >= 0 && ux < n && uy >= 0 && uy < n && uz >= 0 && uz < n;
-            }
-            sQ[e] = in ? Qs[((int64_t)ux * n + uy) * n + uz] : Real(0);
-        }
-    }
-    __syncthreads();
-    if (!active) return;
+    // Uniform over the block.  The union box is staged in chunks of whole
+    // x-planes (usually one chunk), so every block with one plane of the box
+    // within the tile takes the staged path; the staged loops read the 1/sqrt
+    // table unguarded.
+    const bool tiled = gen_tile_q<MIXED>() > 0 && g.tab_ok && Lx > 0 && Ly > 0 && Lz > 0 &&
+                       (int64_t)Ly * Lz <= gen_tile_q<MIXED>();
     const int64_t cell = cell_id(nc, cx, cy, cz);
-    const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
-    double phi;
-    if (MIXED)
-        phi = psi[cell] + (double)l2p_cols<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
-    else
-        phi = l2p_cols<P, double>(psi + cell, M, ux, uy, uz);
+    double phi = 0.0;
+    if (active) {
+        const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
+        if (MIXED)
+            phi = psi[cell] + (double)l2p_cols<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
+        else
+            phi = l2p_cols<P, double>(psi + cell, M, ux, uy, uz);
+    }
     // rowof(i, j, shx, shy, shz): the charges of plane row (i, j), indexed by z
     auto near_sum = [&](auto rowof) {
         Real acc = Real(0);
@@ -336,40 +338,123 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         }
         return acc;
     };
-    Real nearv;
+    Real nearv = Real(0);
     if (tiled) {
-        // the staged box: one contiguous range per axis, squared offsets stepped
-        // without multiplies (d^2 falls by 2d - 1 when d falls by 1)
-        nearv = Real(0);
-        const int nz = bhi[2] - blo[2] + 1;
-        const int dz0 = sk - blo[2], stz0 = 2 * dz0 - 1;
-        const int dx0 = si - blo[0], dy0 = sj - blo[1];
-        const Real *plane = sQ + ((blo[0] - lox) * Ly + (blo[1] - loy)) * Lz + (blo[2] - loz);
-        int dx2 = dx0 * dx0 + dz0 * dz0, stx = 2 * dx0 - 1;
-        for (int x = blo[0]; x <= bhi[0]; ++x, plane += Ly * Lz) {
-            const Real *row = plane;
-            int d2y = dx2 + dy0 * dy0, sty = 2 * dy0 - 1;
-            for (int y = blo[1]; y <= bhi[1]; ++y, row += Lz) {
-                int d2 = d2y, st = stz0;
-#pragma unroll 4
-                for (int z = 0; z < nz; ++z) {
-                    nearv += row[z] * sInv[d2];
-                    d2 -= st;
-                    st -= 2;
+        const int cpl = gen_tile_q<MIXED>() / (Ly * Lz);  // x-planes per chunk
+        // plane coordinate u (unwrapped) -> lattice index, or -1 outside a free-space box
+        auto wrap = [&](int u) { return g.periodic ? (u < 0 ? u + n : (u >= n ? u - n : u)) : (u >= 0 && u < n ? u : -1); };
+        // planes x0 .. x0 + nxp - 1 of the union box into sQ, then kTilePad zeros
+        auto stage = [&](int x0, int nxp) {
+            const int tot = nxp * Ly * Lz;
+            if (Lz <= (int)blockDim.x) {
+                // each thread keeps one z of the box and walks the (x, y) rows
+                // rpp at a time: no integer division per element
+                const int rpp = blockDim.x / Lz, zt = t % Lz;
+                int r = t / Lz;
+                if (r < rpp) {
+                    const int uz = wrap(loz + zt);
+                    int ix = r / Ly, iy = r - (r / Ly) * Ly;
+                    for (; r < nxp * Ly; r += rpp) {
+                        const int ux = wrap(x0 + ix), uy = wrap(loy + iy);
+                        const bool in = ux >= 0 && uy >= 0 && uz >= 0;
+                        sQ[r * Lz + zt] = in ? Qs[((int64_t)ux * n + uy) * n + uz] : Real(0);
+                        iy += rpp;
+                        while (iy >= Ly) {
+                            iy -= Ly;
+                            ++ix;
+                        }
+                    }
                 }
-                d2y -= sty;
-                sty -= 2;
+            } else {
+                for (int e = t; e < tot; e += blockDim.x) {
+                    const int ix = e / (Ly * Lz), iy = (e / Lz) % Ly, iz = e % Lz;
+                    const int ux = wrap(x0 + ix), uy = wrap(loy + iy), uz = wrap(loz + iz);
+                    const bool in = ux >= 0 && uy >= 0 && uz >= 0;
+                    sQ[e] = in ? Qs[((int64_t)ux * n + uy) * n + uz] : Real(0);
+                }
             }
-            dx2 -= stx;
-            stx -= 2;
+            if (t < kTilePad) sQ[tot + t] = Real(0);
+        };
+        // The lane's rows with x in [xa, xb], p0 = the staged row (xa, blo_y)
+        // at z = blo_z.  Squared x and y offsets are stepped without
+        // multiplies (d^2 falls by 2d - 1 when d falls by 1).  Fixed-length
+        // rows: NZ >= every lane's nz, unrolled with no remainder; entry z has
+        // table index dxy^2 + off[z], off[z] = (dz0 - z)^2 for z < nz and
+        // kInvTab (a zero weight) past the lane's box.
+        const int nz = bhi[2] - blo[2] + 1, dz0 = sk - blo[2], dy0 = sj - blo[1];
+        auto rows = [&](auto nzc, int xa, int xb, const Real *p0) {
+            constexpr int NZ = decltype(nzc)::value;
+            int off[NZ];
+#pragma unroll
+            for (int z = 0; z < NZ; ++z) off[z] = z < nz ? (dz0 - z) * (dz0 - z) : kInvTab;
+            Real acc = Real(0);
+            const int dx0 = si - xa;
+            int dx2 = dx0 * dx0, stx = 2 * dx0 - 1;
+            for (int x = xa; x <= xb; ++x, p0 += Ly * Lz) {
+                const Real *row = p0;
+                int b = dx2 + dy0 * dy0, sty = 2 * dy0 - 1;
+                for (int y = blo[1]; y <= bhi[1]; ++y, row += Lz) {
+#pragma unroll
+                    for (int z = 0; z < NZ; ++z) acc += row[z] * sInv[b + off[z]];
+                    b -= sty;
+                    sty -= 2;
+                }
+                dx2 -= stx;
+                stx -= 2;
+            }
+            return acc;
+        };
+        // rows of the lane's own length, d^2 stepped along z as well
+        auto rows_var = [&](int xa, int xb, const Real *p0) {
+            Real acc = Real(0);
+            const int dx0 = si - xa, stz0 = 2 * dz0 - 1;
+            int dx2 = dx0 * dx0 + dz0 * dz0, stx = 2 * dx0 - 1;
+            for (int x = xa; x <= xb; ++x, p0 += Ly * Lz) {
+                const Real *row = p0;
+                int d2y = dx2 + dy0 * dy0, sty = 2 * dy0 - 1;
+                for (int y = blo[1]; y <= bhi[1]; ++y, row += Lz) {
+                    int d2 = d2y, st = stz0;
+#pragma unroll 4
+                    for (int z = 0; z < nz; ++z) {
+                        acc += row[z] * sInv[d2];
+                        d2 -= st;
+                        st -= 2;
+                    }
+                    d2y -= sty;
+                    sty -= 2;
+                }
+                dx2 -= stx;
+                stx -= 2;
+            }
+            return acc;
+        };
+        for (int x0 = lox; x0 < lox + Lx; x0 += cpl) {
+            const int nxp = min(cpl, lox + Lx - x0);
+            __syncthreads();  // the previous chunk has been read
+            stage(x0, nxp);
+            __syncthreads();
+            const int xa = max(blo[0], x0), xb = min(bhi[0], x0 + nxp - 1);
+            if (active && xa <= xb) {
+                const Real *p0 = sQ + ((xa - x0) * Ly + (blo[1] - loy)) * Lz + (blo[2] - loz);
+                const int nzmax = *sNz;  // uniform
+                if (gen_fixed_rows<MIXED>() && nzmax <= 6)
+                    nearv += rows(std::integral_constant<int, 6>{}, xa, xb, p0);
+                else if (gen_fixed_rows<MIXED>() && nzmax <= 9)
+                    nearv += rows(std::integral_constant<int, 9>{}, xa, xb, p0);
+                else if (gen_fixed_rows<MIXED>() && nzmax <= 12)
+                    nearv += rows(std::integral_constant<int, 12>{}, xa, xb, p0);
+                else
+                    nearv += rows_var(xa, xb, p0);
+            }
         }
-    } else {
+    } else if (active) {
         // the per-site array (wrapped z), read through a pointer of known
         // address space so the loop uses global rather than flat loads
         using GReal = const __attribute__((address_space(1))) Real;
         GReal *Qg = (GReal *)Qs;
         nearv = near_sum([&](int i, int j, int, int, int) { return Qg + ((int64_t)i * n + j) * n; });
     }
+    if (!active) return;
     phi += (double)nearv / g.h;
     if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
     const int32_t rk = site_rank[s];
