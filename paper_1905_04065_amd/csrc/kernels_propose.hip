@@ -157,23 +157,15 @@ struct InvSqrtTab {
 // from a table of integer d^2.  The site's own occupant (d^2 = 0) is left out,
 // so occupied sites get phi_occ.  The union of the block's boxes (in unwrapped
 // plane coordinates, where each lane's box is one range per axis) is staged in
-// LDS once, with coalesced loads, so the inner loop reads LDS instead of one
-// scattered global load per (site, box site); a block whose union does not fit
-// reads the per-site array directly.  The FP64 tile is smaller: at 8192
-// doubles (two blocks per CU) the staged kernel measured slower than without
-// staging.
+// LDS with coalesced loads, in chunks of whole x-planes that fit the tile
+// (usually one chunk), so the inner loop reads LDS instead of one scattered
+// global load per (site, box site).  Only a block whose box has a single plane
+// larger than the tile, or a lattice too coarse for the 1/sqrt table, reads
+// the per-site array directly.  The FP64 tile keeps three blocks per CU.
 constexpr int kGenSites = 256;   // sites (lanes) per block
 constexpr int kTileQ = 8192;     // staged charges per block (mixed)
-constexpr bool kFixedRows64 = false;  // FP64 rows at fixed length too
-constexpr int kTileQ64 = kFixedRows64 ? 5632 : 6144;  // staged charges per block (FP64)
-constexpr int kTilePad = 16;     // zeros after the staged box: fixed-length rows read past a lane's box
-
-// staged rows read at a fixed, unrolled length (with a zero-weight table half)
-template <bool MIXED>
-constexpr bool gen_fixed_rows()
-{
-    return MIXED || kFixedRows64;
-}
+constexpr int kTileQ64 = 5632;   // staged charges per block (FP64)
+constexpr int kTilePad = 16;     // zeros after a staged chunk: fixed-length rows read past a lane's box
 
 template <bool MIXED>
 constexpr int gen_tile_q()
@@ -185,9 +177,7 @@ constexpr int gen_tile_q()
 template <bool MIXED>
 constexpr int gen_smem_bytes()
 {
-    return (int)(((gen_fixed_rows<MIXED>() ? 2 : 1) * kInvTab + gen_tile_q<MIXED>() + kTilePad) *
-                 (MIXED ? sizeof(float) : sizeof(double))) +
-           32;
+    return (int)((2 * kInvTab + gen_tile_q<MIXED>() + kTilePad) * (MIXED ? sizeof(float) : sizeof(double))) + 32;
 }
 
 template <int P, bool MIXED>
@@ -202,8 +192,8 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     constexpr InvSqrtTab IT{};
-    // 1/sqrt table, then (fixed-length rows) kInvTab zeros: the weight of a padded row entry
-    constexpr int kTab = (gen_fixed_rows<MIXED>() ? 2 : 1) * kInvTab;
+    // 1/sqrt table, then kInvTab zeros: the weight of a padded row entry
+    constexpr int kTab = 2 * kInvTab;
     Real *sInv = (Real *)smem;                // kTab
     Real *sQ = sInv + kTab;                   // gen_tile_q<MIXED>() + kTilePad
     int *sLo = (int *)(sQ + gen_tile_q<MIXED>() + kTilePad), *sHi = sLo + 3, *sNz = sHi + 3;
@@ -437,11 +427,11 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
             if (active && xa <= xb) {
                 const Real *p0 = sQ + ((xa - x0) * Ly + (blo[1] - loy)) * Lz + (blo[2] - loz);
                 const int nzmax = *sNz;  // uniform
-                if (gen_fixed_rows<MIXED>() && nzmax <= 6)
+                if (nzmax <= 6)
                     nearv += rows(std::integral_constant<int, 6>{}, xa, xb, p0);
-                else if (gen_fixed_rows<MIXED>() && nzmax <= 9)
+                else if (nzmax <= 9)
                     nearv += rows(std::integral_constant<int, 9>{}, xa, xb, p0);
-                else if (gen_fixed_rows<MIXED>() && nzmax <= 12)
+                else if (nzmax <= 12)
                     nearv += rows(std::integral_constant<int, 12>{}, xa, xb, p0);
                 else
                     nearv += rows_var(xa, xb, p0);
