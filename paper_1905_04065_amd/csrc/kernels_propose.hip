@@ -282,9 +282,11 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         else
             phi = l2p_cols<P, double>(psi + cell, M, ux, uy, uz);
     }
+    // The near field is summed per row in the working precision and the row
+    // sums in FP64, so FP32 rounding does not grow with the box (mixed).
     // rowof(i, j, shx, shy, shz): the charges of plane row (i, j), indexed by z
     auto near_sum = [&](auto rowof) {
-        Real acc = Real(0);
+        double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const int ilo = a ? rx.lo1 : rx.lo0, ihi = a ? rx.hi1 : rx.hi0, shx = a ? rx.sh1 : rx.sh0;
@@ -302,13 +304,14 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
                             const int shz = e ? rz.sh1 : rz.sh0;
                             const int off = sk - shz;
                             const auto row = rowof(i, j, shx, shy, shz);
+                            Real racc = Real(0);
                             // 1/sqrt(0) is stored as 0: the site's own occupant drops out
                             if (g.tab_ok) {
                                 // d2 = dij + (off - k)^2, stepped without multiplies
                                 int d2 = dij + (off - klo) * (off - klo), st = 2 * (off - klo) - 1;
 #pragma unroll 4
                                 for (int k = klo; k <= khi; ++k) {
-                                    acc += row[k] * sInv[d2];
+                                    racc += row[k] * sInv[d2];
                                     d2 -= st;
                                     st -= 2;
                                 }
@@ -318,9 +321,10 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
                                     const int d2 = dij + dk * dk;
                                     const Real inv = d2 < kInvTab ? sInv[d2 < kInvTab ? d2 : 0]
                                                                   : Real(1) / sqrt((Real)d2);
-                                    acc += row[k] * inv;
+                                    racc += row[k] * inv;
                                 }
                             }
+                            acc += (double)racc;
                         }
                     }
                 }
@@ -328,7 +332,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         }
         return acc;
     };
-    Real nearv = Real(0);
+    double nearv = 0.0;
     if (tiled) {
         const int cpl = gen_tile_q<MIXED>() / (Ly * Lz);  // x-planes per chunk
         // plane coordinate u (unwrapped) -> lattice index, or -1 outside a free-space box
@@ -377,15 +381,17 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
             int off[NZ];
 #pragma unroll
             for (int z = 0; z < NZ; ++z) off[z] = z < nz ? (dz0 - z) * (dz0 - z) : kInvTab;
-            Real acc = Real(0);
+            double acc = 0.0;
             const int dx0 = si - xa;
             int dx2 = dx0 * dx0, stx = 2 * dx0 - 1;
             for (int x = xa; x <= xb; ++x, p0 += Ly * Lz) {
                 const Real *row = p0;
                 int b = dx2 + dy0 * dy0, sty = 2 * dy0 - 1;
                 for (int y = blo[1]; y <= bhi[1]; ++y, row += Lz) {
+                    Real racc = Real(0);
 #pragma unroll
-                    for (int z = 0; z < NZ; ++z) acc += row[z] * sInv[b + off[z]];
+                    for (int z = 0; z < NZ; ++z) racc += row[z] * sInv[b + off[z]];
+                    acc += (double)racc;
                     b -= sty;
                     sty -= 2;
                 }
@@ -396,7 +402,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         };
         // rows of the lane's own length, d^2 stepped along z as well
         auto rows_var = [&](int xa, int xb, const Real *p0) {
-            Real acc = Real(0);
+            double acc = 0.0;
             const int dx0 = si - xa, stz0 = 2 * dz0 - 1;
             int dx2 = dx0 * dx0 + dz0 * dz0, stx = 2 * dx0 - 1;
             for (int x = xa; x <= xb; ++x, p0 += Ly * Lz) {
@@ -404,12 +410,14 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
                 int d2y = dx2 + dy0 * dy0, sty = 2 * dy0 - 1;
                 for (int y = blo[1]; y <= bhi[1]; ++y, row += Lz) {
                     int d2 = d2y, st = stz0;
+                    Real racc = Real(0);
 #pragma unroll 4
                     for (int z = 0; z < nz; ++z) {
-                        acc += row[z] * sInv[d2];
+                        racc += row[z] * sInv[d2];
                         d2 -= st;
                         st -= 2;
                     }
+                    acc += (double)racc;
                     d2y -= sty;
                     sty -= 2;
                 }
@@ -445,7 +453,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         nearv = near_sum([&](int i, int j, int, int, int) { return Qg + ((int64_t)i * n + j) * n; });
     }
     if (!active) return;
-    phi += (double)nearv / g.h;
+    phi += nearv / g.h;
     if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
     const int32_t rk = site_rank[s];
     if (rk >= 0) phi_r[rk] = phi;

@@ -46,6 +46,39 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_general_lattice_staged_in_chunks(precision, tol):
+    """A general lattice (3.75 sites per cell edge: cells of 3 or 4 planes,
+    near-field boxes up to 12 planes) whose blocks' union boxes exceed the LDS
+    tile, so the site kernel stages them in several x-plane chunks and reads
+    the longest fixed-length rows.  The whole mask bit-exactly, a seeded
+    sample of slots against O-fmm (formed lazily)."""
+    import torch
+    n, L, p = 60, 5, 8
+    N = 2 * (int(0.4 * n ** 3) // 2)
+    sites, xyz, q = W.lattice_charges(n, N, 2024)
+    t, v = W.lattice_targets(sites, n, W.HOPS6, True)
+    v = v.reshape(-1)
+    K = len(W.HOPS6)
+    print(f"general lattice n={n} N={N} L={L} p={p} periodic {precision}", flush=True)
+    ctx = make_ctx(xyz, q, n, L, p, "periodic", precision)
+    ctx.initialise()
+    dU, mask = ctx.propose_lattice(W.HOPS6)
+    torch.cuda.synchronize()
+    dU = dU.cpu().numpy().reshape(-1)
+    assert np.array_equal(mask.cpu().numpy().reshape(-1).astype(bool), v)
+    assert np.all(np.isnan(dU[~v])) and not np.any(np.isnan(dU[v]))
+    ref = O.FmmKmc(xyz, q, n, L, p, "periodic", lazy=True)
+    pick = np.random.default_rng(W.BASE_SEED + 60).choice(np.nonzero(v)[0], 256, replace=False)
+    d_ref = ref.propose(pick // K, W.site_xyz(t.reshape(-1)[pick], n))
+    scale = float(np.mean(np.abs(dU[v])))
+    err = float(np.max(np.abs(dU[pick] - d_ref) / np.maximum(np.abs(d_ref), scale)))
+    print(f"  256 sampled slots of {v.sum()}: max guarded rel err {err:.3e}", flush=True)
+    assert err < tol
+    ctx.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("n,N,L,p,bc", CASES)
 def test_lattice_proposals_match_oracle(n, N, L, p, bc):
     import torch
