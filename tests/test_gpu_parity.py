@@ -43,6 +43,7 @@ CASES = [
     (16, 300, 3, 8, "periodic"),   # general site kernel, periodic
     (16, 400, 4, 8, "periodic"),   # 2x2x2 kernel, periodic
     (20, 500, 4, 7, "periodic"),   # non-integer cell width (2.5 sites), ties at cell faces
+    (16, 200, 2, 6, "free"),       # 8 sites per cell axis: boxes beyond the 1/sqrt table (computed 1/|d|)
 ]
 
 
