@@ -12,6 +12,19 @@
 
 namespace fmmkmc {
 
+// Global-memory view of a device pointer.  The batched kernels take their
+// pointers from a replica table, where the compiler cannot see that they
+// address global memory and would emit flat loads and stores (which also
+// count against the LDS wait counter).  Accesses through this view are global
+// ones; it must only be applied to device (global) allocations.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T *p)
+{
+    return (gptr<T>)p;
+}
+
 __host__ __device__ inline int64_t cell_id(int nc, int cx, int cy, int cz)
 {
     return ((int64_t)cx * nc + cy) * nc + cz;
@@ -62,8 +75,8 @@ struct RecTables {
 // loop: one column's coefficients are live at a time, so the compiler cannot
 // hoist all (p+1)^2 loads at once and the caller keeps a small register
 // footprint; the recurrence reciprocals come from RecTables (uniform indices).
-template <int P, typename T, bool SKIP0 = false>
-__device__ inline T l2p_cols(const T *L, long stride, T x, T y, T z)
+template <int P, typename T, bool SKIP0 = false, typename PT = const T *>
+__device__ inline T l2p_cols(PT L, long stride, T x, T y, T z)
 {
     constexpr RecTables RT{};
     const T r2 = x * x + y * y + z * z;

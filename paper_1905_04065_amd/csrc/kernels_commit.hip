@@ -104,9 +104,10 @@ struct ScaledIrregular {
     }
 };
 
-template <int P, int M0, int M1>
-__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv, double *__restrict__ psi,
-                           float *__restrict__ psi32)
+// PD, PF: pointers to the FP64 expansions and their FP32 shadow (or null),
+// generic or global-space
+template <int P, int M0, int M1, class PD, class PF>
+__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv, PD psi, PF psi32)
 {
     constexpr ScaledIrregular<P> SI{};
     constexpr int NACC = col_offset(P, M0, M1 + 1);
@@ -202,9 +203,8 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv,
     }
 }
 
-template <int P, int G = 0>
-__device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const Move &mv, double *psi,
-                               float *psi32)
+template <int P, int G = 0, class PD, class PF>
+__device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const Move &mv, PD psi, PF psi32)
 {
     if constexpr (G < n_groups(P)) {
         if (grp == G)
@@ -395,7 +395,12 @@ __global__ __launch_bounds__(256) void k_b_sweep(const RepDev *__restrict__ reps
     const int64_t cell = (blockIdx.x - base[r]) * blockDim.x + threadIdx.x;
     if (cell >= d.M) return;
     const Move m = mv.mv;  // a copy: the source loop then reads registers, not the descriptor in memory
-    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, m, d.psi, d.psi32);
+    // The expansions' pointers come from the replica table, so the compiler
+    // cannot tell they address global memory and would use flat loads and
+    // stores for the write-back; global-space pointers keep it global.
+    using GD = __attribute__((address_space(1))) double;
+    using GF = __attribute__((address_space(1))) float;
+    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, m, (GD *)d.psi, (GF *)d.psi32);
 }
 
 __global__ void k_b_path(const RepDev *__restrict__ reps, int R, const int64_t *__restrict__ base,

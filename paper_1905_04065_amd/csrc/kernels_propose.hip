@@ -118,12 +118,11 @@ void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz,
 // ---- lattice sites, any cell geometry --------------------------------------
 
 // far-field potential at lattice site (i, j, k) from the Chebyshev columns
-template <int P>
-__device__ inline double far_site(int n, int i, int j, int k, const double *__restrict__ Bz,
-                                  const double *__restrict__ Tax)
+template <int P, typename PD = const double *>
+__device__ inline double far_site(int n, int i, int j, int k, PD Bz, PD Tax)
 {
-    const double *b = Bz + ((int64_t)i * n + j) * (P + 1);
-    const double *t = Tax + (int64_t)k * (P + 1);
+    const auto b = Bz + ((int64_t)i * n + j) * (P + 1);
+    const auto t = Tax + (int64_t)k * (P + 1);
     double acc = 0.0;
 #pragma unroll
     for (int cc = 0; cc <= P; ++cc) acc += b[cc] * t[cc];
@@ -181,17 +180,21 @@ constexpr int gen_smem_bytes()
 }
 
 template <int P, bool MIXED>
-__device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
-                                                  const float *__restrict__ psi32, const double *__restrict__ Bz,
-                                                  const double *__restrict__ Tax, const double *__restrict__ qsite,
-                                                  const float *__restrict__ qsite32,
-                                                  const int32_t *__restrict__ cell_rng,
-                                                  const int32_t *__restrict__ site_rank,
-                                                  double *__restrict__ phisite, double *__restrict__ phi_r,
+__device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi_,
+                                                  const float *__restrict__ psi32_, const double *__restrict__ Bz_,
+                                                  const double *__restrict__ Tax_, const double *__restrict__ qsite_,
+                                                  const float *__restrict__ qsite32_,
+                                                  const int32_t *__restrict__ cell_rng_,
+                                                  const int32_t *__restrict__ site_rank_,
+                                                  double *__restrict__ phisite_, double *__restrict__ phi_r_,
                                                   unsigned char *smem)
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     constexpr InvSqrtTab IT{};
+    const auto psi = as_global(psi_), Bz = as_global(Bz_), Tax = as_global(Tax_), qsite = as_global(qsite_);
+    const auto psi32 = as_global(psi32_), qsite32 = as_global(qsite32_);
+    const auto cell_rng = as_global(cell_rng_), site_rank = as_global(site_rank_);
+    const auto phisite = as_global(phisite_), phi_r = as_global(phi_r_);
     // 1/sqrt table, then kInvTab zeros: the weight of a padded row entry
     constexpr int kTab = 2 * kInvTab;
     Real *sInv = (Real *)smem;                // kTab
@@ -208,7 +211,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         sHi[t] = -0x7fffffff;
     }
     if (t == 0) *sNz = 0;
-    const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
+    const gptr<const Real> Qs = MIXED ? (gptr<const Real>)qsite32 : (gptr<const Real>)qsite;
     // per axis, the planes of cells c-1, c, c+1 are at most two runs of
     // consecutive indices (two when the block wraps around a periodic face);
     // run r of an axis: planes [lo_r, hi_r] shifted by sh_r planes (empty if hi_r < lo_r)
@@ -280,7 +283,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         if (MIXED)
             phi = psi[cell] + (double)l2p_cols<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
         else
-            phi = l2p_cols<P, double>(psi + cell, M, ux, uy, uz);
+            phi = l2p_cols<P, double>((gptr<const double>)psi + cell, M, ux, uy, uz);
     }
     // The near field is summed per row in the working precision and the row
     // sums in FP64, so FP32 rounding does not grow with the box (mixed).
@@ -446,11 +449,8 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
             }
         }
     } else if (active) {
-        // the per-site array (wrapped z), read through a pointer of known
-        // address space so the loop uses global rather than flat loads
-        using GReal = const __attribute__((address_space(1))) Real;
-        GReal *Qg = (GReal *)Qs;
-        nearv = near_sum([&](int i, int j, int, int, int) { return Qg + ((int64_t)i * n + j) * n; });
+        // the per-site array (wrapped z)
+        nearv = near_sum([&](int i, int j, int, int, int) { return Qs + ((int64_t)i * n + j) * n; });
     }
     if (!active) return;
     phi += nearv / g.h;
@@ -576,14 +576,18 @@ constexpr int s2_smem_bytes()
 }
 
 template <int P, bool MIXED, int NW>
-__device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
-                                             const float *__restrict__ psi32, const double *__restrict__ qsite,
-                                             const float *__restrict__ qsite32,
-                                             const int32_t *__restrict__ site_rank, const double *__restrict__ Bz,
-                                             const double *__restrict__ Tax, double *__restrict__ phisite,
-                                             double *__restrict__ phi_r, unsigned char *smem)
+__device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi_,
+                                             const float *__restrict__ psi32_, const double *__restrict__ qsite_,
+                                             const float *__restrict__ qsite32_,
+                                             const int32_t *__restrict__ site_rank_, const double *__restrict__ Bz_,
+                                             const double *__restrict__ Tax_, double *__restrict__ phisite_,
+                                             double *__restrict__ phi_r_, unsigned char *smem)
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
+    const auto psi = as_global(psi_), Bz = as_global(Bz_), Tax = as_global(Tax_), qsite = as_global(qsite_);
+    const auto psi32 = as_global(psi32_), qsite32 = as_global(qsite32_);
+    const auto site_rank = as_global(site_rank_);
+    const auto phisite = as_global(phisite_), phi_r = as_global(phi_r_);
     constexpr S2Weights<P> W{};
     constexpr InvSqrt IS{};
     // per cell and site: local-expansion part, near + far-field part (row of 9: no bank conflicts)
@@ -606,7 +610,7 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
     const int nc = g.nc;
     if (class_wave) {
         if (cell < M) {
-            const Real *Ps = MIXED ? (const Real *)psi32 : (const Real *)psi;
+            const gptr<const Real> Ps = MIXED ? (gptr<const Real>)psi32 : (gptr<const Real>)psi;
             // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part
             Real S[2][2][2] = {};
             Real hn = Real(1);
@@ -647,7 +651,7 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
             }
         }
     } else if (cell < M) {
-        const Real *Qs = MIXED ? (const Real *)qsite32 : (const Real *)qsite;
+        const gptr<const Real> Qs = MIXED ? (gptr<const Real>)qsite32 : (gptr<const Real>)qsite;
         const int cx = (int)(cell / ((int64_t)nc * nc)), cy = (int)((cell / nc) % nc), cz = (int)(cell % nc);
         // near field: the 27 neighbour cells' 8 sites each (wrapped, or absent in
         // free space); the next cell's charges are loaded while the current one is summed
@@ -663,16 +667,20 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
         // The wrapped address is always inside the table, so the loads are
         // unconditional (no branch per load) and an absent cell is zeroed after.
         auto load8 = [&](int64_t base, bool ok, Real *o) {
+            // builtin vector types: the HIP wrapper types cannot be copied
+            // out of a global-space reference
+            typedef float vf4 __attribute__((ext_vector_type(4)));
+            typedef double vd2 __attribute__((ext_vector_type(2)));
             if constexpr (MIXED) {
-                const float4 *q4 = (const float4 *)(Qs + base);
-                const float4 a0 = q4[0], a1 = q4[1];
+                const gptr<const vf4> q4 = (gptr<const vf4>)(Qs + base);
+                const vf4 a0 = q4[0], a1 = q4[1];
                 o[0] = a0.x, o[1] = a0.y, o[2] = a0.z, o[3] = a0.w;
                 o[4] = a1.x, o[5] = a1.y, o[6] = a1.z, o[7] = a1.w;
             } else {
-                const double2 *q2 = (const double2 *)(Qs + base);
+                const gptr<const vd2> q2 = (gptr<const vd2>)(Qs + base);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const double2 a = q2[t];
+                    const vd2 a = q2[t];
                     o[2 * t] = a.x;
                     o[2 * t + 1] = a.y;
                 }
@@ -707,11 +715,11 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
         double fs[8] = {};
         if (g.periodic) {
             const int n = g.n;
-            const double *t0 = Tax + (int64_t)(2 * cz) * (P + 1);
+            const auto t0 = Tax + (int64_t)(2 * cz) * (P + 1);
 #pragma unroll
             for (int ij = 0; ij < 4; ++ij) {
                 const int i = 2 * cx + (ij >> 1), j = 2 * cy + (ij & 1);
-                const double *bz = Bz + ((int64_t)i * n + j) * (P + 1);
+                const auto bz = Bz + ((int64_t)i * n + j) * (P + 1);
                 double a0 = 0.0, a1 = 0.0;
 #pragma unroll
                 for (int cc = 0; cc <= P; ++cc) {
@@ -791,12 +799,16 @@ constexpr int SLOTB = 4;  // slots per lane whose loads are in flight together
 
 template <int TC>
 __device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_t K, uint32_t kmul,
-                                          const int32_t *__restrict__ offs, const int32_t *__restrict__ order,
-                                          const int32_t *__restrict__ ijk_r, const double *__restrict__ q_r,
-                                          const double *__restrict__ phi_r, const double *__restrict__ phisite,
-                                          const double *__restrict__ F, int s2, double *__restrict__ dU,
-                                          uint8_t *__restrict__ mask)
+                                          const int32_t *__restrict__ offs_, const int32_t *__restrict__ order_,
+                                          const int32_t *__restrict__ ijk_r_, const double *__restrict__ q_r_,
+                                          const double *__restrict__ phi_r_, const double *__restrict__ phisite_,
+                                          const double *__restrict__ F_, int s2, double *__restrict__ dU_,
+                                          uint8_t *__restrict__ mask_)
 {
+    const auto offs = as_global(offs_), order = as_global(order_), ijk_r = as_global(ijk_r_);
+    const auto q_r = as_global(q_r_), phi_r = as_global(phi_r_), phisite = as_global(phisite_), F = as_global(F_);
+    const auto dU = as_global(dU_);
+    const auto mask = as_global(mask_);
     __shared__ int32_t soff[3 * kMaxHops];
     __shared__ int32_t s_ijk[TC], s_ord[TC];
     __shared__ double s_q[TC], s_phi[TC];
