@@ -812,17 +812,21 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
         // C1: dU of the move (footnote to Sec. 3.1) as partial sums, read back
         // after the commit kernels are queued behind it (one synchronisation per accept)
         double *dUd = c->acc_buf;
-        launch_move_dU(c, g, i, np, dUd);
-        // The work beside the sweep goes to the side stream, after dU of the
-        // move and every earlier proposal (they read the old state): the moved
-        // charge's row of the lattice proposal table (it depends only on the new
-        // site), the multipole path, the bookkeeping and the far-field refresh.
-        // None of it touches the fine-level expansions or what the sweep reads.
+        // the part that reads the fine-level expansions, before the sweep
+        launch_move_dU(c, g, i, np, dUd, c->stream, 0, 1);
+        // The work beside the sweep goes to the side stream, after every earlier
+        // proposal (they read the old state): the rest of the move's dU (cell
+        // lists and far-field tables, read before the bookkeeping and the
+        // far-field refresh change them), the moved charge's row of the lattice
+        // proposal table (it depends only on the new site), the multipole path,
+        // the bookkeeping and the far-field refresh.  None of it touches the
+        // fine-level expansions or what the sweep reads.
         const bool need_row = c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty();
         const int Krow = (int)c->F_offsets.size() / 3;
         bool row_launched = false;
         HIPCHK(hipEventRecord(c->ev_fork, c->stream));
         HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        launch_move_dU(c, g, i, np, dUd, c->aux, 1, kMoveParts - 1);
         if (need_row) row_launched = launch_f_row1(c, g, Krow, c->hrank[i], new_site, c->aux);
         // C2 + C3
         CommitArgs a;

@@ -481,12 +481,16 @@ void record_step(fmmkmc_batch *b)
                 b->count.d, b->rates, b->wsum);
     launch_prof(b->prof, s, "b_select", k_b_select, dim3((unsigned)R), dim3(256), 0, b->reps, R, b->count.d,
                 b->wsum, b->rates, b->u, b->step, b->moves, b->Q);
-    launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt);
-    // beside the sweep, on the side stream: the F rows (they depend only on the
-    // moves), the multipole paths, the bookkeeping and the far field; none of
-    // it touches the fine-level expansions or what the sweep reads
+    // the part of the move's dU that reads the fine-level expansions, before the sweep
+    launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt, 0, 1);
+    // beside the sweep, on the side stream: the rest of the move's dU (cell
+    // lists and far-field tables, before the bookkeeping and the far-field
+    // update change them), the F rows (they depend only on the moves), the
+    // multipole paths, the bookkeeping and the far field; none of it touches
+    // the fine-level expansions or what the sweep reads
     HIPCHK(hipEventRecord(b->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
+    launch_b_move_dU(b->prof, b->aux, b->reps, R, b->moves, b->acc, b->nt, 1, kMoveParts - 1);
     launch_b_frow(b->prof, b->aux, b->reps, R, b->moves, b->nt, b->K);
     launch_b_path(b->prof, b->aux, b->reps, R, b->path.d, b->path.blocks, b->moves);
     launch_b_book(b->prof, b->aux, b->reps, R, b->moves);

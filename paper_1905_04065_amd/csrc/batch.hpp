@@ -75,8 +75,9 @@ void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, cons
                    int p, bool mixed);
 void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                    int tc);
+// parts [part0, part0 + nparts) of every replica's move dU
 void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, double *acc,
-                      int nt);
+                      int nt, int part0, int nparts);
 size_t f_row1_shm(int nt, int K);
 void launch_b_frow(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, int nt, int K);
 void launch_b_sweep(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,

@@ -113,9 +113,14 @@ void launch_expand_groups(fmmkmc_ctx *c, int64_t G, const int64_t *idx, const in
 void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int ntypes, const int32_t *T,
                         const uint8_t *Mk, int32_t *use);
 // accept
-// dU of a move as kMoveParts partial sums out[0..kMoveParts-1] (added by the caller in index order)
+// dU of a move as kMoveParts partial sums out[0..kMoveParts-1] (added by the
+// caller in index order): part 0 reads the fine-level expansions (so it must
+// precede the sweep), parts 1..3 the cell lists and the far-field tables (so
+// they must precede the bookkeeping and the far-field update).  Launches
+// parts [part0, part0 + nparts) on stream st (the context's stream if null).
 constexpr int kMoveParts = 4;
-void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out);
+void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out,
+                    hipStream_t st = nullptr, int part0 = 0, int nparts = kMoveParts);
 // F row of one charge (rank, lattice site s) on stream st; false (nothing
 // launched) when its tables exceed the kernel's LDS, then use launch_f_rows
 bool launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t s, hipStream_t st);

@@ -1256,16 +1256,18 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
                                                  const double *__restrict__ y, const double *__restrict__ z,
                                                  const double *__restrict__ q, const int32_t *__restrict__ cnt,
                                                  const int32_t *__restrict__ slots, const double *__restrict__ R,
-                                                 const double *__restrict__ H, double *__restrict__ out)
+                                                 const double *__restrict__ H, double *__restrict__ out, int part0)
 {
-    move_dU_body(blockIdx.x, g, p, M, i, tx, ty, tz, psi, x, y, z, q, cnt, slots, R, H, out);
+    move_dU_body(part0 + (int)blockIdx.x, g, p, M, i, tx, ty, tz, psi, x, y, z, q, cnt, slots, R, H, out);
 }
 
-void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out)
+void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out, hipStream_t st,
+                    int part0, int nparts)
 {
     const size_t shm = sizeof(double) * (4 * c->nt + 256);
-    launch_shm(c, "move_dU", k_move_dU, dim3(kMoveParts), dim3(256), shm, g, c->p, c->M, i, t[0], t[1], t[2],
-               c->psi_lv[c->L], c->x, c->y, c->z, c->q, c->cell_cnt, c->cell_slots, c->far.R, c->far.H, out);
+    launch_on(c, st ? st : c->stream, part0 == 0 ? "move_dU" : "move_dU_side", k_move_dU, dim3(nparts), dim3(256),
+              shm, g, c->p, c->M, i, t[0], t[1], t[2], c->psi_lv[c->L], c->x, c->y, c->z, c->q, c->cell_cnt,
+              c->cell_slots, c->far.R, c->far.H, out, part0);
 }
 
 // ---- generic proposals ----------------------------------------------------
@@ -1499,11 +1501,12 @@ __global__ __launch_bounds__(256) void k_b_slot(const RepDev *__restrict__ reps,
                   d.phi_r, d.phisite, d.F, d.s2, d.dU, d.mask);
 }
 
-// kMoveParts blocks per replica
+// nparts blocks per replica: parts part0 .. part0 + nparts - 1
 __global__ __launch_bounds__(256) void k_b_move_dU(const RepDev *__restrict__ reps,
-                                                   const MoveDev *__restrict__ moves, double *__restrict__ acc)
+                                                   const MoveDev *__restrict__ moves, double *__restrict__ acc,
+                                                   int part0, int nparts)
 {
-    const int r = blockIdx.x / kMoveParts, part = blockIdx.x % kMoveParts;
+    const int r = blockIdx.x / nparts, part = part0 + (int)(blockIdx.x % nparts);
     const MoveDev &mv = moves[r];
     if (!mv.valid) return;
     const RepDev &d = reps[r];
@@ -1545,10 +1548,11 @@ void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, cons
 }
 
 void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, double *acc,
-                      int nt)
+                      int nt, int part0, int nparts)
 {
     const size_t shm = sizeof(double) * (4 * nt + 256);
-    launch_prof(pr, st, "b_move_dU", k_b_move_dU, dim3((unsigned)(R * kMoveParts)), dim3(256), shm, reps, moves, acc);
+    launch_prof(pr, st, part0 == 0 ? "b_move_dU" : "b_move_dU_side", k_b_move_dU, dim3((unsigned)(R * nparts)),
+                dim3(256), shm, reps, moves, acc, part0, nparts);
 }
 
 size_t f_row1_shm(int nt, int K) { return sizeof(double) * ((size_t)(K + 3) * nt + 256 + 27 * (size_t)K); }
