@@ -104,10 +104,40 @@ struct ScaledIrregular {
     }
 };
 
+// The sources of a move: -q at the old and +q at the new position, each with
+// its copies nu in V_box (periodic; 2 x 27) or alone (free space; 2).  Every
+// lane of a block reads the same source at the same time, so the block builds
+// this table once in LDS: the copy's position, its charge and its fine-cell
+// coordinates (unwrapped, for the near-field test).
+struct SweepSources {
+    double x[54], y[54], z[54], q[54];
+    int gx[54], gy[54], gz[54];
+};
+
+// by the first 2 x 27 (2) threads of the block; a barrier must follow
+__device__ inline void sweep_sources(const Geo &g, const Move &mv, SweepSources &S)
+{
+    const int nimg = g.periodic ? 27 : 1;
+    const int t = threadIdx.x;
+    if (t < 2 * nimg) {
+        const int e = t >= nimg ? 1 : 0;
+        const int nu = t - e * nimg;
+        const int i = g.periodic ? nu / 9 - 1 : 0, j = g.periodic ? (nu / 3) % 3 - 1 : 0,
+                  k = g.periodic ? nu % 3 - 1 : 0;
+        S.gx[t] = (e ? mv.ngx : mv.ogx) + i * g.nc;
+        S.gy[t] = (e ? mv.ngy : mv.ogy) + j * g.nc;
+        S.gz[t] = (e ? mv.ngz : mv.ogz) + k * g.nc;
+        S.x[t] = (e ? mv.nx : mv.ox) + g.a * i;
+        S.y[t] = (e ? mv.ny : mv.oy) + g.a * j;
+        S.z[t] = (e ? mv.nz : mv.oz) + g.a * k;
+        S.q[t] = e ? mv.q : -mv.q;
+    }
+}
+
 // PD, PF: pointers to the FP64 expansions and their FP32 shadow (or null),
 // generic or global-space
 template <int P, int M0, int M1, class PD, class PF>
-__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv, PD psi, PF psi32)
+__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSources &S, PD psi, PF psi32)
 {
     constexpr ScaledIrregular<P> SI{};
     constexpr int NACC = col_offset(P, M0, M1 + 1);
@@ -117,26 +147,19 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv,
     const int nc = g.nc;
     const int bx = (int)(cell / ((int64_t)nc * nc)), by = (int)((cell / nc) % nc), bz = (int)(cell % nc);
     const double cxw = (bx + 0.5) * g.w, cyw = (by + 0.5) * g.w, czw = (bz + 0.5) * g.w;
-    // sources: -q at the old and +q at the new position, each with its copies
-    // nu in V_box (periodic) or alone; a copy whose cell is one of the 27 around
-    // this cell is in the near field and contributes with charge 0 (no branch,
-    // so the sums stay in place across iterations)
-    const int nimg = g.periodic ? 27 : 1;
+    // a source copy whose cell is one of the 27 around this cell is in the
+    // near field and contributes with charge 0 (no branch, so the sums stay in
+    // place across iterations)
+    const int nsrc = g.periodic ? 54 : 2;
 #pragma unroll 1
-    for (int t = 0; t < 2 * nimg; ++t) {
-        const int e = t >= nimg ? 1 : 0;
-        const int nu = t - e * nimg;
-        const int i = g.periodic ? nu / 9 - 1 : 0, j = g.periodic ? (nu / 3) % 3 - 1 : 0,
-                  k = g.periodic ? nu % 3 - 1 : 0;
-        const int gx = (e ? mv.ngx : mv.ogx) + i * nc, gy = (e ? mv.ngy : mv.ogy) + j * nc,
-                  gz = (e ? mv.ngz : mv.ogz) + k * nc;
-        const bool near = abs(gx - bx) <= 1 && abs(gy - by) <= 1 && abs(gz - bz) <= 1;
-        double dx = (e ? mv.nx : mv.ox) + g.a * i - cxw, dy = (e ? mv.ny : mv.oy) + g.a * j - cyw,
-               dz = (e ? mv.nz : mv.oz) + g.a * k - czw;
+    for (int t = 0; t < nsrc; ++t) {
+        const bool near = ((unsigned)(S.gx[t] - bx + 1) <= 2u) & ((unsigned)(S.gy[t] - by + 1) <= 2u) &
+                          ((unsigned)(S.gz[t] - bz + 1) <= 2u);
+        double dx = S.x[t] - cxw, dy = S.y[t] - cyw, dz = S.z[t] - czw;
         dx = near ? 1.0 : dx;
         dy = near ? 0.0 : dy;
         dz = near ? 0.0 : dz;
-        const double qq = near ? 0.0 : (e ? mv.q : -mv.q);
+        const double qq = near ? 0.0 : S.q[t];
         const double rho = rsqrt_nr(dx * dx + dy * dy + dz * dz);
         const double xh = dx * rho, yh = dy * rho, zh = dz * rho;
         double w[P + 1];  // q rho^(n+1)
@@ -204,13 +227,14 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const Move &mv,
 }
 
 template <int P, int G = 0, class PD, class PF>
-__device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const Move &mv, PD psi, PF psi32)
+__device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const SweepSources &S, PD psi,
+                               PF psi32)
 {
     if constexpr (G < n_groups(P)) {
         if (grp == G)
-            sweep_cols<P, group_m0(P, G), group_end(P, group_m0(P, G))>(g, M, cell, mv, psi, psi32);
+            sweep_cols<P, group_m0(P, G), group_end(P, group_m0(P, G))>(g, M, cell, S, psi, psi32);
         else
-            sweep_dispatch<P, G + 1>(grp, g, M, cell, mv, psi, psi32);
+            sweep_dispatch<P, G + 1>(grp, g, M, cell, S, psi, psi32);
     }
 }
 
@@ -218,9 +242,12 @@ template <int P>
 __global__ __launch_bounds__(256) void k_sweep(Geo g, int64_t M, Move mv, double *__restrict__ psi,
                                                float *__restrict__ psi32)
 {
+    __shared__ SweepSources S;
+    sweep_sources(g, mv, S);
+    __syncthreads();
     const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= M) return;
-    sweep_dispatch<P>(blockIdx.y, g, M, cell, mv, psi, psi32);
+    sweep_dispatch<P>(blockIdx.y, g, M, cell, S, psi, psi32);
 }
 
 // P2M of -q at the old and +q at the new position into the cells containing
@@ -390,17 +417,19 @@ __global__ __launch_bounds__(256) void k_b_sweep(const RepDev *__restrict__ reps
 {
     const int r = find_rep(base, R, blockIdx.x);
     const MoveDev &mv = moves[r];
-    if (!mv.valid) return;
+    if (!mv.valid) return;  // uniform over the block
     const RepDev &d = reps[r];
+    __shared__ SweepSources S;
+    sweep_sources(d.g, mv.mv, S);
+    __syncthreads();
     const int64_t cell = (blockIdx.x - base[r]) * blockDim.x + threadIdx.x;
     if (cell >= d.M) return;
-    const Move m = mv.mv;  // a copy: the source loop then reads registers, not the descriptor in memory
     // The expansions' pointers come from the replica table, so the compiler
     // cannot tell they address global memory and would use flat loads and
     // stores for the write-back; global-space pointers keep it global.
     using GD = __attribute__((address_space(1))) double;
     using GF = __attribute__((address_space(1))) float;
-    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, m, (GD *)d.psi, (GF *)d.psi32);
+    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, S, (GD *)d.psi, (GF *)d.psi32);
 }
 
 __global__ void k_b_path(const RepDev *__restrict__ reps, int R, const int64_t *__restrict__ base,
@@ -426,6 +455,7 @@ __global__ void k_b_book(const RepDev *__restrict__ reps, int R, const MoveDev *
 void launch_b_sweep(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                     int p, const MoveDev *moves, int block)
 {
+    if (block < 64) block = 64;  // the block fills its 54-entry source table with one thread per entry
     FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_sweep", k_b_sweep<P_>, dim3((unsigned)blocks, n_groups(P_)),
                                      dim3(block), 0, reps, R, base, moves));
 }
