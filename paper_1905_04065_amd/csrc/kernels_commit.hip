@@ -156,12 +156,12 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
     for (int t = 0; t < nsrc; ++t) {
         const bool near = ((unsigned)(S.gx[t] - bx + 1) <= 2u) & ((unsigned)(S.gy[t] - by + 1) <= 2u) &
                           ((unsigned)(S.gz[t] - bz + 1) <= 2u);
-        double dx = S.x[t] - cxw, dy = S.y[t] - cyw, dz = S.z[t] - czw;
-        dx = near ? 1.0 : dx;
-        dy = near ? 0.0 : dy;
-        dz = near ? 0.0 : dz;
+        // for a near copy the weights are exactly zero; 1/|d| is taken as 1 so
+        // that every factor stays finite (|d| may be 0), and the zero weights
+        // then add exactly nothing
+        const double dx = S.x[t] - cxw, dy = S.y[t] - cyw, dz = S.z[t] - czw;
         const double qq = near ? 0.0 : S.q[t];
-        const double rho = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+        const double rho = rsqrt_nr(near ? 1.0 : dx * dx + dy * dy + dz * dz);
         const double xh = dx * rho, yh = dy * rho, zh = dz * rho;
         double w[P + 1];  // q rho^(n+1)
         w[0] = qq * rho;
