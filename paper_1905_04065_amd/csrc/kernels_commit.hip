@@ -167,15 +167,33 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
         w[0] = qq * rho;
 #pragma unroll
         for (int n = 1; n <= P; ++n) w[n] = w[n - 1] * rho;
+        // diagonal T_m^m = z^m with z = -(xh + i yh): the group's first order
+        // M0 by repeated squaring, then one step per order
         double dr = 1.0, di = 0.0;
+        {
+            double br = -xh, bi = -yh;  // z^(2^b)
 #pragma unroll
-        for (int m = 0; m <= M1; ++m) {
-            if (m > 0) {
+            for (int b = 0; (1 << b) <= M0; ++b) {
+                if ((M0 >> b) & 1) {
+                    const double ndr = dr * br - di * bi, ndi = dr * bi + di * br;
+                    dr = ndr;
+                    di = ndi;
+                }
+                if ((2 << b) <= M0) {
+                    const double nbr = br * br - bi * bi, nbi = 2.0 * br * bi;
+                    br = nbr;
+                    bi = nbi;
+                }
+            }
+        }
+#pragma unroll
+        for (int m = M0; m <= M1; ++m) {
+            if (m > M0) {
                 const double ndr = yh * di - xh * dr, ndi = -(xh * di + yh * dr);
                 dr = ndr;
                 di = ndi;
             }
-            if (m >= M0) {
+            {
                 const int o = col_offset(P, M0, m);
                 const bool cplxcol = m > 0;
                 double ar = dr, ai = di;
