@@ -172,7 +172,8 @@ constexpr int gen_tile_q()
     return MIXED ? kTileQ : kTileQ64;
 }
 
-// LDS of the general body: the 1/sqrt table, the staged charges, the box bounds
+// LDS of the general body: the 1/sqrt table and its zero half, the staged
+// charges and their zero pad, the union box bounds and the longest row
 template <bool MIXED>
 constexpr int gen_smem_bytes()
 {
