@@ -438,15 +438,21 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
             const int xa = max(blo[0], x0), xb = min(bhi[0], x0 + nxp - 1);
             if (active && xa <= xb) {
                 const Real *p0 = sQ + ((xa - x0) * Ly + (blo[1] - loy)) * Lz + (blo[2] - loz);
-                const int nzmax = *sNz;  // uniform
-                if (nzmax <= 6)
-                    nearv += rows(std::integral_constant<int, 6>{}, xa, xb, p0);
-                else if (nzmax <= 9)
-                    nearv += rows(std::integral_constant<int, 9>{}, xa, xb, p0);
-                else if (nzmax <= 12)
-                    nearv += rows(std::integral_constant<int, 12>{}, xa, xb, p0);
-                else
-                    nearv += rows_var(xa, xb, p0);
+                // row length: the block's longest (uniform), so that padding is
+                // only the difference between its lanes
+                using std::integral_constant;
+                switch (*sNz) {
+                case 1: case 2: case 3: case 4: nearv += rows(integral_constant<int, 4>{}, xa, xb, p0); break;
+                case 5: nearv += rows(integral_constant<int, 5>{}, xa, xb, p0); break;
+                case 6: nearv += rows(integral_constant<int, 6>{}, xa, xb, p0); break;
+                case 7: nearv += rows(integral_constant<int, 7>{}, xa, xb, p0); break;
+                case 8: nearv += rows(integral_constant<int, 8>{}, xa, xb, p0); break;
+                case 9: nearv += rows(integral_constant<int, 9>{}, xa, xb, p0); break;
+                case 10: nearv += rows(integral_constant<int, 10>{}, xa, xb, p0); break;
+                case 11: nearv += rows(integral_constant<int, 11>{}, xa, xb, p0); break;
+                case 12: nearv += rows(integral_constant<int, 12>{}, xa, xb, p0); break;
+                default: nearv += rows_var(xa, xb, p0); break;
+                }
             }
         }
     } else if (active) {
