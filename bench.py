@@ -310,9 +310,12 @@ def run_unbatched_fp64(ctxs, steps, seed):
             vs = np.flatnonzero(m)
             slot = vs[int(u[r] * len(vs))]
             i, k = divmod(int(slot), 6)
-            t, _ = W.lattice_targets(cur[r][i:i + 1], int(ns[r]), W.HOPS6[k:k + 1], True)
-            c.accept(i, W.site_xyz([int(t[0, 0])], int(ns[r]))[0])
-            cur[r][i] = int(t[0, 0])
+            nr = int(ns[r])
+            s = int(cur[r][i])
+            ijk = (np.array([s // (nr * nr), (s // nr) % nr, s % nr]) + W.HOPS6[k]) % nr
+            t = int((ijk[0] * nr + ijk[1]) * nr + ijk[2])
+            c.accept(i, W.site_xyz([t], nr)[0])
+            cur[r][i] = t
 
     one_step(rng.random(R))
     torch.cuda.synchronize()
@@ -342,7 +345,7 @@ def cpu_baseline(n, N, L, p, hops, seed, budget_s=20.0):
     cells = np.floor(xyz / w).astype(int)
     inblock = np.all((cells >= nc // 2) & (cells < nc // 2 + 2), axis=1)
     idx_c = np.nonzero(inblock)[0]
-    t, valid = W.lattice_targets(sites[idx_c], n, hops, True)
+    t, valid = O.lattice_targets(sites[idx_c], n, hops, True)
     idx = np.repeat(idx_c, len(hops))[valid.reshape(-1)]
     tgt = W.site_xyz(t.reshape(-1)[valid.reshape(-1)], n)
     for x in np.concatenate([xyz[idx_c], tgt]):

@@ -18,6 +18,7 @@ import os
 import numpy as np
 
 from . import build as _build
+from .kmc import cumulative, lattice_targets, propensities, select_slot, time_increment  # noqa: F401
 
 _lib = None
 

@@ -56,7 +56,7 @@ def host_steps(ctx, rp, u, hops, cur):
             continue
         slot = vs[int(u[s] * len(vs))]
         i = int(slot // K)
-        t, _ = W.lattice_targets(cur[i:i + 1], rp["n"], hops[slot % K:slot % K + 1], True)
+        t, _ = O.lattice_targets(cur[i:i + 1], rp["n"], hops[slot % K:slot % K + 1], True)
         new_site = int(t.reshape(-1)[0])
         d = ctx.accept(i, W.site_xyz([new_site], rp["n"])[0])
         cur[i] = new_site
@@ -114,7 +114,7 @@ def test_batch_matches_single_context_and_oracle(precision):
             d_ref = ref.accept(int(moved[s, r]), W.site_xyz([site[s, r]], rp["n"])[0])
             scale = max(scale, abs(d_ref))
             assert abs(dU[s, r] - d_ref) <= 1e-10 * max(abs(d_ref), 0.05), (r, s, dU[s, r], d_ref)
-        t, v = W.lattice_targets(curs[r], rp["n"], hops, True)
+        t, v = O.lattice_targets(curs[r], rp["n"], hops, True)
         v = v.reshape(-1)
         idx = np.repeat(np.arange(rp["N"]), len(hops))[v]
         d_ref = ref.propose(idx, W.site_xyz(t.reshape(-1)[v], rp["n"]))
@@ -167,7 +167,7 @@ def test_single_context_accept_after_batched_steps():
     for s in range(5):
         ref.accept(int(moved[s, 0]), W.site_xyz([site[s, 0]], rp["n"])[0])
         cur[int(moved[s, 0])] = site[s, 0]
-    t, v = W.lattice_targets(cur, rp["n"], hops, True)
+    t, v = O.lattice_targets(cur, rp["n"], hops, True)
     vs = np.nonzero(v.reshape(-1))[0]
     slot = vs[len(vs) // 2]
     i, new = int(slot // 6), W.site_xyz([t.reshape(-1)[slot]], rp["n"])[0]
@@ -176,17 +176,6 @@ def test_single_context_accept_after_batched_steps():
     assert abs(d1 - d2) <= 1e-12 * max(1.0, abs(d2))
     assert c.energy == pytest.approx(ref.energy, rel=1e-12)
     batch.close()
-
-
-def rate_reference(kind, nu, beta, dU, valid):
-    """propensities of Alg. 1 in FP64 numpy, masked slots 0"""
-    r = np.zeros_like(dU)
-    x = -beta * dU[valid]
-    if kind == 1:
-        r[valid] = nu * np.exp(np.minimum(x, 600.0))
-    else:
-        r[valid] = np.where(x >= 0.0, nu, nu * np.exp(x))
-    return r
 
 
 @pytest.mark.parametrize("kind,precision", [(1, "fp64"), (2, "mixed")])
@@ -216,10 +205,10 @@ def test_propensity_weighted_selection(kind, precision):
             pdU, pm = batch.proposals(r)  # the pass this step selected from
             pdU = pdU.cpu().numpy().reshape(-1)
             v = pm.cpu().numpy().reshape(-1).astype(bool)
-            t, vv = W.lattice_targets(curs[r], rp["n"], hops, True)
+            t, vv = O.lattice_targets(curs[r], rp["n"], hops, True)
             assert np.array_equal(v, vv.reshape(-1))
-            rates = rate_reference(kind, nu, beta, pdU, v)
-            cum = np.cumsum(rates)
+            rates = O.propensities(kind, nu, beta, pdU, v)
+            cum = O.cumulative(rates)
             Q = cum[-1]
             T = Q * (1.0 - uu[s, r, 0])
             i = int(moved[0, r])
@@ -265,7 +254,7 @@ def test_rates_at_zero_beta_are_a_uniform_choice():
     for s in range(4):
         moved, site, dU, dt = (x.cpu().numpy() for x in batch.step(uu[s:s + 1], with_dt=True))
         for r, rp in enumerate(reps):
-            t, v = W.lattice_targets(curs[r], rp["n"], hops, True)
+            t, v = O.lattice_targets(curs[r], rp["n"], hops, True)
             vs = np.nonzero(v.reshape(-1))[0]
             V = len(vs)
             T = (3.0 * V) * (1.0 - uu[s, r, 0])

@@ -53,7 +53,7 @@ def test_config1_every_slot():
     sites, xyz, q, c = W.config_system(1)
     hops = W.hops(c["hops"])
     print(f"config 1: n={c['n']} N={len(q)} L={c['L']} p={c['p']} free", flush=True)
-    t, v = W.lattice_targets(sites, c["n"], hops, False)
+    t, v = O.lattice_targets(sites, c["n"], hops, False)
     v = v.reshape(-1)
     idx = np.repeat(np.arange(len(q)), len(hops))[v]
     tgt = W.site_xyz(t.reshape(-1)[v], c["n"])
@@ -91,7 +91,7 @@ def test_config2_hundred_steps_with_commit():
     total = 0.0
     for step in range(c["steps"]):
         dU, mask = gpu_lattice(ctx, hops)
-        t, v = W.lattice_targets(cur, n, hops, True)
+        t, v = O.lattice_targets(cur, n, hops, True)
         v = v.reshape(-1)
         if step == 0 or step == c["steps"] - 1:
             assert np.array_equal(mask, v), step
@@ -112,7 +112,7 @@ def test_config2_hundred_steps_with_commit():
     assert ctx.energy == pytest.approx(U0 + total, abs=1e-12 * max(1.0, abs(U0)))
     np.testing.assert_array_equal(ctx.positions().cpu().numpy(), ref.positions())
     dU, mask = gpu_lattice(ctx, hops)
-    t, v = W.lattice_targets(cur, n, hops, True)
+    t, v = O.lattice_targets(cur, n, hops, True)
     v = v.reshape(-1)
     assert np.array_equal(mask, v)
     rng = np.random.default_rng(W.BASE_SEED + 20)
@@ -135,7 +135,7 @@ def test_config3_mixed_drift_after_ten_thousand_commits():
     ctx.initialise()
     ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "free")
     d0, _ = gpu_lattice(ctx, hops)
-    t, v = W.lattice_targets(sites, n, hops, False)
+    t, v = O.lattice_targets(sites, n, hops, False)
     v = v.reshape(-1)
     idx = np.repeat(np.arange(N), K)
     r0 = ref.propose(idx[v], W.site_xyz(t.reshape(-1)[v], n))
@@ -145,7 +145,7 @@ def test_config3_mixed_drift_after_ten_thousand_commits():
     worst = 0.0
     scale = float(np.mean(np.abs(r0)))
     for step in range(commits):
-        t, v = W.lattice_targets(cur, n, hops, False)
+        t, v = O.lattice_targets(cur, n, hops, False)
         vs = np.nonzero(v.reshape(-1))[0]
         s = vs[int(u[step] * len(vs))]
         i = int(s // K)
@@ -155,7 +155,7 @@ def test_config3_mixed_drift_after_ten_thousand_commits():
         worst = max(worst, abs(d_gpu - d_ref) / max(abs(d_ref), scale))
         cur[i] = t.reshape(-1)[s]
     d1, mask = gpu_lattice(ctx, hops)
-    t, v = W.lattice_targets(cur, n, hops, False)
+    t, v = O.lattice_targets(cur, n, hops, False)
     v = v.reshape(-1)
     assert np.array_equal(mask, v)
     r1 = ref.propose(idx[v], W.site_xyz(t.reshape(-1)[v], n))
@@ -180,7 +180,7 @@ def test_config4_sampled_slots_and_full_mask(precision, tol):
     ctx = make_ctx(xyz, q, c, precision)
     ctx.initialise()
     dU, mask = gpu_lattice(ctx, hops)
-    t, v = W.lattice_targets(sites, n, hops, True)
+    t, v = O.lattice_targets(sites, n, hops, True)
     v = v.reshape(-1)
     assert np.array_equal(mask, v)
     assert np.all(np.isnan(dU[~v])) and not np.any(np.isnan(dU[v]))
@@ -197,7 +197,7 @@ def test_config4_sampled_slots_and_full_mask(precision, tol):
     u = W.commit_choices(3, W.BASE_SEED + 41)
     cur = sites.copy()
     for step in range(3):
-        t, v = W.lattice_targets(cur, n, hops, True)
+        t, v = O.lattice_targets(cur, n, hops, True)
         vs = np.nonzero(v.reshape(-1))[0]
         s = vs[int(u[step] * len(vs))]
         i = int(s // K)
@@ -207,7 +207,7 @@ def test_config4_sampled_slots_and_full_mask(precision, tol):
         assert abs(d_gpu - d_ref) <= 1e-10 * max(abs(d_ref), scale), (step, d_gpu, d_ref)
         cur[i] = t.reshape(-1)[s]
     dU, mask = gpu_lattice(ctx, hops)
-    t, v = W.lattice_targets(cur, n, hops, True)
+    t, v = O.lattice_targets(cur, n, hops, True)
     v = v.reshape(-1)
     assert np.array_equal(mask, v)
     pick = rng.choice(np.nonzero(v)[0], 128, replace=False)

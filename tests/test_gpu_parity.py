@@ -23,7 +23,7 @@ def guarded_err(d, ref):
 
 def lattice_case(n, N, seed, periodic, hops=W.HOPS6):
     sites, xyz, q = W.lattice_charges(n, N, seed)
-    t, valid = W.lattice_targets(sites, n, hops, periodic)
+    t, valid = O.lattice_targets(sites, n, hops, periodic)
     idx = np.repeat(np.arange(N), len(hops))
     tgt = W.site_xyz(t.reshape(-1), n)
     return sites, xyz, q, idx, tgt, valid.reshape(-1)
@@ -58,7 +58,7 @@ def test_general_lattice_staged_in_chunks(precision, tol):
     n, L, p = 60, 5, 8
     N = 2 * (int(0.4 * n ** 3) // 2)
     sites, xyz, q = W.lattice_charges(n, N, 2024)
-    t, v = W.lattice_targets(sites, n, W.HOPS6, True)
+    t, v = O.lattice_targets(sites, n, W.HOPS6, True)
     v = v.reshape(-1)
     K = len(W.HOPS6)
     print(f"general lattice n={n} N={N} L={L} p={p} periodic {precision}", flush=True)
@@ -155,7 +155,7 @@ def test_commits_match_oracle_replay(n, N, L, p, bc):
     u = W.commit_choices(25, 99)
     cur_sites = sites.copy()
     for step in range(25):
-        t, vmask = W.lattice_targets(cur_sites, n, W.HOPS6, periodic)
+        t, vmask = O.lattice_targets(cur_sites, n, W.HOPS6, periodic)
         vs = np.nonzero(vmask.reshape(-1))[0]
         s = vs[int(u[step] * len(vs))]
         i, k = divmod(int(s), 6)
@@ -166,7 +166,7 @@ def test_commits_match_oracle_replay(n, N, L, p, bc):
         cur_sites[i] = t.reshape(-1)[s]
     assert ctx.energy == pytest.approx(ref.energy, abs=1e-10 * abs(ref.energy))
     np.testing.assert_array_equal(ctx.positions().cpu().numpy(), ref.positions())
-    t, vmask = W.lattice_targets(cur_sites, n, W.HOPS6, periodic)
+    t, vmask = O.lattice_targets(cur_sites, n, W.HOPS6, periodic)
     dU, mask = ctx.propose_lattice(W.HOPS6)
     torch.cuda.synchronize()
     dU = dU.cpu().numpy().reshape(-1)
@@ -225,7 +225,7 @@ def test_propose_with_dats():
     T = rng.integers(0, 4, size=N).astype(np.int32)
     R = np.zeros((N, K, 3))
     M = np.ones((N, K), np.uint8)
-    t6, v6 = W.lattice_targets(sites, n, W.HOPS6, True)
+    t6, v6 = O.lattice_targets(sites, n, W.HOPS6, True)
     for i in range(N):
         for k in range(K):
             R[i, k] = W.site_xyz([t6[i, k]], n)[0]

@@ -30,7 +30,7 @@ def lattice(n, N, seed):
 
 
 def proposals(sites, n, periodic, hops=W.HOPS6):
-    t, valid = W.lattice_targets(sites, n, hops, periodic)
+    t, valid = O.lattice_targets(sites, n, hops, periodic)
     K = len(hops)
     idx = np.repeat(np.arange(len(sites)), K)
     tgt = W.site_xyz(t.reshape(-1), n)
@@ -181,3 +181,143 @@ def test_masked_and_singular_proposals_are_nan():
     f = O.FmmKmc(xyz, q, n, 3, 4, "free")
     d = f.propose([0, 0, 0, 1], [xyz[5], xyz[0], [n + 0.5, 1.5, 1.5], [0.5, 0.5, -0.5]])
     assert np.all(np.isnan(d))
+
+
+# ---- pins of the accept step's fine-level sweep (Sec. 3 "Accept move", Sec. 3.1 "Accept move") ----
+
+def _long_moves(f, sites, n, L, count, seed, min_cells=3):
+    """accept `count` seeded moves of random charges to random vacant sites at
+    least `min_cells` fine cells away (long moves cross many cells, so every
+    fine cell's expansion sees a moved copy leave or arrive outside its near
+    field); returns the current lattice sites"""
+    rng = np.random.default_rng(seed)
+    cur = np.array(sites, np.int64).copy()
+    occ = set(cur.tolist())
+    w = n / 2 ** (L - 1)
+    N = len(cur)
+    for _ in range(count):
+        while True:
+            i = int(rng.integers(N))
+            s = int(rng.integers(n ** 3))
+            if s in occ:
+                continue
+            a = W.site_xyz([cur[i]], n)[0]
+            b = W.site_xyz([s], n)[0]
+            if np.max(np.abs(np.floor(a / w) - np.floor(b / w))) >= min_cells:
+                break
+        f.accept(i, b)
+        occ.discard(int(cur[i]))
+        occ.add(s)
+        cur[i] = s
+    return cur
+
+
+def test_accept_sweep_long_moves_keep_free_space_dU_exact():
+    """After six long accepted moves, O-fmm's dU of every hop of every charge
+    matches the direct pair sum of the new configuration (O-exact) as closely as
+    a fresh system does (p = 16: truncation ~1e-7 of the mean).  Catches a sweep
+    that does nothing (the moved charge stays at its old place in every far
+    cell's expansion: errors ~1e-2), one that adds with the wrong sign, and one
+    that updates the wrong cells (a near cell counted twice or a far cell
+    missed)."""
+    n, N, L, p = 16, 150, 4, 16
+    sites, xyz, q = lattice(n, N, 21)
+    f = O.FmmKmc(xyz, q, n, L, p, "free")
+    idx, tgt, valid = proposals(sites, n, False)
+    ref0 = O.direct_dU(xyz, q, idx[valid], tgt[valid])
+    e0 = np.max(np.abs(f.propose(idx[valid], tgt[valid]) - ref0)) / np.mean(np.abs(ref0))
+    cur = _long_moves(f, sites, n, L, 6, 5)
+    xyz1 = W.site_xyz(cur, n)
+    np.testing.assert_array_equal(f.positions(), xyz1)
+    idx, tgt, valid = proposals(cur, n, False)
+    ref1 = O.direct_dU(xyz1, q, idx[valid], tgt[valid])
+    e1 = np.max(np.abs(f.propose(idx[valid], tgt[valid]) - ref1)) / np.mean(np.abs(ref1))
+    assert e0 < 2e-7
+    assert e1 < 3 * e0 + 1e-9, (e0, e1)
+    # and the total energy follows the accepted dU's to the direct energy
+    assert abs(f.energy - O.direct_energy(xyz1, q)) < 1e-6 * abs(O.direct_energy(xyz1, q))
+
+
+def test_accept_sweep_long_moves_keep_periodic_dU_exact():
+    """The periodic sweep moves all 27 copies of V_box: after five long moves
+    O-fmm's dU matches tin-foil Ewald for the new configuration within the
+    pre-commit band (p = 18).  Catches a sweep that moves only the primary copy
+    (missing images: the 26 copies around the box stay behind), a sign error,
+    or a wrong near test for wrapped copies."""
+    n, N, L, p = 8, 40, 3, 18
+    sites, xyz, q = lattice(n, N, 22)
+    f = O.FmmKmc(xyz, q, n, L, p, "periodic")
+    cur = _long_moves(f, sites, n, L, 5, 6, min_cells=2)
+    xyz1 = W.site_xyz(cur, n)
+    idx, tgt, valid = proposals(cur, n, True)
+    ref = O.ewald_dU(xyz1, q, n, idx[valid], tgt[valid])
+    d = f.propose(idx[valid], tgt[valid])
+    err = np.max(np.abs(d - ref)) / np.mean(np.abs(ref))
+    assert err < 2e-6, err
+    assert f.energy == pytest.approx(O.ewald_energy(xyz1, q, n), abs=1e-6)
+
+
+def _copies_outside_near(pos, g_cell, n_fine, w, a, periodic):
+    """the copies pos + a nu (nu in V_box, or nu = 0 in free space) whose fine
+    cell (extended coordinates) is not one of the 27 cells around g_cell"""
+    out = []
+    rng = (-1, 0, 1) if periodic else (0,)
+    for i in rng:
+        for j in rng:
+            for k in rng:
+                y = np.array(pos, float) + a * np.array([i, j, k], float)
+                gy = np.floor(y / w).astype(int)
+                if np.max(np.abs(gy - np.asarray(g_cell))) > 1:
+                    out.append(y)
+    return out
+
+
+@pytest.mark.parametrize("bc,n,N,L,p", [("free", 16, 120, 4, 14), ("periodic", 8, 40, 3, 14)])
+def test_accept_changes_each_local_expansion_by_its_far_copies(bc, n, N, L, p):
+    """One accepted move, every fine cell beta: at the cell centre a local
+    expansion reduces to its constant term, so the change of Psi_beta there must
+    equal, to rounding, the Coulomb change sum q (1/|c - r' - a nu| - 1/|c - r -
+    a nu|) over exactly the copies outside the 27 cells around beta (free
+    space: nu = 0 only), and at an interior point the same sum within the
+    truncation bound.  Catches a no-op sweep, a flipped sign, missing periodic
+    copies and a wrong near test (a near copy added, a far copy skipped)."""
+    periodic = bc == "periodic"
+    sites, xyz, q = lattice(n, N, 23)
+    f = O.FmmKmc(xyz, q, n, L, p, bc)
+    nf = 2 ** (L - 1)
+    w = n / nf
+    # a move between two cells that are not neighbours
+    i = 0
+    r = xyz[i].copy()
+    occ = set(sites.tolist())
+    rng = np.random.default_rng(7)
+    while True:
+        s = int(rng.integers(n ** 3))
+        t = W.site_xyz([s], n)[0]
+        if s not in occ and np.max(np.abs(np.floor(t / w) - np.floor(r / w))) >= 2:
+            break
+    cells = range(nf ** 3)
+    before = [f.local(c) for c in cells]
+    f.accept(i, t)
+    off = np.array([0.3, -0.2, 0.25]) * w
+    worst_c, worst_x, scale = 0.0, 0.0, 0.0
+    changed = 0
+    for c in cells:
+        g = np.array([c // (nf * nf), (c // nf) % nf, c % nf])
+        ctr = (g + 0.5) * w
+        dL = f.local(c) - before[c]
+        want_c = sum(q[i] / np.linalg.norm(ctr - y) for y in _copies_outside_near(t, g, nf, w, n, periodic)) - \
+            sum(q[i] / np.linalg.norm(ctr - y) for y in _copies_outside_near(r, g, nf, w, n, periodic))
+        x = ctr + off
+        want_x = sum(q[i] / np.linalg.norm(x - y) for y in _copies_outside_near(t, g, nf, w, n, periodic)) - \
+            sum(q[i] / np.linalg.norm(x - y) for y in _copies_outside_near(r, g, nf, w, n, periodic))
+        got_c = O.eval_local(p, dL, ctr, ctr)
+        got_x = O.eval_local(p, dL, ctr, x)
+        worst_c = max(worst_c, abs(got_c - want_c))
+        worst_x = max(worst_x, abs(got_x - want_x))
+        scale = max(scale, abs(want_c))
+        changed += abs(want_c) > 1e-12
+    assert changed > nf ** 3 // 2  # most cells see the move
+    assert worst_c <= 1e-13 * scale, (worst_c, scale)
+    # interior point at |x - c| = 0.45 w, copies beyond 1.5 w: ratio 0.3, bound ~ 0.3^(p+1) / w
+    assert worst_x <= 2 * 0.3 ** (p + 1) / w * 10, (worst_x, scale)

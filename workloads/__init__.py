@@ -106,30 +106,6 @@ def commit_choices(count, seed):
     return rng.random(count)
 
 
-def lattice_targets(sites, n, offsets, periodic):
-    """Target site of every (charge, hop) slot and a validity mask.
-
-    Masked (invalid) slots: the target is occupied, or (free space) it lies
-    off the lattice.  Returns (tsite int64[N,K], valid bool[N,K]).
-    """
-    sites = np.asarray(sites, np.int64)
-    i = sites // (n * n)
-    j = (sites // n) % n
-    k = sites % n
-    ijk = np.stack([i, j, k], 1)[:, None, :] + np.asarray(offsets, np.int64)[None, :, :]
-    if periodic:
-        inside = np.ones(ijk.shape[:2], bool)
-        ijk = ijk % n
-    else:
-        inside = np.all((ijk >= 0) & (ijk < n), axis=2)
-        ijk = np.clip(ijk, 0, n - 1)
-    t = (ijk[..., 0] * n + ijk[..., 1]) * n + ijk[..., 2]
-    occ = np.zeros(n ** 3, bool)
-    occ[sites] = True
-    valid = inside & ~occ[t]
-    return t, valid
-
-
 def perturbed_lattice(N, density, seed, jitter=0.1):
     """The error-study setup of Sec. 6.1: N charges (N a cube) on a cubic
     lattice at the given number density with small random perturbations,
