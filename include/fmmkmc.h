@@ -127,7 +127,22 @@ int fmmkmc_positions(fmmkmc_ctx *c, double *xyz);
  * expansions and the energy. */
 int fmmkmc_potential(fmmkmc_ctx *c, int64_t m, const double *xyz, const int64_t *exclude, double *out);
 
-/* Per-kernel timing: when on, every kernel launch is bracketed by HIP events
+/* Multipole expansion Phi of one cell of the octree (Eq. (multipole_local_expansion),
+ * kept current by the accept step's update of the moved charge's cells on every
+ * level, Sec. 3 "Accept move").  level in 1..L (root = 1); cell
+ * (ix * s + iy) * s + iz with s = 2^(level-1) cells per axis, cell (ix, iy, iz)
+ * covering [ix w, (ix+1) w) x ... with w = a / s, expanded about its centre c.
+ * out (HOST, (p+1)^2 doubles) gets M_n^m = sum_i q_i conj(R_n^m(r_i - c)) over
+ * the charges in the cell, with the regular solid harmonics
+ *   R_n^m(x) = (-1)^m |x|^n P_n^m(cos theta) e^{i m phi} / (n+m)!
+ * (P_n^m without the Condon-Shortley phase); slot n^2 holds M_n^0, slots
+ * n^2 + 2m - 1 and n^2 + 2m hold Re and Im of M_n^m for m = 1..n (the m < 0
+ * coefficients are (-1)^m conj(M_n^|m|)).  Level 1 is the whole box, whose
+ * multipole the far field uses (Sec. 3.1).  Errors: EINVAL (level or cell out of
+ * range), ESTATE (not initialised), EHIP. */
+int fmmkmc_multipole(fmmkmc_ctx *c, int level, int64_t cell, double *out);
+
+/* Per-kernel timing: when on,/* Per-kernel timing: when on, every kernel launch is bracketed by HIP events
  * on the context's stream.  fmmkmc_kernel_time() returns the accumulated time
  * (ms) and launch count of the named kernel since profiling was switched on. */
 int fmmkmc_set_profiling(fmmkmc_ctx *c, int on);

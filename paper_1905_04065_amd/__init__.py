@@ -61,6 +61,7 @@ def load_library():
         "fmmkmc_energy": (i32, [vp, C.POINTER(d)]),
         "fmmkmc_positions": (i32, [vp, vp]),
         "fmmkmc_potential": (i32, [vp, i64, vp, vp, vp]),
+        "fmmkmc_multipole": (i32, [vp, i32, i64, vp]),
         "fmmkmc_set_profiling": (i32, [vp, i32]),
         "fmmkmc_kernel_time": (i32, [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64)]),
         "fmmkmc_last_error": (C.c_char_p, [vp]),
@@ -253,6 +254,13 @@ class Context:
         if exclude is not None:
             ex = self._dev(exclude, torch.int64).reshape(-1)
         self._check(self._L.fmmkmc_potential(self._h, m, _ptr(xyz), _ptr(ex) if ex is not None else None, _ptr(out)))
+        return out
+
+    def multipole(self, level, cell):
+        """Phi of one octree cell in the library's real storage ((p+1)^2 doubles, see
+        fmmkmc_multipole in include/fmmkmc.h)"""
+        out = np.zeros((self.order + 1) ** 2)
+        self._check(self._L.fmmkmc_multipole(self._h, int(level), int(cell), out.ctypes.data_as(C.c_void_p)))
         return out
 
     def set_profiling(self, on=True):

@@ -15,8 +15,8 @@ using namespace fmmkmc;
 
 namespace {
 
-// scratch buffer of at least `bytes`
-void *scratch(fmmkmc_ctx *c, size_t bytes)
+// context-owned work buffer of at least `bytes` (grown on demand)
+void *work_buffer(fmmkmc_ctx *c, size_t bytes)
 {
     if (c->scr_bytes < bytes) {
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -640,7 +640,7 @@ int fmmkmc_initialise(fmmkmc_ctx *c, double *U_out)
         launch_downward(c);
         if (c->prec == FMMKMC_MIXED) launch_shadow(c);
         if (c->bc == FMMKMC_PERIODIC) launch_far_refresh(c);
-        double *phi = (double *)scratch(c, sizeof(double) * c->N);
+        double *phi = (double *)work_buffer(c, sizeof(double) * c->N);
         // the total energy is always evaluated from the FP64 expansions
         launch_point_phi(c, g, c->N, nullptr, c->iota, c->iota, c->bc == FMMKMC_PERIODIC ? 1 : 0, phi,
                          "point_phi_energy", true);
@@ -685,7 +685,7 @@ int fmmkmc_propose(fmmkmc_ctx *c, int64_t n_groups, const int64_t *idx, const in
         for (int64_t v : hidx)
             if (v < 0 || v >= c->N) return fail(c, FMMKMC_EINVAL, "charge index out of range");
         const size_t bytes = sizeof(double) * 8 * S + sizeof(int64_t) * S;
-        double *work = (double *)scratch(c, bytes);
+        double *work = (double *)work_buffer(c, bytes);
         int64_t *charge = (int64_t *)(work + 8 * S);
         clear_flags(c);
         const Geo g = make_geo(c);
@@ -712,7 +712,7 @@ int fmmkmc_propose_dats(fmmkmc_ctx *c, int K, const int32_t *C, int n_types, con
         HIPCHK(hipSetDevice(c->device));
         const int64_t S = c->N * K;
         const size_t bytes = sizeof(double) * 8 * S + sizeof(int64_t) * S + sizeof(int32_t) * (S + n_types);
-        double *work = (double *)scratch(c, bytes);
+        double *work = (double *)work_buffer(c, bytes);
         int64_t *charge = (int64_t *)(work + 8 * S);
         int32_t *use = (int32_t *)(charge + S);
         int32_t *dC = use + S;
@@ -926,6 +926,23 @@ int fmmkmc_potential(fmmkmc_ctx *c, int64_t m, const double *xyz, const int64_t 
         HIPCHK(hipSetDevice(c->device));
         launch_point_phi(c, make_geo(c), m, xyz, nullptr, exclude, c->bc == FMMKMC_PERIODIC ? 1 : 0, out,
                          "point_phi");
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_multipole(fmmkmc_ctx *c, int level, int64_t cell, double *out)
+{
+    if (!c || !out) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "multipole before initialise");
+    if (level < 1 || level > c->L) return fail(c, FMMKMC_EINVAL, "level must be in 1..L");
+    const int64_t side = (int64_t)1 << (level - 1), cells = side * side * side;
+    if (cell < 0 || cell >= cells) return fail(c, FMMKMC_EINVAL, "cell index out of range for the level");
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        // coefficient-major storage: coefficient k of the cell sits at [k * cells + cell]
+        HIPCHK(hipMemcpy2DAsync(out, sizeof(double), c->phi_lv[level] + cell, sizeof(double) * cells, sizeof(double),
+                                (size_t)c->nt, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         return FMMKMC_OK;
     })

@@ -618,8 +618,10 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
     if (class_wave) {
         if (cell < M) {
             const gptr<const Real> Ps = MIXED ? (gptr<const Real>)psi32 : (gptr<const Real>)psi;
-            // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part
-            Real S[2][2][2] = {};
+            // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part.
+            // Each degree is summed in the working precision and the degrees in FP64, so in
+            // mixed precision the rounding does not grow with the order.
+            double S[2][2][2] = {};
             Real hn = Real(1);
             const Real h = (Real)g.h;
 #pragma unroll
@@ -637,24 +639,24 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
 #pragma unroll
                 for (int B = 0; B < 2; ++B)
 #pragma unroll
-                    for (int C = 0; C < 2; ++C) S[(n + B) & 1][B][C] += hn * part[B][C];
+                    for (int C = 0; C < 2; ++C) S[(n + B) & 1][B][C] += (double)(hn * part[B][C]);
                 hn *= h;
             }
             const double l00 = MIXED ? psi[cell] : 0.0;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int fx = 1 - (u >> 2), fy = 1 - ((u >> 1) & 1), fz = 1 - (u & 1);
-                Real far_ = Real(0);
+                double far_ = 0.0;
 #pragma unroll
                 for (int A = 0; A < 2; ++A)
 #pragma unroll
                     for (int B = 0; B < 2; ++B) {
-                        const Real sz = (fz && A) ? Real(-1) : Real(1);
-                        const Real sre = sz * ((fx && B) ? Real(-1) : Real(1));
-                        const Real sim = sz * ((fx && !B) ? Real(-1) : Real(1)) * (fy ? Real(-1) : Real(1));
+                        const double sz = (fz && A) ? -1.0 : 1.0;
+                        const double sre = sz * ((fx && B) ? -1.0 : 1.0);
+                        const double sim = sz * ((fx && !B) ? -1.0 : 1.0) * (fy ? -1.0 : 1.0);
                         far_ += sre * S[A][B][0] + sim * S[A][B][1];
                     }
-                sFar[lc * 9 + u] = l00 + (double)far_;
+                sFar[lc * 9 + u] = l00 + far_;
             }
         }
     } else if (cell < M) {
@@ -695,7 +697,8 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
 #pragma unroll
             for (int v = 0; v < 8; ++v) o[v] = ok ? o[v] : Real(0);
         };
-        Real near_[8] = {};
+        // each neighbour cell's 8 terms per site in the working precision, the cells in FP64
+        double near_[8] = {};
         Real qn[8];
         {
             bool ok;
@@ -714,9 +717,12 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
             }
             const Real *tb = sT + nb * 64;
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < 8; ++u) {
+                Real part = Real(0);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) near_[u] += tb[u * 8 + v] * qv[v];
+                for (int v = 0; v < 8; ++v) part += tb[u * 8 + v] * qv[v];
+                near_[u] += (double)part;
+            }
         }
         // far field of V_inf at the 8 sites: the 4 (i, j) rows of Bz against the two Tax rows 2cz, 2cz+1
         double fs[8] = {};
@@ -740,7 +746,7 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
         }
         const double inv_h = 1.0 / g.h;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) sNear[lc * 9 + u] = (double)near_[u] * inv_h + fs[u];
+        for (int u = 0; u < 8; ++u) sNear[lc * 9 + u] = near_[u] * inv_h + fs[u];
     }
     __syncthreads();
     const int nsite = (int)((M - c0 < CELLS ? M - c0 : CELLS) * 8);

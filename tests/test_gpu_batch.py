@@ -310,3 +310,68 @@ def test_replica_without_a_valid_hop_does_not_move():
     assert np.all(moved[:, 0] == -1) and np.all(np.isinf(dt[:, 0])) and np.all(np.isfinite(dt[:, 1]))
     assert full.energy == U_full
     batch.close()
+
+
+# replicas of the 256-replica workload (p = 10): the largest (n = 51, L = 5), two
+# with 2 x 2 x 2 sites per fine cell (n = 32, L = 5 and n = 16, L = 4), the
+# smallest (n = 13, L = 4) and four ordinary ones
+CONFIG5_REPLICAS = [36, 4, 8, 203, 0, 1, 2, 3]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_config5_replicas_at_order_ten(precision, tol):
+    """The batched kernels at the workload's own order and sizes: eight replicas
+    drawn from the 256 (seeded as in the benchmark), six batched steps.  Moves
+    exactly and dU to rounding against the single-context path; every accepted
+    dU against O-fmm replaying the moves (FP64 accept path: 1e-10); then 256
+    sampled slots of each replica's next proposal pass against O-fmm (formed
+    lazily) at the precision's tolerance."""
+    from paper_1905_04065_amd import Batch
+    import torch
+    p, hops, K = 10, W.HOPS6, 6
+    Ns, ns, Ls = W.replica_sizes()
+    reps = []
+    for r in CONFIG5_REPLICAS:
+        sites, xyz, q = W.replica_system(r, Ns[r], ns[r])
+        reps.append(dict(n=int(ns[r]), N=int(Ns[r]), L=int(Ls[r]), p=p, sites=sites, xyz=xyz, q=q,
+                         precision=precision))
+    print(f"config-5 replicas {CONFIG5_REPLICAS}: n = {[rp['n'] for rp in reps]}, L = {[rp['L'] for rp in reps]}, "
+          f"p = {p}, {precision}", flush=True)
+    ctxs = [make_ctx(rp) for rp in reps]
+    singles = [make_ctx(rp) for rp in reps]
+    batch = Batch(ctxs, hops)
+    batch.tune(rounds=2)
+    R, steps = len(reps), 6
+    u = np.random.default_rng(W.BASE_SEED + 57).random((steps, R))
+    moved, site, dU = (x.cpu().numpy() for x in batch.step(u))
+    worst_single, worst_acc, worst_slot = 0.0, 0.0, 0.0
+    for r, rp in enumerate(reps):
+        cur = rp["sites"].copy()
+        ref_steps, _ = host_steps(singles[r], rp, u[:, r], hops, cur)
+        for s, (i, ns_, d) in enumerate(ref_steps):
+            assert moved[s, r] == i and site[s, r] == ns_, (r, s)
+            worst_single = max(worst_single, abs(dU[s, r] - d) / max(abs(d), 1e-3))
+        ref = O.FmmKmc(rp["xyz"], rp["q"], float(rp["n"]), rp["L"], p, "periodic", lazy=True)
+        for s in range(steps):
+            d_ref = ref.accept(int(moved[s, r]), W.site_xyz([site[s, r]], rp["n"])[0])
+            worst_acc = max(worst_acc, abs(dU[s, r] - d_ref) / max(abs(d_ref), 0.05))
+        dnow, mnow = ctxs[r].propose_lattice(hops)
+        torch.cuda.synchronize()
+        dnow = dnow.cpu().numpy().reshape(-1)
+        t, v = O.lattice_targets(cur, rp["n"], hops, True)
+        v = v.reshape(-1)
+        assert np.array_equal(mnow.cpu().numpy().reshape(-1).astype(bool), v)
+        pick = np.random.default_rng(W.BASE_SEED + 58 + r).choice(np.nonzero(v)[0], 256, replace=False)
+        d_ref = ref.propose(pick // K, W.site_xyz(t.reshape(-1)[pick], rp["n"]))
+        scale = float(np.mean(np.abs(dnow[v])))
+        err = float(np.max(np.abs(dnow[pick] - d_ref) / np.maximum(np.abs(d_ref), scale)))
+        worst_slot = max(worst_slot, err)
+        print(f"  replica {CONFIG5_REPLICAS[r]} (n={rp['n']}, N={rp['N']}, L={rp['L']}): 256 sampled slots "
+              f"{err:.3e}", flush=True)
+        ref.close()
+    print(f"  batched vs single-context dU {worst_single:.2e}; accepted dU vs O-fmm {worst_acc:.2e}; "
+          f"sampled slots vs O-fmm {worst_slot:.2e}", flush=True)
+    assert worst_single <= 1e-12
+    assert worst_acc <= 1e-10
+    assert worst_slot < tol
+    batch.close()

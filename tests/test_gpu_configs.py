@@ -217,3 +217,30 @@ def test_config4_sampled_slots_and_full_mask(precision, tol):
     assert err < tol
     ctx.close()
     ref.close()
+
+
+def test_config4_mixed_every_slot_against_the_fp64_pass():
+    """Config 4 in mixed precision over all 26M slots, against the FP64 pass of
+    the same system (itself held to O-fmm at 1e-10 by the sampled test above):
+    the maximum and mean guarded error of the whole pass, bound 1e-5."""
+    sites, xyz, q, c = W.config_system(4)
+    hops = W.hops(c["hops"])
+    print(f"config 4 mixed vs FP64, every slot: n={c['n']} N={len(q)} L={c['L']} p={c['p']}", flush=True)
+    ctx = make_ctx(xyz, q, c, "fp64")
+    ctx.initialise()
+    d64, m64 = gpu_lattice(ctx, hops)
+    ctx.close()
+    ctx = make_ctx(xyz, q, c, "mixed")
+    ctx.initialise()
+    d32, m32 = gpu_lattice(ctx, hops)
+    ctx.close()
+    assert np.array_equal(m64, m32)
+    v = m64
+    scale = float(np.mean(np.abs(d64[v])))
+    e = np.abs(d32[v] - d64[v]) / np.maximum(np.abs(d64[v]), scale)
+    c12 = np.abs(d32[v] - d64[v]) / np.maximum(np.abs(d64[v]), 1e-3 * scale)
+    j = int(np.argmax(e))
+    print(f"  {int(v.sum())} valid slots: guarded rel err max {e.max():.3e}, mean {e.mean():.3e}; with the "
+          f"1e-3 <|dU|> floor max {c12.max():.3e}; worst slot dU {d64[v][j]:.6f} (mixed {d32[v][j]:.6f}), "
+          f"mean |dU| {scale:.4f}", flush=True)
+    assert e.max() < 1e-5
