@@ -90,6 +90,20 @@ int fmmkmc_initialise(fmmkmc_ctx *c, double *U_out);
 int fmmkmc_propose(fmmkmc_ctx *c, int64_t n_groups, const int64_t *idx, const int64_t *offs,
                    const double *targets, double *dU);
 
+/* fmmkmc_propose() for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, checks, results and errors, but the per-target work memory is
+ * a fixed array inside the library (18 MiB per GPU, held until the process
+ * ends; located at the first context creation on that device), so the call
+ * allocates nothing.  At most 262144 targets per call (offs[n_groups] larger:
+ * EINVAL, nothing computed).  The CSR is checked on the device (EINVAL for
+ * offs[0] != 0, decreasing offs or a charge index out of range).  All calls on
+ * one GPU share the array: calls that overlap on one GPU (several host threads,
+ * or contexts on different streams) race and must be serialised by the caller.
+ * Returns after dU is complete. */
+int fmmkmc_propose_noalloc(fmmkmc_ctx *c, int64_t n_groups, const int64_t *idx, const int64_t *offs,
+                           const double *targets, double *dU);
+
 /* propose_with_dats(C, T, R, M, U), App. C: every charge i has type T[i] in
  * [0, n_types) and may hop to the first C[T[i]] of its K candidate targets
  * R[i][0..K-1] (N x 3K doubles); M[i][k] = 1 allows the hop, 0 forbids it.

@@ -55,6 +55,7 @@ def load_library():
         "fmmkmc_create": (i32, [C.POINTER(_Params), i64, vp, vp, C.POINTER(vp)]),
         "fmmkmc_initialise": (i32, [vp, C.POINTER(d)]),
         "fmmkmc_propose": (i32, [vp, i64, vp, vp, vp, vp]),
+        "fmmkmc_propose_noalloc": (i32, [vp, i64, vp, vp, vp, vp]),
         "fmmkmc_propose_dats": (i32, [vp, i32, vp, i32, vp, vp, vp, vp]),
         "fmmkmc_propose_lattice": (i32, [vp, i32, vp, vp, vp]),
         "fmmkmc_accept": (i32, [vp, i64, vp, C.POINTER(d)]),
@@ -190,6 +191,14 @@ class Context:
         if check:
             self._check(rc)
         return dU if check else (dU, rc)
+
+    def propose_noalloc(self, idx, offs, targets, dU, check=True):
+        """propose() through the allocation-free entry point: every array (device
+        tensors idx, offs, targets, dU) is supplied by the caller"""
+        rc = self._L.fmmkmc_propose_noalloc(self._h, idx.numel(), _ptr(idx), _ptr(offs), _ptr(targets), _ptr(dU))
+        if check:
+            self._check(rc)
+        return rc
 
     def propose_pairs(self, idx, targets, check=True):
         """one target per charge index (a CSR with groups of one)"""

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,7 +14,38 @@
 
 using namespace fmmkmc;
 
+// ---- work memory of the allocation-free generic proposal call ---------------
+// fmmkmc_propose_noalloc() keeps its per-slot work (wrapped target, potentials at
+// the target and at the charge, far-field change, status word, charge index:
+// 72 bytes per slot) in this file-scope device array instead of memory allocated
+// per call.  Every GPU the library runs on holds one copy until the process
+// ends; all calls on that GPU share it, so such calls must not overlap on one
+// GPU.  Host code never uses the array's name as an address: each device's copy
+// is looked up once (hipGetSymbolAddress, at the first context created on that
+// device) and the kernels get that address.
+constexpr int64_t kNoAllocSlots = (int64_t)1 << 18;
+constexpr int64_t kNoAllocBytes = 72 * kNoAllocSlots;  // 18 MiB
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// this device's copy of `scratch` (the device must be current); nullptr if the
+// device ordinal is beyond the table
+void *device_scratch(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
 
 // context-owned work buffer of at least `bytes` (grown on demand)
 void *work_buffer(fmmkmc_ctx *c, size_t bytes)
@@ -321,6 +353,7 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
         if (c->lat_n > kMaxLattice) return fail(c, FMMKMC_EINVAL, "lattice_n must be <= 1024");
     }
     HIPCHK(hipSetDevice(c->device));
+    (void)device_scratch(c->device);  // resolve this device's work array once, at set-up
     HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
@@ -559,6 +592,18 @@ __global__ void k_interleave(int64_t n, const double *x, const double *y, const 
     out[3 * i + 2] = z[i];
 }
 
+// CSR of a generic proposal call checked on the device: flag 8 when offs[0] != 0 or
+// offs decreases, flag 16 when a charge index is out of range
+__global__ void k_check_csr(int64_t G, const int64_t *__restrict__ idx, const int64_t *__restrict__ offs, int64_t N,
+                            int32_t *__restrict__ flags)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0 && offs[0] != 0) atomicOr(flags, 8);
+    if (g >= G) return;
+    if (offs[g + 1] < offs[g]) atomicOr(flags, 8);
+    if (idx[g] < 0 || idx[g] >= N) atomicOr(flags, 16);
+}
+
 int read_flags(fmmkmc_ctx *c, int32_t *out)
 {
     HIPCHK(hipMemcpyAsync(out, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -692,6 +737,45 @@ int fmmkmc_propose(fmmkmc_ctx *c, int64_t n_groups, const int64_t *idx, const in
         launch_expand_groups(c, n_groups, idx, offs, charge);
         launch_generic(c, g, S, targets, charge, dU, work);
         int32_t fl = 0;
+        read_flags(c, &fl);
+        if (fl & 1) return fail(c, FMMKMC_EDOMAIN, "a target lies outside the box (NaN written)");
+        if (fl & 2) return fail(c, FMMKMC_ECOINCIDENT, "a target coincides with a charge (NaN written)");
+        return FMMKMC_OK;
+    })
+}
+
+int fmmkmc_propose_noalloc(fmmkmc_ctx *c, int64_t n_groups, const int64_t *idx, const int64_t *offs,
+                           const double *targets, double *dU)
+{
+    if (!c) return FMMKMC_EINVAL;
+    if (!c->initialised) return fail(c, FMMKMC_ESTATE, "propose before initialise");
+    if (n_groups < 0 || (n_groups > 0 && (!idx || !offs || !targets || !dU)))
+        return fail(c, FMMKMC_EINVAL, "bad propose arguments");
+    if (n_groups == 0) return FMMKMC_OK;
+    if (c->device < 0 || c->device >= kMaxScratchDevices)
+        return fail(c, FMMKMC_EINVAL, "device ordinal beyond the work-array table");
+    API_GUARD(c, {
+        HIPCHK(hipSetDevice(c->device));
+        void *base = device_scratch(c->device);  // resolved at context creation: a table lookup
+        clear_flags(c);
+        launch(c, "check_csr", k_check_csr, dim3((unsigned)((n_groups + 255) / 256)), dim3(256), n_groups, idx, offs,
+               c->N, c->flags);
+        int32_t fl = 0;
+        int64_t S = 0;
+        HIPCHK(hipMemcpyAsync(&fl, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(&S, offs + n_groups, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (fl & 8) return fail(c, FMMKMC_EINVAL, "offs[0] must be 0 and offs non-decreasing");
+        if (fl & 16) return fail(c, FMMKMC_EINVAL, "charge index out of range");
+        if (S == 0) return FMMKMC_OK;
+        if (S > kNoAllocSlots) return fail(c, FMMKMC_EINVAL, "at most 262144 targets per allocation-free call");
+        // the same work layout as fmmkmc_propose: 8 doubles per slot, then the charge index per slot
+        double *work = (double *)base;
+        int64_t *charge = (int64_t *)(work + 8 * S);
+        clear_flags(c);
+        const Geo g = make_geo(c);
+        launch_expand_groups(c, n_groups, idx, offs, charge);
+        launch_generic(c, g, S, targets, charge, dU, work);
         read_flags(c, &fl);
         if (fl & 1) return fail(c, FMMKMC_EDOMAIN, "a target lies outside the box (NaN written)");
         if (fl & 2) return fail(c, FMMKMC_ECOINCIDENT, "a target coincides with a charge (NaN written)");
