@@ -44,6 +44,8 @@ def lib():
             "or_direct_dU": (None, [i, vp, vp, i, vp, vp, vp]),
             "or_ewald_energy": (d, [i, vp, vp, d, d, d, d]),
             "or_ewald_dU": (None, [i, vp, vp, d, d, d, d, i, vp, vp, vp]),
+            "or_periodic_self_change": (d, [d, vp]),
+            "of_set_self_image": (None, [vp, i]),
             "of_create": (vp, [i, d, i, i, i, vp, vp, i]),
             "of_destroy": (None, [vp]),
             "of_energy": (d, [vp]),
@@ -198,6 +200,12 @@ def ewald_dU(xyz, q, a, idx_, tgt, alpha=None, rc=None, kc=None):
     return out
 
 
+def periodic_self_change(a, d):
+    """psi_self - psi(d): a unit charge's interaction with its own periodic
+    copies after a displacement d, minus before (tin-foil Ewald)"""
+    return lib().or_periodic_self_change(float(a), _p(_f64(d)))
+
+
 # ---- O-fmm -------------------------------------------------------------------
 
 class FmmKmc:
@@ -206,9 +214,11 @@ class FmmKmc:
     bc: "free" or "periodic"; L: levels (root = 1); p: expansion order.
     lazy: form the fine-level local expansion of a cell only when a proposal or
     query needs it (same arithmetic, restricted to those cells).
+    self_image: "expansion" (the paper's self terms of Sec. 3.1) or "exact"
+    (q^2 (psi_self - psi(r' - r)), tin-foil Ewald).
     """
 
-    def __init__(self, xyz, q, a, L, p, bc="free", lazy=False):
+    def __init__(self, xyz, q, a, L, p, bc="free", lazy=False, self_image="expansion"):
         self.xyz = _f64(xyz, (-1, 3)).copy()
         self.q = _f64(q).copy()
         self.a, self.L, self.p = float(a), int(L), int(p)
@@ -219,6 +229,11 @@ class FmmKmc:
             raise ValueError("periodic boxes must be neutral")
         self._c = lib().of_create(1 if bc == "periodic" else 0, self.a, self.L, self.p, len(self.q),
                                   _p(self.xyz), _p(self.q), 1 if lazy else 0)
+        if self_image not in ("expansion", "exact"):
+            raise ValueError("self_image must be 'expansion' or 'exact'")
+        # periodic boxes: the moving charge's own copies by the paper's terms
+        # (V_box sum, constant, 1/2 dE.R'dK) or by the exact Ewald change
+        lib().of_set_self_image(self._c, 1 if self_image == "exact" else 0)
 
     def close(self):
         if getattr(self, "_c", None):

@@ -15,6 +15,16 @@
  *     psi_self = lim_{x->0} (psi(x) - 1/|x|)
  *     dU = q_i sum_{j != i} q_j (psi(r' - r_j) - psi(r - r_j))
  * (a charge's interaction with its own copies does not depend on where it is).
+ *
+ * or_periodic_self_change(a, d) = psi_self - psi(d): the change of a unit
+ * charge's interaction with its own periodic copies when it is displaced by d
+ * while the copies stay where they were.  A KMC proposal's FMM potential
+ * difference q (phi(r') - phi(r)) contains this term for the moving charge
+ * (its copies sit at the old place); adding q^2 (psi_self - psi(d)) removes it
+ * exactly, which is the exact counterpart of the V_box self terms plus the
+ * quadratic far-field term of Sec. 3.1.  Pinned by the caesium chloride
+ * Madelung constant (d = half the body diagonal) and by the small-d expansion
+ * psi(d) = 1/|d| + psi_self + (2 pi / 3V) |d|^2 + O(|d|^4 / a^5).
  * alpha, the real-space cutoff rc and the reciprocal cutoff kc are chosen by the
  * caller; the result is independent of alpha to rounding when both truncation
  * errors are below it.  Pinned in tests/test_oracle_exact.py by the Madelung
@@ -174,4 +184,27 @@ void or_ewald_dU(int n, const double *xyz, const double *q, double a, double alp
         }
         dU[s] = bad ? NAN : q[i] * acc;
     }
+}
+
+/* parameters chosen like the Python helper ewald_params: rc = a/2 and both
+ * truncations below 10^-16.5 */
+static ewald_par self_change_params(double a)
+{
+    double x = 1.0;
+    while (exp(-x * x) / x > pow(10.0, -16.5)) x += 0.01;
+    double rc = 0.5 * a, alpha = x / rc;
+    return ewald_setup(a, alpha, rc, 2.0 * alpha * x);
+}
+
+double or_periodic_self_change(double a, const double d[3])
+{
+    ewald_par e = self_change_params(a);
+    double zero[3] = {0.0, 0.0, 0.0};
+    double psi_self = ewald_real(&e, zero, 1) + ewald_recip(&e, zero) - 2.0 * e.alpha / sqrt(M_PI) -
+                      M_PI / (e.alpha * e.alpha * e.V);
+    /* reduce d to its nearest image: psi is periodic and the real-space sum
+     * assumes |d_k| <= a/2 */
+    double w[3];
+    for (int k = 0; k < 3; ++k) w[k] = d[k] - a * floor(d[k] / a + 0.5);
+    return psi_self - ewald_psi(&e, w);
 }

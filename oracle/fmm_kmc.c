@@ -36,6 +36,10 @@
  *     because E.(R dK) = dE.(R K) (the copies nu and -nu are both in V_inf)
  *     and avoids subtracting two large numbers.  The factor 1/2 in U_inf is
  *     the same double-counting factor as in U_sr (reading of Sec. 3.1).
+ *   With the exact self-image option (of_set_self_image) the V_box self terms,
+ *   the constant and 1/2 dE.(R dK) are replaced by q^2 (psi_self - psi(r' - r)),
+ *   psi the tin-foil Ewald pair potential (exact.c): the same quantity without
+ *   truncation, so results move at truncation level.
  * Accept (Sec. 3, "Accept move"; Sec. 3.1): dU is recomputed (footnote of
  *   Sec. 3.1); every fine cell beta gets -P2L(q at r + a nu) for every copy nu
  *   (free space: nu = 0 only) that is not in the 27 cells around beta, and
@@ -65,6 +69,7 @@ struct of_ctx {
     cplx *Gfar, *E, *K, *H;
     double U;
     int U_valid;
+    int self_exact;
 };
 
 static int side(int l) { return 1 << (l - 1); }
@@ -376,6 +381,8 @@ of_ctx *of_create(int bc, double a, int L, int p, int n, const double *xyz, cons
     return c;
 }
 
+void of_set_self_image(of_ctx *c, int exact) { c->self_exact = exact ? 1 : 0; }
+
 void of_destroy(of_ctx *c)
 {
     if (!c) return;
@@ -532,15 +539,21 @@ static double propose_one(of_ctx *c, int64_t i, const double t[3])
         return dU;
     }
     /* periodic: self terms of Eq. (proposed_energy_sr) */
-    double self = 0.0;
-    for (int a0 = -1; a0 <= 1; ++a0)
-        for (int a1 = -1; a1 <= 1; ++a1)
-            for (int a2 = -1; a2 <= 1; ++a2) {
-                double d0 = tw[0] - (r[0] + c->a * a0), d1 = tw[1] - (r[1] + c->a * a1),
-                       d2 = tw[2] - (r[2] + c->a * a2);
-                self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            }
-    dU += -q * q * self + q * q * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / c->a;
+    if (c->self_exact) {
+        /* the exact change of the moving charge's interaction with its own copies */
+        double d[3] = {tw[0] - r[0], tw[1] - r[1], tw[2] - r[2]};
+        dU += q * q * or_periodic_self_change(c->a, d);
+    } else {
+        double self = 0.0;
+        for (int a0 = -1; a0 <= 1; ++a0)
+            for (int a1 = -1; a1 <= 1; ++a1)
+                for (int a2 = -1; a2 <= 1; ++a2) {
+                    double d0 = tw[0] - (r[0] + c->a * a0), d1 = tw[1] - (r[1] + c->a * a1),
+                           d2 = tw[2] - (r[2] + c->a * a2);
+                    self += 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                }
+        dU += -q * q * self + q * q * (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / c->a;
+    }
     /* far field */
     int nt = c->nt;
     cplx *ypn = (cplx *)malloc(sizeof(cplx) * nt), *ymn = (cplx *)malloc(sizeof(cplx) * nt);
@@ -559,7 +572,9 @@ static double propose_one(of_ctx *c, int64_t i, const double t[3])
         s1 += dE[k] * c->H[k];
         s2 += dE[k] * dH[k];
     }
-    dU += creal(s1) + 0.5 * creal(s2);
+    /* with the exact self term, 1/2 dE.R'dK (the copies in V_inf of the moving
+     * charge seen from its new place) is already part of it */
+    dU += creal(s1) + (c->self_exact ? 0.0 : 0.5 * creal(s2));
     free(ypn);
     free(ymn);
     free(ypo);

@@ -74,6 +74,8 @@ double or_ewald_energy(int n, const double *xyz, const double *q, double a,
 void or_ewald_dU(int n, const double *xyz, const double *q, double a, double alpha,
                  double rc, double kc, int np, const int64_t *idx, const double *tgt,
                  double *dU);
+/* psi_self - psi(d) of a unit charge and its own copies (tin-foil Ewald) */
+double or_periodic_self_change(double a, const double d[3]);
 
 /* ---- O-fmm (fmm_kmc.c) ------------------------------------------------ */
 typedef struct of_ctx of_ctx;
@@ -84,6 +86,10 @@ typedef struct of_ctx of_ctx;
 of_ctx *of_create(int bc, double a, int L, int p, int n, const double *xyz,
                   const double *q, int lazy);
 void of_destroy(of_ctx *c);
+/* self-image terms of a periodic proposal: 0 (default) the paper's V_box sum,
+ * constant and 1/2 dE.R'dK (Sec. 3.1); 1 the exact change q^2 (psi_self -
+ * psi(r' - r)) of the moving charge's interaction with its own copies */
+void of_set_self_image(of_ctx *c, int exact);
 double of_energy(of_ctx *c);
 void of_propose(of_ctx *c, int np, const int64_t *idx, const double *tgt, double *dU);
 double of_accept(of_ctx *c, int64_t i, const double newpos[3]);

@@ -103,3 +103,30 @@ def test_cubic_shell_sum_is_tinfoil_plus_surface_term():
     surface = 2 * math.pi / (3 * a ** 3) * float(d @ d)
     assert limit == pytest.approx(Ue + surface, abs=1e-6)
     assert abs(limit - Ue) > 0.1  # the surface term is not negligible here
+
+
+def test_periodic_self_change_caesium_chloride():
+    """psi_self - psi(b) with b half the body diagonal is the energy per ion pair
+    of caesium chloride (a + ion's interaction with its own lattice minus the
+    - lattice at the body centres): -M_CsCl / r_nn, r_nn = a sqrt(3) / 2"""
+    for a in (1.0, 7.0, 64.0):
+        b = np.array([a / 2, a / 2, a / 2])
+        want = -GOLD["CsCl"] / (a * math.sqrt(3.0) / 2.0)
+        assert O.periodic_self_change(a, b) == pytest.approx(want, rel=1e-14)
+        # periodic in the displacement
+        assert O.periodic_self_change(a, b - np.array([a, 0, 2 * a])) == pytest.approx(want, rel=1e-14)
+
+
+def test_periodic_self_change_small_displacement():
+    """psi(d) = 1/|d| + psi_self + (2 pi / 3V)|d|^2 + O(|d|^4 / a^5) (the background
+    makes the Laplacian of psi - 1/r equal 4 pi / V, isotropic by cubic
+    symmetry): the remainder falls as |d|^4 along a fixed direction"""
+    a = 10.0
+    rem = []
+    for dd in (0.25, 0.5, 1.0):
+        d = dd * np.array([1.0, 2.0, 2.0]) / 3.0
+        v = O.periodic_self_change(a, d)
+        rem.append(v - (-1.0 / dd - 2.0 * math.pi / (3.0 * a ** 3) * dd * dd))
+    assert abs(rem[0]) < 4.0 * 0.25 ** 4 / a ** 5
+    assert rem[1] / rem[0] == pytest.approx(16.0, rel=0.02)
+    assert rem[2] / rem[1] == pytest.approx(16.0, rel=0.02)

@@ -321,3 +321,38 @@ def test_accept_changes_each_local_expansion_by_its_far_copies(bc, n, N, L, p):
     assert worst_c <= 1e-13 * scale, (worst_c, scale)
     # interior point at |x - c| = 0.45 w, copies beyond 1.5 w: ratio 0.3, bound ~ 0.3^(p+1) / w
     assert worst_x <= 2 * 0.3 ** (p + 1) / w * 10, (worst_x, scale)
+
+
+def test_exact_self_image_matches_ewald(periodic_box):
+    """With the exact self-image term (q^2 (psi_self - psi(r' - r)) in place of the
+    V_box self sum, the constant and 1/2 dE.R'dK) O-fmm still converges to tin-foil
+    Ewald: within the same band as the paper's terms at p = 18, and the two forms
+    differ only at truncation level (they approximate the same quantity)."""
+    n, xyz, q, idx, tgt, valid, ref, Ue = periodic_box
+    lit = O.FmmKmc(xyz, q, n, 3, 18, "periodic").propose(idx[valid], tgt[valid])
+    ex = O.FmmKmc(xyz, q, n, 3, 18, "periodic", self_image="exact").propose(idx[valid], tgt[valid])
+    scale = np.mean(np.abs(ref[valid]))
+    assert np.max(np.abs(ex - ref[valid])) < 2e-6 * scale
+    assert np.max(np.abs(ex - lit)) < 2e-6 * scale
+    errs = []
+    for p in (6, 10, 14):
+        d = O.FmmKmc(xyz, q, n, 3, p, "periodic", self_image="exact").propose(idx[valid], tgt[valid])
+        errs.append(np.max(np.abs(d - ref[valid])))
+    assert errs[0] > 5 * errs[1] > 25 * errs[2]
+
+
+def test_exact_self_image_accepts_and_round_trips():
+    """the exact self-image term in the accept step: the round trip restores the
+    expansions and the accepted dU's match Ewald energy differences"""
+    n, N = 8, 40
+    sites, xyz, q = lattice(n, N, 24)
+    idx, tgt, valid = proposals(sites, n, True)
+    f = O.FmmKmc(xyz, q, n, 3, 18, "periodic", self_image="exact")
+    s = np.nonzero(valid)[0][5]
+    i, t = idx[s], tgt[s]
+    d1 = f.accept(i, t)
+    xyz1 = xyz.copy()
+    xyz1[i] = t
+    assert d1 == pytest.approx(O.ewald_energy(xyz1, q, n) - O.ewald_energy(xyz, q, n), abs=2e-6)
+    d2 = f.accept(i, xyz[i])
+    assert d2 == pytest.approx(-d1, abs=2e-6)
