@@ -51,7 +51,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_work(kernel, n, N, K, p, precision):
+def kernel_work(kernel, n, N, K, p, precision, exact_self=False):
     """(bound, algorithmic amount per launch, unit) of the three kernels that
     carry a step: what the method must move (bytes) or compute (flop) once."""
     nt = (p + 1) ** 2
@@ -64,8 +64,9 @@ def kernel_work(kernel, n, N, K, p, precision):
         psi = cells * nt * (4 if mixed else 8) + (cells * 8 if mixed else 0)
         return "hbm", psi + sites * ((4 if mixed else 8) + 4 + 8) + N * 8 + n * n * (p + 1) * 8, "B"
     if kernel == "slot_lattice":
-        # per slot: dU out, mask out, F in; per charge: site, index, q, phi_occ; potential of every site once
-        return "hbm", N * K * (8 + 1 + 8) + N * (4 + 4 + 8 + 8) + sites * 8, "B"
+        # per slot: dU out, mask out, F in (not with the exact self-image option: a per-hop
+        # table); per charge: site, index, q, phi_occ; potential of every site once
+        return "hbm", N * K * (8 + 1 + (0 if exact_self else 8)) + N * (4 + 4 + 8 + 8) + sites * 8, "B"
     if kernel == "sweep":
         # 27 copies x 2 endpoints of P2L into every fine cell
         return "alu", cells * 54 * P2L_FLOP, "flop"
@@ -136,17 +137,17 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed):
+def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed, self_image="expansion", host_loop=True):
     import torch
 
     from paper_1905_04065_amd import Context
 
     sites, xyz, q = W.lattice_charges(n, N, seed)
     K = len(hops)
-    log(f"[{precision}] create n={n} N={N} L={L} p={p} K={K}")
+    log(f"[{precision}, self image {self_image}] create n={n} N={N} L={L} p={p} K={K}")
     t0 = time.perf_counter()
     ctx = Context(xyz, q, a=float(n), levels=L, order=p, bc="periodic", precision=precision, lattice_n=n,
-                  device=0)
+                  device=0, self_image=self_image)
     U0 = ctx.initialise()
     dU, mask = ctx.propose_lattice(hops)  # builds the per-charge hop table once
     torch.cuda.synchronize()
@@ -177,37 +178,39 @@ def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed):
         cur[i] = t
         return d
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     names = ["site_phi_s2", "site_phi", "slot_lattice", "sweep", "path", "far_refresh", "cheb_a", "cheb_b", "f_rows",
-             "f_row1", "book", "move_dU"]  # f_row1 runs on the side stream, beside the sweep
-    ktimes = {nm: ctx.kernel_time(nm) for nm in names}
-    ctx.set_profiling(False)
-    # propose-only timing (no commit) for the proposal rate
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.propose_lattice(hops, dU=dU, mask=mask)
-    torch.cuda.synchronize()
-    propose_wall = time.perf_counter() - t0
-    # commit-only timing
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        i, t = choose()
-        ctx.accept(i, W.site_xyz([t], n)[0])
-        occ[cur[i]] = False
-        occ[t] = True
-        cur[i] = t
-    torch.cuda.synchronize()
-    commit_wall = time.perf_counter() - t0
+             "f_row1", "self_hops", "book", "move_dU"]  # f_row1 runs on the side stream, beside the sweep
+    ktimes, wall, propose_wall, commit_wall = {}, float("nan"), float("nan"), float("nan")
+    if host_loop:
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ktimes = {nm: ctx.kernel_time(nm) for nm in names}
+        ctx.set_profiling(False)
+        # propose-only timing (no commit) for the proposal rate
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.propose_lattice(hops, dU=dU, mask=mask)
+        torch.cuda.synchronize()
+        propose_wall = time.perf_counter() - t0
+        # commit-only timing
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            i, t = choose()
+            ctx.accept(i, W.site_xyz([t], n)[0])
+            occ[cur[i]] = False
+            occ[t] = True
+            cur[i] = t
+        torch.cuda.synchronize()
+        commit_wall = time.perf_counter() - t0
     valid = int(mask.sum().item())
     # the same step driven by the device: selection on the GPU (a seeded uniform
     # choice among the valid slots, as above) and the whole step replayed from a
@@ -367,12 +370,12 @@ def cpu_baseline(n, N, L, p, hops, seed, budget_s=20.0):
                        f"formation of the touched cells' local expansions excluded")
 
 
-def roofline_entry(kernel, kt, n, N, K, p, precision, copy_gbs, traffic):
+def roofline_entry(kernel, kt, n, N, K, p, precision, copy_gbs, traffic, exact_self=False):
     ms, launches = kt.get(kernel, (0.0, 0))
     if launches == 0:
         return None
     avg_s = ms / launches / 1e3
-    bound, amount, unit = kernel_work(kernel, n, N, K, p, precision)
+    bound, amount, unit = kernel_work(kernel, n, N, K, p, precision, exact_self)
     e = {"kernel": kernel, "avg_us": avg_s * 1e6, "launches": launches}
     if bound == "hbm":
         ach = amount / avg_s / 1e9
@@ -502,6 +505,8 @@ def main():
     ap.add_argument("--skip-batch", action="store_true",
                     help="leave out the batched-replica and grounded-slab workloads")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-replica workload (JSON to stdout)")
+    ap.add_argument("--skip-exact-self", action="store_true",
+                    help="leave out the runs with the exact self-image option")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is "
@@ -519,17 +524,19 @@ def main():
     K = len(hops)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     res = {pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed) for pr in precs}
+    res_exact = {} if args.skip_exact_self else {
+        pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, self_image="exact") for pr in precs}
     copy_gbs = copy_bandwidth()
     if args.copy_calibration:
         copy_bandwidth(1 << 30, reps=3)
     head_prec = "fp64" if "fp64" in res else precs[0]
     slots = N * K
 
-    def summary(pr):
-        r = res[pr]
+    def summary(pr, exact=False):
+        r = (res_exact if exact else res)[pr]
         kt = r["kernels"]
-        traffic = profiled_traffic(tag, pr)
-        roof = {k: roofline_entry(k, kt, n, N, K, p, pr, copy_gbs, traffic)
+        traffic = {} if exact else profiled_traffic(tag, pr)
+        roof = {k: roofline_entry(k, kt, n, N, K, p, pr, copy_gbs, traffic, exact)
                 for k in ("site_phi_s2", "slot_lattice", "sweep")}
         # the kernel that takes the largest share of a step
         dom = max(roof, key=lambda k: roof[k]["avg_us"] if roof[k] else -1)
@@ -584,6 +591,16 @@ def main():
                         "commit_us": m["commit_us"],
                         "dtype": "f32 fine-level evaluation, f64 difference/far field/commit",
                         "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"]}
+    if res_exact:
+        out["exact_self_image"] = {}
+        for pr in precs:
+            m = summary(pr, exact=True)
+            out["exact_self_image"][pr] = {
+                "value": m["value"], "ms_per_step": m["ms_per_step"], "host_driven_ms_per_step": m["host_driven_ms_per_step"],
+                "propose_us": m["propose_us"], "commit_us": m["commit_us"], "setup_s": m["setup_s"],
+                "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"],
+                "note": "self_image=1: the moving charge's own copies by the exact Ewald change per hop instead of the "
+                        "V_box sum + constant + 1/2 dE.R'dK (no per-charge hop table)"}
     if not args.skip_batch:
         out["batched"] = batched_summary(args)
         out["slab"] = run_slab(max(args.steps, 5), args.warmup, W.BASE_SEED + 6)

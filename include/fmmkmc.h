@@ -65,6 +65,14 @@ typedef struct fmmkmc_params {
                           or 4 x the largest initial occupancy (otherwise) */
     int device;        /* HIP device ordinal */
     void *stream;      /* hipStream_t for all work, NULL for the null stream */
+    int self_image;    /* periodic boxes: how a proposal removes the moving charge's
+                          interaction with its own periodic copies.  0: the terms of
+                          Sec. 3.1 (V_box self sum, the constant (6 + 8/sqrt3 +
+                          12/sqrt2)/a and 1/2 dE.R'dK); 1: their exact value
+                          q^2 (G_self - G(r' - r)), G the conducting-boundary periodic
+                          pair potential (Ewald sum): results move at truncation level,
+                          and lattice proposals need no per-charge hop table.
+                          Ignored in free space. */
 } fmmkmc_params;
 
 /* Create a context for n charges (KMCFMM(positions, charges, r, l), Sec. 5.2).

@@ -33,7 +33,10 @@ class FmmKmcError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("bc", C.c_int), ("levels", C.c_int), ("order", C.c_int),
                 ("precision", C.c_int), ("lattice_n", C.c_int), ("cell_capacity", C.c_int),
-                ("device", C.c_int), ("stream", C.c_void_p)]
+                ("device", C.c_int), ("stream", C.c_void_p), ("self_image", C.c_int)]
+
+
+_SELF_IMAGE = {"expansion": 0, "exact": 1}
 
 
 def library_path():
@@ -115,11 +118,13 @@ class Context:
 
     bc: "free" or "periodic"; levels: L (root = 1); order: p;
     precision: "fp64" or "mixed"; lattice_n: n > 0 when every charge sits on a
-    site of the n^3 lattice of spacing a/n (enables propose_lattice).
+    site of the n^3 lattice of spacing a/n (enables propose_lattice);
+    self_image (periodic): "expansion" (the self terms of Sec. 3.1) or "exact"
+    (their exact Ewald value, see fmmkmc_params in include/fmmkmc.h).
     """
 
     def __init__(self, xyz, q, a, levels, order, bc="free", precision="fp64", lattice_n=0, cell_capacity=0,
-                 device=0, stream=None):
+                 device=0, stream=None, self_image="expansion"):
         torch = _torch()
         self._L = load_library()
         self.device = torch.device("cuda", device)
@@ -134,7 +139,7 @@ class Context:
         self.K = None
         prm = _Params(float(a), 1 if bc == "periodic" else 0, int(levels), int(order),
                       1 if precision == "mixed" else 0, int(lattice_n), int(cell_capacity), int(device),
-                      C.c_void_p(stream.cuda_stream))
+                      C.c_void_p(stream.cuda_stream), _SELF_IMAGE[self_image])
         h = C.c_void_p()
         rc = self._L.fmmkmc_create(C.byref(prm), self.N, xyz.ctypes.data_as(C.c_void_p),
                                    q.ctypes.data_as(C.c_void_p), C.byref(h))
@@ -143,6 +148,7 @@ class Context:
         self._h = h
         self.a, self.bc, self.levels, self.order = float(a), bc, int(levels), int(order)
         self.precision, self.lattice_n = precision, int(lattice_n)
+        self.self_image = self_image
 
     # -- helpers --
     def _check(self, rc):
@@ -376,7 +382,7 @@ class Slab:
     boundaries, by the first mirror image and the periodic algorithm)."""
 
     def __init__(self, xyz, q, a, levels, order, lattice_n, ez=0.0, precision="fp64", cell_capacity=0, device=0,
-                 stream=None):
+                 stream=None, self_image="expansion"):
         torch = _torch()
         self._L = load_library()
         self.device = torch.device("cuda", device)
@@ -389,7 +395,7 @@ class Slab:
             raise ValueError("xyz and q lengths differ")
         self.N = len(q)
         prm = _Params(float(a), 1, int(levels), int(order), 1 if precision == "mixed" else 0, int(lattice_n),
-                      int(cell_capacity), int(device), C.c_void_p(stream.cuda_stream))
+                      int(cell_capacity), int(device), C.c_void_p(stream.cuda_stream), _SELF_IMAGE[self_image])
         h = C.c_void_p()
         rc = self._L.fmmkmc_slab_create(C.byref(prm), self.N, xyz.ctypes.data_as(C.c_void_p),
                                         q.ctypes.data_as(C.c_void_p), float(ez), C.byref(h))

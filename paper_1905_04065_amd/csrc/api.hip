@@ -169,6 +169,7 @@ void release(fmmkmc_ctx *c)
     dfree(c->far.sigma);
     c->far.K = nullptr;  // alias of phi_lv[1]
     dfree(c->F);
+    dfree(c->Fhop);
     dfree(c->d_offsets);
     dfree(c->scr);
     dfree(c->flags);
@@ -342,6 +343,8 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
     c->p = prm->order;
     c->nt = nterms(c->p);
     c->prec = prm->precision;
+    if (prm->self_image != 0 && prm->self_image != 1) return fail(c, FMMKMC_EINVAL, "self_image must be 0 or 1");
+    c->self_exact = (prm->bc == FMMKMC_PERIODIC && prm->self_image == 1) ? 1 : 0;
     c->lat_n = prm->lattice_n;
     c->device = prm->device;
     c->stream = (hipStream_t)prm->stream;
@@ -628,6 +631,7 @@ Geo make_geo(const fmmkmc_ctx *c)
     g.periodic = c->bc == FMMKMC_PERIODIC ? 1 : 0;
     g.cap = c->cap;
     g.tab_ok = c->near_tab_ok;
+    g.self_exact = c->self_exact;
     return g;
 }
 
@@ -834,7 +838,11 @@ int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double 
             c->d_offsets = dalloc<int32_t>(3 * K);
             upload(c->d_offsets, off.data(), 3 * K, c->stream);
             c->d_offsets_K = K;
-            if (c->bc == FMMKMC_PERIODIC) {
+            if (c->bc == FMMKMC_PERIODIC && c->self_exact) {
+                dfree(c->Fhop);
+                c->Fhop = dalloc<double>(K);
+                launch_self_hops(c, K);
+            } else if (c->bc == FMMKMC_PERIODIC) {
                 if (!c->far.sigma) {
                     const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
                     c->far.sigma = dalloc<double>(ns);
@@ -905,7 +913,7 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
         // proposal table (it depends only on the new site), the multipole path,
         // the bookkeeping and the far-field refresh.  None of it touches the
         // fine-level expansions or what the sweep reads.
-        const bool need_row = c->bc == FMMKMC_PERIODIC && c->F && !c->F_offsets.empty();
+        const bool need_row = c->bc == FMMKMC_PERIODIC && !c->self_exact && c->F && !c->F_offsets.empty();
         const int Krow = (int)c->F_offsets.size() / 3;
         bool row_launched = false;
         HIPCHK(hipEventRecord(c->ev_fork, c->stream));

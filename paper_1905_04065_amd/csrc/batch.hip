@@ -625,7 +625,8 @@ RepDev make_rep(const fmmkmc_ctx *c, int K, double *dU, uint8_t *mask)
     d.ijk_r = c->ijk_r;
     d.q_r = c->q_r;
     d.phi_r = c->phi_r;
-    d.F = c->bc == FMMKMC_PERIODIC ? c->F : nullptr;
+    d.F = (c->bc == FMMKMC_PERIODIC && !c->self_exact) ? c->F : nullptr;
+    d.Fhop = (c->bc == FMMKMC_PERIODIC && c->self_exact) ? c->Fhop : nullptr;
     d.offsets = c->d_offsets;
     d.dU = dU;
     d.mask = mask;

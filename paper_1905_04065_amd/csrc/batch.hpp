@@ -34,6 +34,7 @@ struct RepDev {
     // by rank
     int32_t *order, *ijk_r;
     double *q_r, *phi_r, *F;
+    double *Fhop;  // exact self-image option: per-hop table instead of F
     // hops and the proposal output of this replica ([charge][hop])
     int32_t *offsets;
     double *dU;

@@ -28,6 +28,8 @@ struct Geo {
     int periodic;  // 1 periodic, 0 free space
     int cap;       // slots per fine cell
     int tab_ok;    // lattice: every squared site offset of a near field is below kInvTab
+    int self_exact;  // periodic: proposals take the exact self-image change (Ewald), not the
+                     // V_box self sum + constant + 1/2 dE.R'dK
 };
 
 // entries of the 1/sqrt(k) table of the lattice near field (integer squared offsets)
@@ -111,8 +113,11 @@ struct fmmkmc_ctx {
     double *scale = nullptr;     // [level][2][nt]: w^-deg(n) and w^-(deg(k)+1)
     fmmkmc::FarField far;
 
-    // lattice proposal table (periodic): F[i][k] per charge and hop
+    // lattice proposal table (periodic): F[i][k] per charge and hop; with the
+    // exact self-image option a per-hop table Fhop[k] instead
+    int self_exact = 0;
     double *F = nullptr;
+    double *Fhop = nullptr;
     std::vector<int32_t> F_offsets;   // 3K ints the table was built for
     int32_t *d_offsets = nullptr;     // device copy of the current hop offsets
     int d_offsets_K = 0;

@@ -100,6 +100,8 @@ void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz,
                       bool fp64 = false);
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g);
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask);
+// exact self-image option: Fhop[k] = G_self - G(h offsets[k]) for the K hops
+void launch_self_hops(fmmkmc_ctx *c, int K);
 // blocks of the general-geometry site kernel for an n^3 lattice
 int64_t general_site_blocks(int n);
 void launch_sigma(fmmkmc_ctx *c, const Geo &g);

@@ -17,6 +17,7 @@
 // charge-configuration-independent terms (self terms and the quadratic far-field
 // term) are tabulated per charge and hop in F.
 #include "batch.hpp"
+#include "ewald.hpp"
 #include "kernels.hpp"
 
 namespace fmmkmc {
@@ -815,19 +816,31 @@ __device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_
                                           const int32_t *__restrict__ offs_, const int32_t *__restrict__ order_,
                                           const int32_t *__restrict__ ijk_r_, const double *__restrict__ q_r_,
                                           const double *__restrict__ phi_r_, const double *__restrict__ phisite_,
-                                          const double *__restrict__ F_, int s2, double *__restrict__ dU_,
-                                          uint8_t *__restrict__ mask_)
+                                          const double *__restrict__ F_, const double *__restrict__ Fhop_,
+                                          int s2, double *__restrict__ dU_, uint8_t *__restrict__ mask_)
 {
     const auto offs = as_global(offs_), order = as_global(order_), ijk_r = as_global(ijk_r_);
     const auto q_r = as_global(q_r_), phi_r = as_global(phi_r_), phisite = as_global(phisite_), F = as_global(F_);
     const auto dU = as_global(dU_);
     const auto mask = as_global(mask_);
     __shared__ int32_t soff[3 * kMaxHops];
+    __shared__ double sfhop[kMaxHops];
     __shared__ int32_t s_ijk[TC], s_ord[TC];
     __shared__ double s_q[TC], s_phi[TC];
     const int64_t r0 = blk * TC;
     const int nloc = (int)((N - r0) < TC ? (N - r0) : TC);
     for (uint32_t e = threadIdx.x; e < 3 * K; e += blockDim.x) soff[e] = offs[e];
+    const bool per_charge = g.periodic && F_ != nullptr;  // else a per-hop correction
+    for (uint32_t e = threadIdx.x; e < K; e += blockDim.x) {
+        double v = 0.0;
+        if (!g.periodic) {
+            const double ox = offs[3 * e], oy = offs[3 * e + 1], oz = offs[3 * e + 2];
+            v = -1.0 / (g.h * sqrt(ox * ox + oy * oy + oz * oz));
+        } else if (!per_charge) {
+            v = Fhop_[e];
+        }
+        sfhop[e] = v;
+    }
     if ((int)threadIdx.x < nloc) {
         const int64_t r = r0 + threadIdx.x;
         s_ijk[threadIdx.x] = ijk_r[r];
@@ -874,7 +887,7 @@ __device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_
                                       : (((int64_t)ti * n + tj) * n + tk);
                 v[b] = phisite[pt];
             }
-            if (g.periodic) f[b] = F[r0 * K + e];
+            if (per_charge) f[b] = F[r0 * K + e];
         }
 #pragma unroll
         for (int b = 0; b < SLOTB; ++b) {
@@ -882,11 +895,7 @@ __device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_
             if (e >= total) continue;
             const uint32_t c = lc[b], k = kk[b];
             const double qi = s_q[c];
-            double corr = f[b];
-            if (!g.periodic) {
-                const double ox = soff[3 * k], oy = soff[3 * k + 1], oz = soff[3 * k + 2];
-                corr = -1.0 / (g.h * sqrt(ox * ox + oy * oy + oz * oz));
-            }
+            const double corr = per_charge ? f[b] : sfhop[k];
             const bool valid = !__builtin_isnan(v[b]);
             const double out = valid ? qi * (v[b] - s_phi[c]) + qi * qi * corr : nanv;
             const int64_t o = (int64_t)s_ord[c] * K + k;
@@ -902,18 +911,32 @@ __global__ __launch_bounds__(256) void k_slot_lattice(Geo g, int64_t N, uint32_t
                                                       const int32_t *__restrict__ ijk_r, const double *__restrict__ q_r,
                                                       const double *__restrict__ phi_r,
                                                       const double *__restrict__ phisite,
-                                                      const double *__restrict__ F, int s2,
-                                                      double *__restrict__ dU, uint8_t *__restrict__ mask)
+                                                      const double *__restrict__ F, const double *__restrict__ Fhop,
+                                                      int s2, double *__restrict__ dU, uint8_t *__restrict__ mask)
 {
-    slot_body<TCH>(blockIdx.x, g, N, K, kmul, offs, order, ijk_r, q_r, phi_r, phisite, F, s2, dU, mask);
+    slot_body<TCH>(blockIdx.x, g, N, K, kmul, offs, order, ijk_r, q_r, phi_r, phisite, F, Fhop, s2, dU, mask);
 }
 
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask)
 {
     const uint32_t kmul = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)K);
     launch(c, "slot_lattice", k_slot_lattice, dim3((unsigned)((c->N + TCH - 1) / TCH)), dim3(256), g, c->N,
-           (uint32_t)K, kmul, c->d_offsets, c->order, c->ijk_r, c->q_r, c->phi_r, c->phisite, c->F, c->s2 ? 1 : 0,
-           dU, mask);
+           (uint32_t)K, kmul, c->d_offsets, c->order, c->ijk_r, c->q_r, c->phi_r, c->phisite,
+           c->self_exact ? nullptr : c->F, c->Fhop, c->s2 ? 1 : 0, dU, mask);
+}
+
+// exact self-image option: the per-hop change G_self - G(h offsets[k]) (the
+// Ewald sum of ewald.hpp), one lane per hop
+__global__ void k_self_hops(int K, const int32_t *__restrict__ offs, double h, double a, double *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    out[k] = periodic_self_change(a, h * offs[3 * k], h * offs[3 * k + 1], h * offs[3 * k + 2]);
+}
+
+void launch_self_hops(fmmkmc_ctx *c, int K)
+{
+    launch(c, "self_hops", k_self_hops, dim3(1), dim3(64), K, c->d_offsets, c->h, c->a, c->Fhop);
 }
 
 // ---- far-field helpers (LDS-tiled matrix-vector products with R) ----------
@@ -1169,8 +1192,11 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
         const int64_t tcell = cell_id(g.nc, tcx, tcy, tcz), rcell = cell_id(g.nc, rcx, rcy, rcz);
         for (int k = threadIdx.x; k < nt; k += blockDim.x)
             part += qi * (psi[(int64_t)k * M + tcell] * Wa[k] - psi[(int64_t)k * M + rcell] * Wb[k]);
-        // self terms: one copy nu of the old position per lane
-        if (g.periodic) {
+        // self terms: one copy nu of the old position per lane, or the exact
+        // self-image change with its Ewald terms split over the block
+        if (g.periodic && g.self_exact) {
+            part += qi * qi * periodic_self_change_share(g.a, tx - rx, ty - ry, tz - rz, threadIdx.x, blockDim.x);
+        } else if (g.periodic) {
             if (threadIdx.x < 27) {
                 const int nu = threadIdx.x;
                 const double d0 = tx - rx - g.a * (nu / 9 - 1), d1 = ty - ry - g.a * ((nu / 3) % 3 - 1),
@@ -1237,8 +1263,9 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nt; k += blockDim.x) part += qi * Wt[k] * H[k];
-        // eight independent loads of R in flight per lane
-        const int nn = nt * nt;
+        // eight independent loads of R in flight per lane (the quadratic term is
+        // part of the exact self-image change when that option is on)
+        const int nn = g.self_exact ? 0 : nt * nt;
         double acc8[8] = {};
         int e = threadIdx.x;
         for (; e + 7 * 256 < nn; e += 8 * 256) {
@@ -1363,7 +1390,9 @@ __global__ __launch_bounds__(256) void k_generic_far(Geo g, int p, int64_t S, co
         const int bb = e / nt, k = e % nt;
         if (s0 + bb >= S) continue;
         double dh = 0.0;
-        for (int m = 0; m < nt; ++m) dh += R[(int64_t)m * nt + k] * Kt[bb * nt + m];
+        // with the exact self-image option the quadratic term is not taken here
+        if (!g.self_exact)
+            for (int m = 0; m < nt; ++m) dh += R[(int64_t)m * nt + k] * Kt[bb * nt + m];
         const double qi = q[charge[s0 + bb]];
         Kr[e] = Wt[e] * qi * (H[k] + 0.5 * dh);
     }
@@ -1395,7 +1424,9 @@ __global__ __launch_bounds__(256) void k_generic_combine(Geo g, int64_t S, const
     const double qi = q[i];
     const double tx = tw[3 * s], ty = tw[3 * s + 1], tz = tw[3 * s + 2];
     double d = qi * (phit[s] - phir[s]);
-    if (g.periodic) {
+    if (g.periodic && g.self_exact) {
+        d += qi * qi * periodic_self_change(g.a, tx - x[i], ty - y[i], tz - z[i]) + far[s];
+    } else if (g.periodic) {
         double self = 0.0;
         for (int a0 = -1; a0 <= 1; ++a0)
             for (int a1 = -1; a1 <= 1; ++a1)
@@ -1511,7 +1542,7 @@ __global__ __launch_bounds__(256) void k_b_slot(const RepDev *__restrict__ reps,
     const int r = find_rep(base, R, blockIdx.x);
     const RepDev &d = reps[r];
     slot_body<TC>(blockIdx.x - base[r], d.g, d.N, (uint32_t)d.K, d.kmul, d.offsets, d.order, d.ijk_r, d.q_r,
-                  d.phi_r, d.phisite, d.F, d.s2, d.dU, d.mask);
+                  d.phi_r, d.phisite, d.F, d.Fhop, d.s2, d.dU, d.mask);
 }
 
 // nparts blocks per replica: parts part0 .. part0 + nparts - 1

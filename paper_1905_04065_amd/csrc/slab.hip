@@ -27,44 +27,12 @@
 #include <vector>
 
 #include "../../include/fmmkmc.h"
+#include "ewald.hpp"
 #include "hostutil.hpp"
 
 using namespace fmmkmc;
 
 namespace {
-
-// G(x) of the conducting-boundary periodic lattice (period a) without its
-// constant: sum over images of erfc(alpha r) / r plus the reciprocal sum
-// (4 pi / V) sum_{k != 0} exp(-k^2 / (4 alpha^2)) / k^2 cos(k . x).  The
-// offset is first reduced to the nearest image; with alpha = 2.44 / a the
-// real-space images beyond |nu_i| <= 2 and the wave vectors beyond |n_i| <= 7
-// are below 1e-17 of the leading terms.
-__device__ double lattice_g(double x, double y, double z, double a)
-{
-    x -= a * rint(x / a);
-    y -= a * rint(y / a);
-    z -= a * rint(z / a);
-    const double alpha = 2.44 / a;
-    double real = 0.0;
-    for (int i = -2; i <= 2; ++i)
-        for (int j = -2; j <= 2; ++j)
-            for (int k = -2; k <= 2; ++k) {
-                const double dx = x + a * i, dy = y + a * j, dz = z + a * k;
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                real += erfc(alpha * r) / r;
-            }
-    const double V = a * a * a, tk = 2.0 * M_PI / a;
-    double recip = 0.0;
-    for (int i = -7; i <= 7; ++i)
-        for (int j = -7; j <= 7; ++j)
-            for (int k = -7; k <= 7; ++k) {
-                if (i == 0 && j == 0 && k == 0) continue;
-                const double kx = tk * i, ky = tk * j, kz = tk * k;
-                const double k2 = kx * kx + ky * ky + kz * kz;
-                recip += exp(-k2 / (4.0 * alpha * alpha)) / k2 * cos(kx * x + ky * y + kz * z);
-            }
-    return real + 4.0 * M_PI / V * recip;
-}
 
 // bracket of the pair move for a charge on layer zi (z = (zi + 1/2) h) and hop
 // k with offsets (dx, dy, dz): G(d1) - 2 G(d2) + G(d4) (the two mixed terms are
@@ -83,9 +51,9 @@ __global__ void k_slab_cross(int half, int K, const int32_t *__restrict__ offs, 
         return;
     }
     const double z = (zi + 0.5) * h, zt = (tz + 0.5) * h;
-    const double g1 = lattice_g(0.0, 0.0, 2.0 * zt - a, a);                 // r_i' - r_m'
-    const double g2 = lattice_g(dx * h, dy * h, z + zt - a, a);             // r_i' - r_m
-    const double g4 = lattice_g(0.0, 0.0, 2.0 * z - a, a);                  // r_i - r_m
+    const double g1 = periodic_g(0.0, 0.0, 2.0 * zt - a, a);                 // r_i' - r_m'
+    const double g2 = periodic_g(dx * h, dy * h, z + zt - a, a);             // r_i' - r_m
+    const double g4 = periodic_g(0.0, 0.0, 2.0 * z - a, a);                  // r_i - r_m
     cross[e] = g1 - 2.0 * g2 + g4;
 }
 
