@@ -47,6 +47,7 @@ def lib():
             "or_periodic_self_change": (d, [d, vp]),
             "of_set_self_image": (None, [vp, i]),
             "of_create": (vp, [i, d, i, i, i, vp, vp, i]),
+            "of_create_levels": (vp, [i, d, i, i, i, vp, vp, i, i]),
             "of_destroy": (None, [vp]),
             "of_energy": (d, [vp]),
             "of_propose": (None, [vp, i, vp, vp, vp]),
@@ -54,6 +55,7 @@ def lib():
             "of_nterms": (i, [vp]),
             "of_fine_cell_of": (i, [vp, vp]),
             "of_get_local": (None, [vp, i, vp]),
+            "of_get_level_local": (None, [vp, i, i, vp]),
             "of_get_multipole": (None, [vp, i, i, vp]),
             "of_get_far": (None, [vp, vp, vp, vp]),
             "of_get_positions": (None, [vp, vp]),
@@ -216,9 +218,11 @@ class FmmKmc:
     query needs it (same arithmetic, restricted to those cells).
     self_image: "expansion" (the paper's self terms of Sec. 3.1) or "exact"
     (q^2 (psi_self - psi(r' - r)), tin-foil Ewald).
+    per_level: keep the local expansion of every level apart and update each
+    level's interaction-list cells at an accept (instead of every fine cell).
     """
 
-    def __init__(self, xyz, q, a, L, p, bc="free", lazy=False, self_image="expansion"):
+    def __init__(self, xyz, q, a, L, p, bc="free", lazy=False, self_image="expansion", per_level=False):
         self.xyz = _f64(xyz, (-1, 3)).copy()
         self.q = _f64(q).copy()
         self.a, self.L, self.p = float(a), int(L), int(p)
@@ -227,8 +231,9 @@ class FmmKmc:
             raise ValueError("periodic boxes need L >= 3")
         if bc == "periodic" and abs(self.q.sum()) > 1e-12:
             raise ValueError("periodic boxes must be neutral")
-        self._c = lib().of_create(1 if bc == "periodic" else 0, self.a, self.L, self.p, len(self.q),
-                                  _p(self.xyz), _p(self.q), 1 if lazy else 0)
+        self._c = lib().of_create_levels(1 if bc == "periodic" else 0, self.a, self.L, self.p, len(self.q),
+                                         _p(self.xyz), _p(self.q), 1 if lazy else 0, 1 if per_level else 0)
+        self.per_level = bool(per_level)
         if self_image not in ("expansion", "exact"):
             raise ValueError("self_image must be 'expansion' or 'exact'")
         # periodic boxes: the moving charge's own copies by the paper's terms
@@ -260,6 +265,12 @@ class FmmKmc:
     def positions(self):
         out = np.zeros((len(self.q), 3))
         lib().of_get_positions(self._c, _p(out))
+        return out
+
+    def level_local(self, level, cell):
+        """Psi of one cell on a level (per-level expansions: that level's own terms)"""
+        out = np.zeros(nterms(self.p), np.complex128)
+        lib().of_get_level_local(self._c, int(level), int(cell), _p(out))
         return out
 
     def local(self, cell):

@@ -44,6 +44,19 @@
  *   Sec. 3.1); every fine cell beta gets -P2L(q at r + a nu) for every copy nu
  *   (free space: nu = 0 only) that is not in the 27 cells around beta, and
  *   +P2L(q at r' + a nu) likewise; E += dE, K += dK, H = R K; U += dU.
+ * Per-level expansions (the survey's next step f1: the O(log N) accept that the
+ *   Introduction and Sec. 7 point to): Psi_l of level l holds only the M2L
+ *   terms of its own interaction list, with no L2L from the parent, and the
+ *   potential of a point is the sum over l = start..L of Psi_l of its level-l
+ *   cell, each about that cell's centre (equal to the accumulated Psi_L up to
+ *   rounding, since L2L of a truncated local expansion is exact).  The accept
+ *   rule is then applied per level: Psi_{l,beta} gets -P2L(q at r + a nu) for
+ *   every copy whose level-l cell lies in the interaction list of beta
+ *   (outside the 27 cells around beta, inside the children of the 27 cells
+ *   around its parent), and +P2L(q at r' + a nu) likewise, about the centre of
+ *   beta.  This touches at most 189 cells per level and copy instead of every
+ *   fine cell; the truncation differs from the fine-level rule, so results
+ *   move at truncation level.
  * Energy (Alg. "fmm_evaluation", with the charge q_i that the printed line 4
  *   leaves out): U = sum_i 1/2 q_i (Psi(r_i) + sum_{near, j != i} q_j / r_ij)
  *   + 1/2 sum E H.
@@ -70,6 +83,7 @@ struct of_ctx {
     double U;
     int U_valid;
     int self_exact;
+    int per_level; /* keep Psi_l of every level apart (no L2L) */
 };
 
 static int side(int l) { return 1 << (l - 1); }
@@ -207,6 +221,40 @@ static void accept_update_cell(of_ctx *c, int cell, double q, const double rold[
     }
 }
 
+/* per-level accept rule: P2L into cell `cell` of level l of every copy of the
+ * two endpoints whose level-l cell is in the interaction list of `cell` */
+static void accept_update_level(of_ctx *c, int l, int cell, double q, const double rold[3],
+                                const double rnew[3], cplx *Y)
+{
+    int n = side(l), nf = side(c->L), bx, by, bz;
+    cxyz(n, cell, &bx, &by, &bz);
+    int b[3] = {bx, by, bz};
+    double ctr[3];
+    centre(c, l, bx, by, bz, ctr);
+    int lim = c->bc ? 1 : 0, f = 1 << (c->L - l);
+    for (int e = 0; e < 2; ++e) {
+        const double *y = e ? rnew : rold;
+        double qq = e ? q : -q;
+        int g0[3];
+        fine_index(c, y, g0);
+        for (int i = -lim; i <= lim; ++i)
+            for (int j = -lim; j <= lim; ++j)
+                for (int k = -lim; k <= lim; ++k) {
+                    int nu[3] = {i, j, k}, G[3], in_il = 0, near = 1, parent_near = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        /* the copy's cell on level l, in unwrapped coordinates */
+                        G[d] = floordiv(g0[d] + nu[d] * nf, f);
+                        if (abs(G[d] - b[d]) > 1) near = 0;
+                        if (abs(floordiv(G[d], 2) - floordiv(b[d], 2)) > 1) parent_near = 0;
+                    }
+                    in_il = !near && parent_near;
+                    if (!in_il) continue;
+                    double d[3] = {y[0] + c->a * i - ctr[0], y[1] + c->a * j - ctr[1], y[2] + c->a * k - ctr[2]};
+                    ops_p2l_add(c->ops, qq, d, c->psi[l] + (size_t)cell * c->nt, Y);
+                }
+    }
+}
+
 /* Psi of one cell on level l, given Psi of its parent (if any) and Phi */
 static void compute_psi(of_ctx *c, int l, int cell, cplx *Y, cplx *Y2)
 {
@@ -216,7 +264,7 @@ static void compute_psi(of_ctx *c, int l, int cell, cplx *Y, cplx *Y2)
     memset(P, 0, sizeof(cplx) * nt);
     double ctr[3];
     centre(c, l, ax, ay, az, ctr);
-    if (l - 1 >= c->start) {
+    if (l - 1 >= c->start && !c->per_level) {
         int np = side(l - 1);
         int px = ax >> 1, py = ay >> 1, pz = az >> 1;
         double pctr[3];
@@ -242,7 +290,10 @@ static void compute_psi(of_ctx *c, int l, int cell, cplx *Y, cplx *Y2)
                 double Q[3] = {sctr[0] - ctr[0], sctr[1] - ctr[1], sctr[2] - ctr[2]};
                 ops_m2l_add(c->ops, c->phi[l] + (size_t)prim * nt, Q, P, Y2);
             }
-    if (l == c->L) {
+    if (c->per_level) {
+        for (int e = 0; e < c->nlog; ++e)
+            accept_update_level(c, l, cell, c->log_q[e], c->log_old + 3 * e, c->log_new + 3 * e, Y);
+    } else if (l == c->L) {
         for (int e = 0; e < c->nlog; ++e)
             accept_update_cell(c, cell, c->log_q[e], c->log_old + 3 * e, c->log_new + 3 * e, Y);
     }
@@ -312,7 +363,14 @@ static void apply_R(const of_ctx *c, const cplx *K, cplx *H)
 
 of_ctx *of_create(int bc, double a, int L, int p, int n, const double *xyz, const double *q, int lazy)
 {
+    return of_create_levels(bc, a, L, p, n, xyz, q, lazy, 0);
+}
+
+of_ctx *of_create_levels(int bc, double a, int L, int p, int n, const double *xyz, const double *q, int lazy,
+                         int per_level)
+{
     of_ctx *c = (of_ctx *)calloc(1, sizeof(of_ctx));
+    c->per_level = per_level ? 1 : 0;
     c->bc = bc;
     c->a = a;
     c->L = L;
@@ -464,18 +522,36 @@ static double near_sum(const of_ctx *c, const double x[3], const int g[3], int64
     return s;
 }
 
+/* the local-expansion part of the potential at x in fine cell g: Psi_L of the
+ * cell, or with per-level expansions the sum over levels of Psi_l of the
+ * level-l cell containing it, each about that cell's centre */
+static double local_part(const of_ctx *c, const double x[3], const int g[3], cplx *Y)
+{
+    if (!c->per_level) {
+        double ctr[3];
+        centre(c, c->L, g[0], g[1], g[2], ctr);
+        double d[3] = {x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2]};
+        return ops_eval_local(c->ops, c->psi[c->L] + (size_t)cid(side(c->L), g[0], g[1], g[2]) * c->nt, d, Y);
+    }
+    double s = 0.0;
+    for (int l = c->start; l <= c->L; ++l) {
+        int sh = c->L - l, ax = g[0] >> sh, ay = g[1] >> sh, az = g[2] >> sh;
+        double ctr[3];
+        centre(c, l, ax, ay, az, ctr);
+        double d[3] = {x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2]};
+        s += ops_eval_local(c->ops, c->psi[l] + (size_t)cid(side(l), ax, ay, az) * c->nt, d, Y);
+    }
+    return s;
+}
+
 /* potential at x (a point of the box) from all charges except `exclude`;
  * Psi_L of x's cell must exist */
 double of_potential(of_ctx *c, const double x[3], int64_t exclude)
 {
     int g[3];
     fine_index(c, x, g);
-    int n = side(c->L), cell = cid(n, g[0], g[1], g[2]);
-    double ctr[3];
-    centre(c, c->L, g[0], g[1], g[2], ctr);
     cplx *Y = (cplx *)malloc(sizeof(cplx) * c->nt);
-    double d[3] = {x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2]};
-    double phi = ops_eval_local(c->ops, c->psi[c->L] + (size_t)cell * c->nt, d, Y);
+    double phi = local_part(c, x, g, Y);
     phi += near_sum(c, x, g, exclude);
     if (c->bc) {
         double e[3] = {x[0] - 0.5 * c->a, x[1] - 0.5 * c->a, x[2] - 0.5 * c->a};
@@ -520,17 +596,9 @@ static double propose_one(of_ctx *c, int64_t i, const double t[3])
     int ga[3], gb[3];
     fine_index(c, r, ga);
     fine_index(c, tw, gb);
-    int n = side(c->L);
-    double ca[3], cb[3];
-    centre(c, c->L, ga[0], ga[1], ga[2], ca);
-    centre(c, c->L, gb[0], gb[1], gb[2], cb);
     cplx *Y = (cplx *)malloc(sizeof(cplx) * c->nt);
-    double da[3] = {r[0] - ca[0], r[1] - ca[1], r[2] - ca[2]};
-    double db[3] = {tw[0] - cb[0], tw[1] - cb[1], tw[2] - cb[2]};
-    double phi_new = ops_eval_local(c->ops, c->psi[c->L] + (size_t)cid(n, gb[0], gb[1], gb[2]) * c->nt, db, Y) +
-                     near_sum(c, tw, gb, -1);
-    double phi_old = ops_eval_local(c->ops, c->psi[c->L] + (size_t)cid(n, ga[0], ga[1], ga[2]) * c->nt, da, Y) +
-                     near_sum(c, r, ga, i);
+    double phi_new = local_part(c, tw, gb, Y) + near_sum(c, tw, gb, -1);
+    double phi_old = local_part(c, r, ga, Y) + near_sum(c, r, ga, i);
     double dU = q * phi_new - q * phi_old;
     if (!c->bc) {
         double d0 = tw[0] - r[0], d1 = tw[1] - r[1], d2 = tw[2] - r[2];
@@ -617,8 +685,20 @@ double of_accept(of_ctx *c, int64_t i, const double newpos[3])
         cplx *Y = (cplx *)malloc(sizeof(cplx) * c->nt);
 #pragma omp for schedule(dynamic, 16)
         for (int b = 0; b < nf; ++b)
-            if (c->psi_ok[L][b]) accept_update_cell(c, b, q, rold, tw, Y);
+            if (c->psi_ok[L][b] && !c->per_level) accept_update_cell(c, b, q, rold, tw, Y);
         free(Y);
+    }
+    if (c->per_level) {
+        for (int l = c->start; l <= L; ++l) {
+#pragma omp parallel
+            {
+                cplx *Y = (cplx *)malloc(sizeof(cplx) * c->nt);
+#pragma omp for schedule(dynamic, 16)
+                for (int b = 0; b < ncell(l); ++b)
+                    if (c->psi_ok[l][b]) accept_update_level(c, l, b, q, rold, tw, Y);
+                free(Y);
+            }
+        }
     }
     /* log for cells whose local expansion is formed later */
     if (c->nlog == c->caplog) {
@@ -661,6 +741,17 @@ void of_get_local(of_ctx *c, int cell, cplx *out)
 {
     ensure_psi(c, 1, &cell);
     memcpy(out, c->psi[c->L] + (size_t)cell * c->nt, sizeof(cplx) * c->nt);
+}
+
+/* Psi of one cell on level l (formed first if needed) */
+void of_get_level_local(of_ctx *c, int level, int cell, cplx *out)
+{
+    int sh = c->L - level, n = side(level), nf = side(c->L);
+    int ax, ay, az;
+    cxyz(n, cell, &ax, &ay, &az);
+    int fine = cid(nf, ax << sh, ay << sh, az << sh);
+    ensure_psi(c, 1, &fine);
+    memcpy(out, c->psi[level] + (size_t)cell * c->nt, sizeof(cplx) * c->nt);
 }
 
 void of_get_multipole(of_ctx *c, int level, int cell, cplx *out)

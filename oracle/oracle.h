@@ -85,6 +85,11 @@ typedef struct of_ctx of_ctx;
  * order, restricted to the cells that are asked for). */
 of_ctx *of_create(int bc, double a, int L, int p, int n, const double *xyz,
                   const double *q, int lazy);
+/* as of_create; per_level: keep the local expansion of every level apart (the
+ * interaction-list terms of that level only) and apply the accept rule per
+ * level (see fmm_kmc.c) */
+of_ctx *of_create_levels(int bc, double a, int L, int p, int n, const double *xyz, const double *q, int lazy,
+                         int per_level);
 void of_destroy(of_ctx *c);
 /* self-image terms of a periodic proposal: 0 (default) the paper's V_box sum,
  * constant and 1/2 dE.R'dK (Sec. 3.1); 1 the exact change q^2 (psi_self -
@@ -97,6 +102,7 @@ int of_nterms(of_ctx *c);
 int of_fine_cell_of(of_ctx *c, const double x[3]);
 void of_get_local(of_ctx *c, int cell, cplx *out);
 void of_get_multipole(of_ctx *c, int level, int cell, cplx *out);
+void of_get_level_local(of_ctx *c, int level, int cell, cplx *out);
 void of_get_far(of_ctx *c, cplx *E, cplx *K, cplx *H);
 void of_get_positions(of_ctx *c, double *xyz);
 double of_potential(of_ctx *c, const double x[3], int64_t exclude);

@@ -356,3 +356,100 @@ def test_exact_self_image_accepts_and_round_trips():
     assert d1 == pytest.approx(O.ewald_energy(xyz1, q, n) - O.ewald_energy(xyz, q, n), abs=2e-6)
     d2 = f.accept(i, xyz[i])
     assert d2 == pytest.approx(-d1, abs=2e-6)
+
+
+# ---- per-level expansions (the survey's next step f1; Introduction and Sec. 7) ----
+
+@pytest.mark.parametrize("bc,L", [("free", 4), ("periodic", 3), ("periodic", 4)])
+def test_per_level_expansions_equal_accumulated_before_commits(bc, L):
+    """Summing every level's own expansion at a point equals the accumulated
+    fine-level expansion to rounding (L2L of a truncated local expansion is an
+    exact polynomial translation), so before any commit the two modes agree"""
+    n, N, p = 16, 300, 8
+    sites, xyz, q = lattice(n, N, 25)
+    idx, tgt, valid = proposals(sites, n, bc == "periodic")
+    a = O.FmmKmc(xyz, q, n, L, p, bc).propose(idx[valid], tgt[valid])
+    f = O.FmmKmc(xyz, q, n, L, p, bc, per_level=True)
+    b = f.propose(idx[valid], tgt[valid])
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.mean(np.abs(a))
+    assert f.energy == pytest.approx(O.FmmKmc(xyz, q, n, L, p, bc).energy, rel=1e-13)
+
+
+@pytest.mark.parametrize("bc,n,N,L,p", [("free", 16, 150, 4, 16), ("periodic", 8, 40, 3, 18)])
+def test_per_level_commits_keep_dU_exact(bc, n, N, L, p):
+    """After long moves the per-level update keeps O-fmm's dU as close to
+    O-exact (direct sum, tin-foil Ewald) as before the commits (high p).
+    Catches a per-level rule that misses copies (a wrong interaction-list
+    test, missing images) or updates with the wrong sign."""
+    periodic = bc == "periodic"
+    sites, xyz, q = lattice(n, N, 26)
+    f = O.FmmKmc(xyz, q, n, L, p, bc, per_level=True)
+    cur = _long_moves(f, sites, n, L, 6 if not periodic else 5, 8, min_cells=3 if not periodic else 2)
+    xyz1 = W.site_xyz(cur, n)
+    idx, tgt, valid = proposals(cur, n, periodic)
+    ref = O.ewald_dU(xyz1, q, n, idx[valid], tgt[valid]) if periodic else O.direct_dU(xyz1, q, idx[valid],
+                                                                                        tgt[valid])
+    d = f.propose(idx[valid], tgt[valid])
+    err = np.max(np.abs(d - ref)) / np.mean(np.abs(ref))
+    assert err < (2e-6 if periodic else 3e-7), err
+
+
+@pytest.mark.parametrize("bc,n,N,L,p", [("free", 16, 120, 4, 10), ("periodic", 8, 40, 3, 10),
+                                        ("periodic", 16, 120, 4, 10)])
+def test_per_level_accept_changes_each_cell_by_its_interaction_list(bc, n, N, L, p):
+    """One accepted move, every cell of every level: at a cell's centre its
+    expansion reduces to the constant term, so the change of Psi_{l,beta} there
+    must equal, to rounding, the Coulomb change of exactly the copies whose
+    level-l cell is in the interaction list of beta (outside the 27 cells
+    around beta, inside the children of the 27 around its parent)"""
+    periodic = bc == "periodic"
+    sites, xyz, q = lattice(n, N, 27)
+    f = O.FmmKmc(xyz, q, n, L, p, bc, per_level=True)
+    start = 2 if periodic else 3
+    i = 1
+    r = xyz[i].copy()
+    occ = set(sites.tolist())
+    rng = np.random.default_rng(9)
+    while True:
+        s = int(rng.integers(n ** 3))
+        if s not in occ:
+            t = W.site_xyz([s], n)[0]
+            break
+    levels = range(start, L + 1)
+    before = {(l, c): f.level_local(l, c) for l in levels for c in range(8 ** (l - 1))}
+    f.accept(i, t)
+    rngc = (-1, 0, 1) if periodic else (0,)
+    worst, scale = 0.0, 0.0
+    for (l, c), b0 in before.items():
+        side = 2 ** (l - 1)
+        w = n / side
+        g = np.array([c // (side * side), (c // side) % side, c % side])
+        ctr = (g + 0.5) * w
+        want = 0.0
+        for pos, sgn in ((t, 1.0), (r, -1.0)):
+            for nu in [(a, b, cc) for a in rngc for b in rngc for cc in rngc]:
+                y = pos + n * np.array(nu, float)
+                G = np.floor(y / w).astype(int)
+                near = np.max(np.abs(G - g)) <= 1
+                parent_near = np.max(np.abs(np.floor_divide(G, 2) - g // 2)) <= 1
+                if not near and parent_near:
+                    want += sgn * q[i] / np.linalg.norm(ctr - y)
+        got = O.eval_local(p, f.level_local(l, c) - b0, ctr, ctr)
+        worst = max(worst, abs(got - want))
+        scale = max(scale, abs(want))
+    assert scale > 0
+    assert worst <= 1e-13 * scale, (worst, scale)
+
+
+def test_per_level_round_trip_restores_state():
+    n, N, L, p = 16, 120, 4, 8
+    sites, xyz, q = lattice(n, N, 28)
+    f = O.FmmKmc(xyz, q, n, L, p, "periodic", per_level=True)
+    cells = [(2, 3), (3, 17), (4, 100), (4, 511)]
+    before = [f.level_local(l, c) for l, c in cells]
+    idx, tgt, valid = proposals(sites, n, True)
+    s = np.nonzero(valid)[0][7]
+    f.accept(idx[s], tgt[s])
+    f.accept(idx[s], xyz[idx[s]])
+    for (l, c), b in zip(cells, before):
+        assert np.max(np.abs(f.level_local(l, c) - b)) <= 1e-13 * np.max(np.abs(b))
