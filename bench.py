@@ -137,17 +137,18 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed, self_image="expansion", host_loop=True):
+def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed, self_image="expansion", host_loop=True,
+            per_level=False):
     import torch
 
     from paper_1905_04065_amd import Context
 
     sites, xyz, q = W.lattice_charges(n, N, seed)
     K = len(hops)
-    log(f"[{precision}, self image {self_image}] create n={n} N={N} L={L} p={p} K={K}")
+    log(f"[{precision}, self image {self_image}, per-level {per_level}] create n={n} N={N} L={L} p={p} K={K}")
     t0 = time.perf_counter()
     ctx = Context(xyz, q, a=float(n), levels=L, order=p, bc="periodic", precision=precision, lattice_n=n,
-                  device=0, self_image=self_image)
+                  device=0, self_image=self_image, per_level=per_level)
     U0 = ctx.initialise()
     dU, mask = ctx.propose_lattice(hops)  # builds the per-charge hop table once
     torch.cuda.synchronize()
@@ -179,7 +180,8 @@ def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed, self_image="expans
         return d
 
     names = ["site_phi_s2", "site_phi", "slot_lattice", "sweep", "path", "far_refresh", "cheb_a", "cheb_b", "f_rows",
-             "f_row1", "self_hops", "book", "move_dU"]  # f_row1 runs on the side stream, beside the sweep
+             "f_row1", "self_hops", "book", "move_dU", "levels", "coarse_s2", "coarse_sites"]
+    # f_row1 runs on the side stream, beside the sweep
     ktimes, wall, propose_wall, commit_wall = {}, float("nan"), float("nan"), float("nan")
     if host_loop:
         for _ in range(warmup):
@@ -507,6 +509,8 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="only the batched-replica workload (JSON to stdout)")
     ap.add_argument("--skip-exact-self", action="store_true",
                     help="leave out the runs with the exact self-image option")
+    ap.add_argument("--skip-per-level", action="store_true",
+                    help="leave out the runs with per-level local expansions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is "
@@ -526,16 +530,18 @@ def main():
     res = {pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed) for pr in precs}
     res_exact = {} if args.skip_exact_self else {
         pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, self_image="exact") for pr in precs}
+    res_levels = {} if args.skip_per_level else {
+        pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, per_level=True) for pr in precs}
     copy_gbs = copy_bandwidth()
     if args.copy_calibration:
         copy_bandwidth(1 << 30, reps=3)
     head_prec = "fp64" if "fp64" in res else precs[0]
     slots = N * K
 
-    def summary(pr, exact=False):
-        r = (res_exact if exact else res)[pr]
+    def summary(pr, exact=False, levels=False):
+        r = (res_levels if levels else res_exact if exact else res)[pr]
         kt = r["kernels"]
-        traffic = {} if exact else profiled_traffic(tag, pr)
+        traffic = {} if (exact or levels) else profiled_traffic(tag, pr)
         roof = {k: roofline_entry(k, kt, n, N, K, p, pr, copy_gbs, traffic, exact)
                 for k in ("site_phi_s2", "slot_lattice", "sweep")}
         # the kernel that takes the largest share of a step
@@ -601,6 +607,17 @@ def main():
                 "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"],
                 "note": "self_image=1: the moving charge's own copies by the exact Ewald change per hop instead of the "
                         "V_box sum + constant + 1/2 dE.R'dK (no per-charge hop table)"}
+    if res_levels:
+        out["per_level"] = {}
+        for pr in precs:
+            m = summary(pr, levels=True)
+            out["per_level"][pr] = {
+                "value": m["value"], "ms_per_step": m["ms_per_step"], "host_driven_ms_per_step": m["host_driven_ms_per_step"],
+                "propose_us": m["propose_us"], "commit_us": m["commit_us"], "setup_s": m["setup_s"],
+                "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"],
+                "note": "per_level=1: local expansions kept per level; an accept updates the interaction-list cells "
+                        "of each level (k_levels) instead of every fine cell (k_sweep); proposals add the coarser "
+                        "levels per site (k_coarse_s2)"}
     if not args.skip_batch:
         out["batched"] = batched_summary(args)
         out["slab"] = run_slab(max(args.steps, 5), args.warmup, W.BASE_SEED + 6)

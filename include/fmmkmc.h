@@ -73,6 +73,15 @@ typedef struct fmmkmc_params {
                           pair potential (Ewald sum): results move at truncation level,
                           and lattice proposals need no per-charge hop table.
                           Ignored in free space. */
+    int per_level;     /* 0: fine-level local expansions accumulated over the levels
+                          (Alg. "fmm"), every fine cell updated at an accept (Sec. 3
+                          "Accept move"); 1: each level keeps only its own
+                          interaction-list terms, a proposal sums the levels, and an
+                          accept updates per level only the cells whose interaction
+                          list holds the moved charge (at most 189 per level and copy
+                          instead of every fine cell; the O(log N) accept the
+                          Introduction and Sec. 7 point to).  Same result before any
+                          accept; after accepts the two differ at truncation level. */
 } fmmkmc_params;
 
 /* Create a context for n charges (KMCFMM(positions, charges, r, l), Sec. 5.2).

@@ -33,7 +33,7 @@ class FmmKmcError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("bc", C.c_int), ("levels", C.c_int), ("order", C.c_int),
                 ("precision", C.c_int), ("lattice_n", C.c_int), ("cell_capacity", C.c_int),
-                ("device", C.c_int), ("stream", C.c_void_p), ("self_image", C.c_int)]
+                ("device", C.c_int), ("stream", C.c_void_p), ("self_image", C.c_int), ("per_level", C.c_int)]
 
 
 _SELF_IMAGE = {"expansion": 0, "exact": 1}
@@ -120,11 +120,14 @@ class Context:
     precision: "fp64" or "mixed"; lattice_n: n > 0 when every charge sits on a
     site of the n^3 lattice of spacing a/n (enables propose_lattice);
     self_image (periodic): "expansion" (the self terms of Sec. 3.1) or "exact"
-    (their exact Ewald value, see fmmkmc_params in include/fmmkmc.h).
+    (their exact Ewald value, see fmmkmc_params in include/fmmkmc.h);
+    per_level: keep the local expansions of every level apart, so that an
+    accept updates only the cells whose interaction lists hold the moved
+    charge instead of every fine cell.
     """
 
     def __init__(self, xyz, q, a, levels, order, bc="free", precision="fp64", lattice_n=0, cell_capacity=0,
-                 device=0, stream=None, self_image="expansion"):
+                 device=0, stream=None, self_image="expansion", per_level=False):
         torch = _torch()
         self._L = load_library()
         self.device = torch.device("cuda", device)
@@ -139,7 +142,7 @@ class Context:
         self.K = None
         prm = _Params(float(a), 1 if bc == "periodic" else 0, int(levels), int(order),
                       1 if precision == "mixed" else 0, int(lattice_n), int(cell_capacity), int(device),
-                      C.c_void_p(stream.cuda_stream), _SELF_IMAGE[self_image])
+                      C.c_void_p(stream.cuda_stream), _SELF_IMAGE[self_image], 1 if per_level else 0)
         h = C.c_void_p()
         rc = self._L.fmmkmc_create(C.byref(prm), self.N, xyz.ctypes.data_as(C.c_void_p),
                                    q.ctypes.data_as(C.c_void_p), C.byref(h))
@@ -149,6 +152,7 @@ class Context:
         self.a, self.bc, self.levels, self.order = float(a), bc, int(levels), int(order)
         self.precision, self.lattice_n = precision, int(lattice_n)
         self.self_image = self_image
+        self.per_level = bool(per_level)
 
     # -- helpers --
     def _check(self, rc):
@@ -382,7 +386,7 @@ class Slab:
     boundaries, by the first mirror image and the periodic algorithm)."""
 
     def __init__(self, xyz, q, a, levels, order, lattice_n, ez=0.0, precision="fp64", cell_capacity=0, device=0,
-                 stream=None, self_image="expansion"):
+                 stream=None, self_image="expansion", per_level=False):
         torch = _torch()
         self._L = load_library()
         self.device = torch.device("cuda", device)
@@ -395,7 +399,8 @@ class Slab:
             raise ValueError("xyz and q lengths differ")
         self.N = len(q)
         prm = _Params(float(a), 1, int(levels), int(order), 1 if precision == "mixed" else 0, int(lattice_n),
-                      int(cell_capacity), int(device), C.c_void_p(stream.cuda_stream), _SELF_IMAGE[self_image])
+                      int(cell_capacity), int(device), C.c_void_p(stream.cuda_stream), _SELF_IMAGE[self_image],
+                      1 if per_level else 0)
         h = C.c_void_p()
         rc = self._L.fmmkmc_slab_create(C.byref(prm), self.N, xyz.ctypes.data_as(C.c_void_p),
                                         q.ctypes.data_as(C.c_void_p), float(ez), C.byref(h))

@@ -149,6 +149,8 @@ void release(fmmkmc_ctx *c)
     for (auto &p : c->phi_lv) dfree(p);
     for (auto &p : c->psi_lv) dfree(p);
     dfree(c->d_phi_ptrs);
+    dfree(c->d_psi_ptrs);
+    dfree(c->phicoarse);
     dfree(c->psi32);
     dfree(c->phisite);
     for (auto &p : c->m2m) dfree(p);
@@ -345,6 +347,8 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
     c->prec = prm->precision;
     if (prm->self_image != 0 && prm->self_image != 1) return fail(c, FMMKMC_EINVAL, "self_image must be 0 or 1");
     c->self_exact = (prm->bc == FMMKMC_PERIODIC && prm->self_image == 1) ? 1 : 0;
+    if (prm->per_level != 0 && prm->per_level != 1) return fail(c, FMMKMC_EINVAL, "per_level must be 0 or 1");
+    c->per_level = prm->per_level;
     c->lat_n = prm->lattice_n;
     c->device = prm->device;
     c->stream = (hipStream_t)prm->stream;
@@ -475,6 +479,8 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
     }
     c->d_phi_ptrs = dalloc<double *>(c->L + 1);
     upload(c->d_phi_ptrs, c->phi_lv.data(), c->L + 1, s);
+    c->d_psi_ptrs = dalloc<double *>(c->L + 1);
+    upload(c->d_psi_ptrs, c->psi_lv.data(), c->L + 1, s);
     if (c->prec == FMMKMC_MIXED) c->psi32 = dalloc<float>((size_t)c->M * c->nt);
     if (c->lat_n > 0) {
         const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
@@ -511,6 +517,10 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
             HIPCHK(hipStreamSynchronize(s));
         }
         c->phisite = dalloc<double>(ns);
+        // per-level mode: the coarser levels' potential per site (none when only the fine level has an
+        // interaction list)
+        const int lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
+        if (c->per_level && c->L - 1 >= lstart) c->phicoarse = dalloc<double>(ns);
         {
             // charge per site in site order (0 on a vacant site)
             std::vector<double> qs(ns, 0.0);
@@ -632,6 +642,9 @@ Geo make_geo(const fmmkmc_ctx *c)
     g.cap = c->cap;
     g.tab_ok = c->near_tab_ok;
     g.self_exact = c->self_exact;
+    g.per_level = c->per_level;
+    g.L = c->L;
+    g.lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
     return g;
 }
 
@@ -854,6 +867,7 @@ int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double 
             }
             c->F_offsets = off;
         }
+        launch_coarse_sites(c, g);  // per-level mode: the levels above the fine one
         launch_site_phi(c, g);
         launch_slot_lattice(c, g, K, dU, mask);
         return FMMKMC_OK;

@@ -420,8 +420,10 @@ struct fmmkmc_batch {
     double *out_dU = nullptr, *out_dt = nullptr;
     int cap_steps = 0;
     // phases
-    Phase site, slot, count, sweep, path, far, cheb_a, cheb_b;
+    Phase site, slot, count, sweep, path, far, cheb_a, cheb_b, coarse;
     int slot_tc = 64, sweep_block = 256;
+    bool per_level = false;  // replicas keep their local expansions per level (no sweep)
+    int Lmax = 0;
     int64_t slots_per_step = 0;
     // graph of one step
     hipGraph_t graph = nullptr;
@@ -475,6 +477,7 @@ void record_step(fmmkmc_batch *b)
 {
     const hipStream_t s = b->stream;
     const int R = b->R;
+    if (b->per_level) launch_b_coarse(b->prof, s, b->reps, R, b->coarse.d, b->coarse.blocks, b->p);
     launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->p, b->mixed);
     launch_b_slot(b->prof, s, b->reps, R, b->slot.d, b->slot.blocks, b->slot_tc);
     launch_prof(b->prof, s, "b_count", k_b_count, dim3((unsigned)b->count.blocks), dim3(256), 0, b->reps, R,
@@ -497,7 +500,10 @@ void record_step(fmmkmc_batch *b)
     launch_b_far(b->prof, b->aux, b->reps, R, b->far.d, b->far.blocks, b->cheb_a.d, b->cheb_a.blocks, b->cheb_b.d,
                  b->cheb_b.blocks, b->moves);
     HIPCHK(hipEventRecord(b->ev_join, b->aux));
-    launch_b_sweep(b->prof, s, b->reps, R, b->sweep.d, b->sweep.blocks, b->p, b->moves, b->sweep_block);
+    if (b->per_level)
+        launch_b_levels(b->prof, s, b->reps, R, b->p, b->moves, b->Lmax, 2);
+    else
+        launch_b_sweep(b->prof, s, b->reps, R, b->sweep.d, b->sweep.blocks, b->p, b->moves, b->sweep_block);
     HIPCHK(hipStreamWaitEvent(s, b->ev_join, 0));
     launch_prof(b->prof, s, "b_finish", k_b_finish, dim3(1), dim3(256), 0, (const MoveDev *)b->moves, R,
                 (const double *)b->acc, b->U, b->step, b->out_i, b->out_site, b->out_dU, b->rates,
@@ -572,7 +578,8 @@ void release_batch(fmmkmc_batch *b)
     dfree(b->out_site);
     dfree(b->out_dU);
     dfree(b->out_dt);
-    for (Phase *ph : {&b->site, &b->slot, &b->count, &b->sweep, &b->path, &b->far, &b->cheb_a, &b->cheb_b})
+    for (Phase *ph : {&b->site, &b->slot, &b->count, &b->sweep, &b->path, &b->far, &b->cheb_a, &b->cheb_b,
+                      &b->coarse})
         dfree(ph->d);
     for (auto &pd : b->prof.pending) {
         (void)hipEventDestroy(pd.a);
@@ -605,6 +612,8 @@ RepDev make_rep(const fmmkmc_ctx *c, int K, double *dU, uint8_t *mask)
     d.psi = c->psi_lv[c->L];
     d.psi32 = c->prec == FMMKMC_MIXED ? c->psi32 : nullptr;
     d.phi_lv = c->d_phi_ptrs;
+    d.psi_lv = c->d_psi_ptrs;
+    d.phicoarse = c->phicoarse;
     d.x = c->x;
     d.y = c->y;
     d.z = c->z;
@@ -711,6 +720,7 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
         if (!c->initialised) return FMMKMC_ESTATE;
         if (c->p != ctx[0]->p || c->prec != ctx[0]->prec || c->device != ctx[0]->device) return FMMKMC_EINVAL;
         if (c->N * (int64_t)K >= ((int64_t)1 << 32)) return FMMKMC_EINVAL;
+        if (c->per_level != ctx[0]->per_level) return FMMKMC_EINVAL;
     }
     if (f_row1_shm(ctx[0]->nt, K) > 64 * 1024) return FMMKMC_EINVAL;
     fmmkmc_batch *b = new (std::nothrow) fmmkmc_batch();
@@ -721,6 +731,8 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
     b->K = K;
     b->device = ctx[0]->device;
     b->mixed = ctx[0]->prec == FMMKMC_MIXED;
+    b->per_level = ctx[0]->per_level != 0;
+    for (int r = 0; r < n; ++r) b->Lmax = std::max(b->Lmax, ctx[r]->L);
     b->stream = (hipStream_t)stream;
     b->ctx.assign(ctx, ctx + n);
     b->offsets.assign(offsets, offsets + 3 * K);
@@ -761,7 +773,7 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
         upload(b->U, U.data(), n, s);
         b->step = dalloc<int32_t>(1);
         // phase block tables
-        std::vector<int64_t> nsite(n), ncount(n), npath(n), nfar(n), na(n), nb(n);
+        std::vector<int64_t> nsite(n), ncount(n), npath(n), nfar(n), na(n), nb(n), ncoarse(n);
         for (int r = 0; r < n; ++r) {
             const fmmkmc_ctx *c = ctx[r];
             const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
@@ -773,7 +785,9 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             nfar[r] = per ? (c->nt + c->far.ncz + 15) / 16 : 0;
             na[r] = per ? ((int64_t)c->lat_n * q * q + 255) / 256 : 0;
             nb[r] = per ? ((int64_t)c->lat_n * c->lat_n * q + 255) / 256 : 0;
+            ncoarse[r] = c->phicoarse ? (ns + 255) / 256 : 0;
         }
+        set_phase(b->coarse, ncoarse, s);
         set_phase(b->site, nsite, s);
         set_phase(b->count, ncount, s);
         set_phase(b->path, npath, s);
@@ -901,6 +915,7 @@ int fmmkmc_batch_tune(fmmkmc_batch *b, int rounds)
         // sweep: threads per block, timed with zero-charge moves (they leave every expansion unchanged)
         int best_blk = b->sweep_block;
         for (int blk : {128, 256}) {
+            if (b->per_level) break;  // no sweep
             b->sweep_block = blk;
             set_sweep_phase(b);
             const float t = time_launches(b, rounds, [&] {

@@ -22,6 +22,8 @@ struct RepDev {
     double *psi;
     float *psi32;
     double *const *phi_lv;
+    double *const *psi_lv;  // local expansions of every level (per-level mode)
+    double *phicoarse;      // per-level mode: the coarse levels' potential at each site
     // charges
     double *x, *y, *z, *q;
     int32_t *cell, *slot, *site, *cnt, *slots, *rank_of;
@@ -85,6 +87,12 @@ void launch_b_sweep(Profiler &pr, hipStream_t st, const RepDev *reps, int R, con
                     int p, const MoveDev *moves, int block);
 void launch_b_path(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                    const MoveDev *moves);
+// per-level mode: the commit on every level of every replica (instead of the sweep)
+void launch_b_levels(Profiler &pr, hipStream_t st, const RepDev *reps, int R, int p, const MoveDev *moves, int Lmax,
+                     int lstart);
+// per-level mode: the coarse levels' potential at every site of every replica
+void launch_b_coarse(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                     int p);
 void launch_b_book(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves);
 void launch_b_far(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base_far,
                   int64_t blocks_far, const int64_t *base_a, int64_t blocks_a, const int64_t *base_b,

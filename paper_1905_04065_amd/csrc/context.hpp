@@ -30,6 +30,9 @@ struct Geo {
     int tab_ok;    // lattice: every squared site offset of a near field is below kInvTab
     int self_exact;  // periodic: proposals take the exact self-image change (Ewald), not the
                      // V_box self sum + constant + 1/2 dE.R'dK
+    int per_level;   // local expansions kept per level (no L2L); evaluation sums the levels
+    int L;           // levels (root = 1): the fine level
+    int lstart;      // first level with an interaction list (periodic 2, free space 3)
 };
 
 // entries of the 1/sqrt(k) table of the lattice near field (integer squared offsets)
@@ -100,6 +103,9 @@ struct fmmkmc_ctx {
     // expansions (device), coefficient-major [k][cells]
     std::vector<double *> phi_lv, psi_lv;  // index = level 1..L
     double **d_phi_ptrs = nullptr;         // device copy of phi_lv
+    double **d_psi_ptrs = nullptr;         // device copy of psi_lv
+    int per_level = 0;                     // levels kept apart (see fmmkmc_params)
+    double *phicoarse = nullptr;           // per-level, lattice: the levels above the fine one at each site
     float *psi32 = nullptr;                // mixed: FP32 copy of psi_lv[L]
     double *phisite = nullptr;             // lattice: potential per vacant site (NaN if occupied), site order
     double *phi_r = nullptr;               // lattice: phi_occ of each charge, by rank

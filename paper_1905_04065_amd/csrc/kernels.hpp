@@ -99,6 +99,8 @@ void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz,
                       const int64_t *exclude, int with_far, double *out, const char *name,
                       bool fp64 = false);
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g);
+// per-level mode, lattice: the levels above the fine one at every site (phicoarse)
+void launch_coarse_sites(fmmkmc_ctx *c, const Geo &g);
 void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t *mask);
 // exact self-image option: Fhop[k] = G_self - G(h offsets[k]) for the K hops
 void launch_self_hops(fmmkmc_ctx *c, int K);

@@ -8,6 +8,12 @@
 // m): the lane runs the irregular recurrences down its columns and owns
 // coefficients (n, m), n >= m, of its cell, so no two lanes write the same word.
 //
+// Per-level expansions (see fmmkmc_params.per_level): the same P2L, applied on
+// every level l to the cells beta of that level whose interaction list holds
+// the copy (its level-l cell outside the 27 around beta, inside the children
+// of the 27 around beta's parent).  Such cells lie within 3 cells of the copy,
+// so a commit visits the 7^3 blocks around the two endpoints on each level.
+//
 // Path: the multipole expansions of the old and new cell of the moved charge
 // on every level change by -/+ its P2M; level 1 is the box multipole K of the
 // far field.
@@ -136,9 +142,12 @@ __device__ inline void sweep_sources(const Geo &g, const Move &mv, SweepSources 
 }
 
 // PD, PF: pointers to the FP64 expansions and their FP32 shadow (or null),
-// generic or global-space
-template <int P, int M0, int M1, class PD, class PF>
-__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSources &S, PD psi, PF psi32)
+// generic or global-space.  LEVEL: g is the geometry of a coarser level whose
+// cells are the fine cells shifted right by sh, and a copy contributes only
+// from the interaction list (the per-level rule); else every copy outside the
+// near field contributes.
+template <int P, int M0, int M1, bool LEVEL, class PD, class PF>
+__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSources &S, PD psi, PF psi32, int sh)
 {
     constexpr ScaledIrregular<P> SI{};
     constexpr int NACC = col_offset(P, M0, M1 + 1);
@@ -154,8 +163,19 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
     const int nsrc = g.periodic ? 54 : 2;
 #pragma unroll 1
     for (int t = 0; t < nsrc; ++t) {
-        const bool near = ((unsigned)(S.gx[t] - bx + 1) <= 2u) & ((unsigned)(S.gy[t] - by + 1) <= 2u) &
-                          ((unsigned)(S.gz[t] - bz + 1) <= 2u);
+        int sx = S.gx[t], sy = S.gy[t], sz = S.gz[t];
+        if (LEVEL) {  // arithmetic shifts: floor division of the unwrapped coordinates
+            sx >>= sh;
+            sy >>= sh;
+            sz >>= sh;
+        }
+        bool near = ((unsigned)(sx - bx + 1) <= 2u) & ((unsigned)(sy - by + 1) <= 2u) & ((unsigned)(sz - bz + 1) <= 2u);
+        if (LEVEL) {
+            const bool parent_near = ((unsigned)((sx >> 1) - (bx >> 1) + 1) <= 2u) &
+                                     ((unsigned)((sy >> 1) - (by >> 1) + 1) <= 2u) &
+                                     ((unsigned)((sz >> 1) - (bz >> 1) + 1) <= 2u);
+            near = near | !parent_near;  // outside the interaction list: no contribution
+        }
         // for a near copy the weights are exactly zero; 1/|d| is taken as 1 so
         // that every factor stays finite (|d| may be 0), and the zero weights
         // then add exactly nothing
@@ -245,16 +265,84 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
     }
 }
 
-template <int P, int G = 0, class PD, class PF>
+template <int P, bool LEVEL = false, int G = 0, class PD, class PF>
 __device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const SweepSources &S, PD psi,
-                               PF psi32)
+                               PF psi32, int sh = 0)
 {
     if constexpr (G < n_groups(P)) {
         if (grp == G)
-            sweep_cols<P, group_m0(P, G), group_end(P, group_m0(P, G))>(g, M, cell, S, psi, psi32);
+            sweep_cols<P, group_m0(P, G), group_end(P, group_m0(P, G)), LEVEL>(g, M, cell, S, psi, psi32, sh);
         else
-            sweep_dispatch<P, G + 1>(grp, g, M, cell, S, psi, psi32);
+            sweep_dispatch<P, LEVEL, G + 1>(grp, g, M, cell, S, psi, psi32, sh);
     }
+}
+
+// Target t of a per-level commit: level lstart + t / (2 * 343), then the 7^3
+// block around the old (first) or new (second) endpoint's cell on that level.
+// A level with at most 7 cells per axis is enumerated once, cell by cell; the
+// new endpoint's block skips the cells of the old one's, so no cell is visited
+// twice and no two lanes write the same expansion.
+__device__ inline bool level_target(const Geo &g, const Move &mv, int64_t t, int &level, int64_t &cell)
+{
+    const int per = 2 * 343;
+    const int li = (int)(t / per);
+    if (li > g.L - g.lstart) return false;
+    level = g.lstart + li;
+    const int rem = (int)(t - (int64_t)li * per), e = rem / 343, d = rem % 343;
+    const int side = 1 << (level - 1), sh = g.L - level;
+    if (side <= 7) {
+        if (e == 1 || d >= side * side * side) return false;
+        cell = d;
+        return true;
+    }
+    const int ox = mv.ogx >> sh, oy = mv.ogy >> sh, oz = mv.ogz >> sh;
+    int bx = (e ? mv.ngx >> sh : ox) + d / 49 - 3, by = (e ? mv.ngy >> sh : oy) + (d / 7) % 7 - 3,
+        bz = (e ? mv.ngz >> sh : oz) + d % 7 - 3;
+    if (g.periodic) {
+        bx = posmod(bx, side);
+        by = posmod(by, side);
+        bz = posmod(bz, side);
+    } else if (bx < 0 || bx >= side || by < 0 || by >= side || bz < 0 || bz >= side) {
+        return false;
+    }
+    if (e == 1) {
+        auto dist = [&](int u, int v) {
+            if (!g.periodic) return abs(u - v);
+            const int w = posmod(u - v, side);
+            return w < side - w ? w : side - w;
+        };
+        if (dist(bx, ox) <= 3 && dist(by, oy) <= 3 && dist(bz, oz) <= 3) return false;
+    }
+    cell = cell_id(side, bx, by, bz);
+    return true;
+}
+
+__host__ __device__ inline int64_t level_targets(int L, int lstart) { return (int64_t)(L - lstart + 1) * 2 * 343; }
+
+// the per-level commit of one target (level, cell) and one column group
+template <int P, class PD, class PF>
+__device__ inline void levels_body(int grp, const Geo &gf, const Move &mv, const SweepSources &S, int64_t t,
+                                   PD const *psi_lv, PF psi32)
+{
+    int level;
+    int64_t cell;
+    if (!level_target(gf, mv, t, level, cell)) return;
+    Geo g = gf;
+    g.nc = 1 << (level - 1);
+    g.w = gf.a / g.nc;
+    const int64_t Ml = (int64_t)g.nc * g.nc * g.nc;
+    sweep_dispatch<P, true>(grp, g, Ml, cell, S, psi_lv[level], level == gf.L ? psi32 : (PF) nullptr,
+                            gf.L - level);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_levels(Geo g, Move mv, double *const *__restrict__ psi_lv,
+                                                float *__restrict__ psi32)
+{
+    __shared__ SweepSources S;
+    sweep_sources(g, mv, S);
+    __syncthreads();
+    levels_body<P>(blockIdx.y, g, mv, S, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, psi_lv, psi32);
 }
 
 template <int P>
@@ -398,8 +486,14 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a, hipStream_t
     mv.ngy = a.new_g[1];
     mv.ngz = a.new_g[2];
     float *p32 = c->prec == FMMKMC_MIXED ? c->psi32 : nullptr;
-    FMMKMC_DISPATCH_P(c->p, launch(c, "sweep", k_sweep<P_>, dim3((unsigned)((c->M + 255) / 256), n_groups(P_)),
-                                   dim3(256), g, c->M, mv, c->psi_lv[c->L], p32));
+    if (c->per_level) {
+        const int64_t nt_ = level_targets(g.L, g.lstart);
+        FMMKMC_DISPATCH_P(c->p, launch(c, "levels", k_levels<P_>, dim3((unsigned)((nt_ + 255) / 256), n_groups(P_)),
+                                       dim3(256), g, mv, (double *const *)c->d_psi_ptrs, p32));
+    } else {
+        FMMKMC_DISPATCH_P(c->p, launch(c, "sweep", k_sweep<P_>, dim3((unsigned)((c->M + 255) / 256), n_groups(P_)),
+                                       dim3(256), g, c->M, mv, c->psi_lv[c->L], p32));
+    }
     const int per = (c->p + 1) * (c->p + 2) / 2;
     launch_on(c, side, "path", k_path, dim3((c->L * per + 255) / 256), dim3(256), 0, g, c->L, c->p, mv,
               c->d_phi_ptrs);
@@ -449,6 +543,32 @@ __global__ __launch_bounds__(256) void k_b_sweep(const RepDev *__restrict__ reps
     using GD = __attribute__((address_space(1))) double;
     using GF = __attribute__((address_space(1))) float;
     sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, S, (GD *)d.psi, (GF *)d.psi32);
+}
+
+// per-level commit of every replica: nb blocks per replica
+template <int P>
+__global__ __launch_bounds__(256) void k_b_levels(const RepDev *__restrict__ reps, const MoveDev *__restrict__ moves,
+                                                  int nb)
+{
+    const int r = blockIdx.x / nb;
+    const MoveDev &mv = moves[r];
+    if (!mv.valid) return;  // uniform over the block
+    const RepDev &d = reps[r];
+    __shared__ SweepSources S;
+    sweep_sources(d.g, mv.mv, S);
+    __syncthreads();
+    using GD = __attribute__((address_space(1))) double;
+    using GF = __attribute__((address_space(1))) float;
+    levels_body<P>(blockIdx.y, d.g, mv.mv, S, (int64_t)(blockIdx.x % nb) * blockDim.x + threadIdx.x,
+                   (GD *const *)d.psi_lv, (GF *)d.psi32);
+}
+
+void launch_b_levels(Profiler &pr, hipStream_t st, const RepDev *reps, int R, int p, const MoveDev *moves, int Lmax,
+                     int lstart)
+{
+    const int nb = (int)((level_targets(Lmax, lstart) + 255) / 256);
+    FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_levels", k_b_levels<P_>, dim3((unsigned)(R * nb), n_groups(P_)),
+                                     dim3(256), 0, reps, moves, nb));
 }
 
 __global__ void k_b_path(const RepDev *__restrict__ reps, int R, const int64_t *__restrict__ base,

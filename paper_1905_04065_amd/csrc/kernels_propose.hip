@@ -22,6 +22,28 @@
 
 namespace fmmkmc {
 
+// ---- per-level expansions -------------------------------------------------
+
+// The levels above the fine one (per-level mode): sum over l = lstart .. L-1 of
+// Psi_l of the level-l cell holding the point, about that cell's centre.  The
+// cells are the fine cell's ancestors (fine coordinates shifted right), so the
+// assignment at cell faces is the fine level's.
+template <int P, class PP>
+__device__ inline double coarse_part(const Geo &g, PP psi_lv, double px, double py, double pz, int fx, int fy,
+                                     int fz)
+{
+    double s = 0.0;
+    for (int l = g.lstart; l < g.L; ++l) {
+        const int side = 1 << (l - 1), sh = g.L - l;
+        const double w = g.a / side;
+        const int cx = fx >> sh, cy = fy >> sh, cz = fz >> sh;
+        const int64_t Ml = (int64_t)side * side * side;
+        s += l2p<P, double>(psi_lv[l] + cell_id(side, cx, cy, cz), Ml, px - (cx + 0.5) * w, py - (cy + 0.5) * w,
+                            pz - (cz + 0.5) * w);
+    }
+    return s;
+}
+
 // ---- generic points ------------------------------------------------------
 
 // potential at arbitrary points: local expansion + near field (+ far field);
@@ -35,7 +57,8 @@ __global__ __launch_bounds__(256) void k_point_phi(Geo g, int64_t M, int64_t m, 
                                                    const double *__restrict__ x, const double *__restrict__ y,
                                                    const double *__restrict__ z, const double *__restrict__ q,
                                                    const int32_t *__restrict__ cnt,
-                                                   const int32_t *__restrict__ slots, double *__restrict__ out)
+                                                   const int32_t *__restrict__ slots, double *__restrict__ out,
+                                                   double *const *__restrict__ psi_lv)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m) return;
@@ -60,6 +83,7 @@ __global__ __launch_bounds__(256) void k_point_phi(Geo g, int64_t M, int64_t m, 
     } else {
         phi = l2p<P, double>(psi + cell, M, ux, uy, uz);
     }
+    if (g.per_level) phi += coarse_part<P>(g, psi_lv, px, py, pz, cx, cy, cz);
     // near field over the 27 neighbour cells
     double nearv = 0.0;
     float nearf = 0.0f;
@@ -108,11 +132,11 @@ void launch_point_phi(fmmkmc_ctx *c, const Geo &g, int64_t m, const double *xyz,
     if (c->prec == FMMKMC_MIXED && !fp64) {
         FMMKMC_DISPATCH_P(c->p, launch(c, name, k_point_phi<P_, true>, grid, dim3(256), g, c->M, m, xyz, pidx,
                                        exclude, c->psi_lv[c->L], c->psi32, c->far.H, with_far, c->x, c->y, c->z,
-                                       c->q, c->cell_cnt, c->cell_slots, out));
+                                       c->q, c->cell_cnt, c->cell_slots, out, (double *const *)c->d_psi_ptrs));
     } else {
         FMMKMC_DISPATCH_P(c->p, launch(c, name, k_point_phi<P_, false>, grid, dim3(256), g, c->M, m, xyz, pidx,
                                        exclude, c->psi_lv[c->L], c->psi32, c->far.H, with_far, c->x, c->y, c->z,
-                                       c->q, c->cell_cnt, c->cell_slots, out));
+                                       c->q, c->cell_cnt, c->cell_slots, out, (double *const *)c->d_psi_ptrs));
     }
 }
 
@@ -189,7 +213,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
                                                   const int32_t *__restrict__ cell_rng_,
                                                   const int32_t *__restrict__ site_rank_,
                                                   double *__restrict__ phisite_, double *__restrict__ phi_r_,
-                                                  unsigned char *smem)
+                                                  const double *__restrict__ phic_, unsigned char *smem)
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     constexpr InvSqrtTab IT{};
@@ -462,6 +486,7 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
     }
     if (!active) return;
     phi += nearv / g.h;
+    if (phic_) phi += as_global(phic_)[s];  // per-level mode: the coarser levels
     if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
     const int32_t rk = site_rank[s];
     if (rk >= 0) phi_r[rk] = phi;
@@ -482,11 +507,12 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
                                                           const float *__restrict__ qsite32,
                                                           const int32_t *__restrict__ cell_rng,
                                                           const int32_t *__restrict__ site_rank,
-                                                          double *__restrict__ phisite, double *__restrict__ phi_r)
+                                                          double *__restrict__ phisite, double *__restrict__ phi_r,
+                                                          const double *__restrict__ phic)
 {
     __shared__ __align__(16) unsigned char smem[gen_smem_bytes<MIXED>()];
     site_general_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, Bz, Tax, qsite, qsite32, cell_rng, site_rank,
-                                phisite, phi_r, smem);
+                                phisite, phi_r, phic, smem);
 }
 
 // ---- lattice with 2 x 2 x 2 sites per fine cell ----------------------------
@@ -589,7 +615,8 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
                                              const float *__restrict__ qsite32_,
                                              const int32_t *__restrict__ site_rank_, const double *__restrict__ Bz_,
                                              const double *__restrict__ Tax_, double *__restrict__ phisite_,
-                                             double *__restrict__ phi_r_, unsigned char *smem)
+                                             double *__restrict__ phi_r_, const double *__restrict__ phic_,
+                                             unsigned char *smem)
 {
     using Real = typename std::conditional<MIXED, float, double>::type;
     const auto psi = as_global(psi_), Bz = as_global(Bz_), Tax = as_global(Tax_), qsite = as_global(qsite_);
@@ -753,7 +780,8 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
     const int nsite = (int)((M - c0 < CELLS ? M - c0 : CELLS) * 8);
     for (int e = threadIdx.x; e < nsite; e += blockDim.x) {
         const int l = e >> 3, u = e & 7;
-        const double phi = sFar[l * 9 + u] + sNear[l * 9 + u];
+        double phi = sFar[l * 9 + u] + sNear[l * 9 + u];
+        if (phic_) phi += as_global(phic_)[c0 * 8 + e];  // per-level mode: the coarser levels
         const int32_t rk = site_rank[c0 * 8 + e];
         if (rk >= 0) phi_r[rk] = phi;
         phisite[c0 * 8 + e] = rk >= 0 ? __builtin_nan("") : phi;
@@ -767,11 +795,12 @@ __global__ __launch_bounds__(512) void k_site_phi_s2(Geo g, int64_t M, const dou
                                                      const float *__restrict__ qsite32,
                                                      const int32_t *__restrict__ site_rank,
                                                      const double *__restrict__ Bz, const double *__restrict__ Tax,
-                                                     double *__restrict__ phisite, double *__restrict__ phi_r)
+                                                     double *__restrict__ phisite, double *__restrict__ phi_r,
+                                                     const double *__restrict__ phic)
 {
     __shared__ __align__(16) unsigned char smem[s2_smem_bytes<MIXED, 8>()];
     site_s2_body<P, MIXED, 8>(blockIdx.x, g, M, psi, psi32, qsite, qsite32, site_rank, Bz, Tax, phisite, phi_r,
-                              smem);
+                              phic, smem);
 }
 
 void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
@@ -782,23 +811,155 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, true>, grid, dim3(512), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->qsite, c->qsite32, c->site_rank, c->far.Bz,
-                                           c->far.Tax, c->phisite, c->phi_r));
+                                           c->far.Tax, c->phisite, c->phi_r, c->phicoarse));
         } else {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi_s2", k_site_phi_s2<P_, false>, grid, dim3(512), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->qsite, c->qsite32, c->site_rank, c->far.Bz,
-                                           c->far.Tax, c->phisite, c->phi_r));
+                                           c->far.Tax, c->phisite, c->phi_r, c->phicoarse));
         }
     } else {
         dim3 grid((unsigned)general_site_blocks(c->lat_n));
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, true>, grid, dim3(256), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->qsite, c->qsite32,
-                                           c->cell_rng, c->site_rank, c->phisite, c->phi_r));
+                                           c->cell_rng, c->site_rank, c->phisite, c->phi_r, c->phicoarse));
         } else {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, false>, grid, dim3(256), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->qsite, c->qsite32,
-                                           c->cell_rng, c->site_rank, c->phisite, c->phi_r));
+                                           c->cell_rng, c->site_rank, c->phisite, c->phi_r, c->phicoarse));
         }
+    }
+}
+
+// ---- per-level mode: the coarser levels at every lattice site ----------------
+//
+// phicoarse[s] = sum over l = lstart .. L-1 of Psi_l at site s (site order of
+// the site kernels).  Any lattice: one lane per site, every coarse level.
+
+template <int P>
+__device__ inline void coarse_site_body(const Geo &g, double *const *psi_lv, int64_t s, int s2,
+                                        double *__restrict__ phic)
+{
+    const int n = g.n;
+    const int64_t ns = (int64_t)n * n * n;
+    if (s >= ns) return;
+    const int i = (int)(s / ((int64_t)n * n)), j = (int)((s / n) % n), k = (int)(s % n);
+    const double px = (i + 0.5) * g.h, py = (j + 0.5) * g.h, pz = (k + 0.5) * g.h;
+    const int fx = fine_coord(px, g.w, g.nc), fy = fine_coord(py, g.w, g.nc), fz = fine_coord(pz, g.w, g.nc);
+    const double v = coarse_part<P>(g, psi_lv, px, py, pz, fx, fy, fz);
+    phic[s2 ? s2_site(g.nc, i, j, k) : s] = v;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_coarse_sites(Geo g, double *const *__restrict__ psi_lv, int s2,
+                                                      double *__restrict__ phic)
+{
+    coarse_site_body<P>(g, psi_lv, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, s2, phic);
+}
+
+// 2 x 2 x 2 sites per fine cell: a level-l cell holds W = 2^(L-l+1) sites per
+// axis, symmetric about its centre, so its sites fall into orbits of 8 under
+// the reflections x, y, z -> -x, -y, -z about the centre.  Reflecting maps
+// R_n^m to (-1)^m conj(R_n^m) (x), conj(R_n^m) (y) and (-1)^(n+m) R_n^m (z), so
+// the 8 values of an orbit are signed sums of 8 class sums of one set of
+// regular harmonics (classes: n+m parity, m parity, real or imaginary part).
+// One lane per (level-l cell, orbit); the orbit's base offset is
+// ((bx + 1/2) h, (by + 1/2) h, (bz + 1/2) h), bx, by, bz in [0, W/2).  The
+// first level launched writes, the others add.
+template <int P>
+__global__ __launch_bounds__(256) void k_coarse_s2(Geo g, int level, const double *__restrict__ psi, int first,
+                                                   double *__restrict__ phic)
+{
+    const int side = 1 << (level - 1), sh = g.L - level;
+    const int Hh = 1 << sh;  // W / 2 = 2^(L-l)
+    const int64_t orbits = (int64_t)Hh * Hh * Hh, Ml = (int64_t)side * side * side;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Ml * orbits) return;
+    const int64_t cell = t / orbits;
+    const int b = (int)(t - cell * orbits);
+    const int bx = b / (Hh * Hh), by = (b / Hh) % Hh, bz = b % Hh;
+    const int cx = (int)(cell / ((int64_t)side * side)), cy = (int)((cell / side) % side), cz = (int)(cell % side);
+    const double x = (bx + 0.5) * g.h, y = (by + 0.5) * g.h, z = (bz + 0.5) * g.h;
+    const double r2 = x * x + y * y + z * z;
+    const auto L = psi + cell;
+    // class sums S[A][B][C]: A = (n + m) & 1, B = m & 1, C = 0 real / 1 imaginary part
+    double S[2][2][2] = {};
+    {  // m = 0 column
+        double cm2 = 1.0, cm1 = z;
+        S[0][0][0] += L[0];
+        if (P >= 1) S[1][0][0] += L[(int64_t)slot0(1) * Ml] * z;
+#pragma unroll
+        for (int nn = 2; nn <= P; ++nn) {
+            const double c = ((2 * nn - 1) * z * cm1 - r2 * cm2) * rinv(nn, 0);
+            S[nn & 1][0][0] += L[(int64_t)slot0(nn) * Ml] * c;
+            cm2 = cm1;
+            cm1 = c;
+        }
+    }
+    double dr = 1.0, di = 0.0;
+#pragma unroll
+    for (int m = 1; m <= P; ++m) {
+        const double f = -0.5 / m;
+        const double ndr = f * (x * dr - y * di), ndi = f * (x * di + y * dr);
+        dr = ndr;
+        di = ndi;
+        double ar = dr, ai = di;
+        const int B = m & 1;
+        S[0][B][0] += 2.0 * L[(int64_t)slot_re(m, m) * Ml] * ar;  // n = m: n + m even
+        S[0][B][1] += 2.0 * L[(int64_t)slot_im(m, m) * Ml] * ai;
+        if (m + 1 <= P) {
+            double br = z * ar, bi = z * ai;
+            S[1][B][0] += 2.0 * L[(int64_t)slot_re(m + 1, m) * Ml] * br;
+            S[1][B][1] += 2.0 * L[(int64_t)slot_im(m + 1, m) * Ml] * bi;
+#pragma unroll
+            for (int nn = m + 2; nn <= P; ++nn) {
+                const double w = rinv(nn, m);
+                const double cr = ((2 * nn - 1) * z * br - r2 * ar) * w, ci = ((2 * nn - 1) * z * bi - r2 * ai) * w;
+                const int A = (nn + m) & 1;
+                S[A][B][0] += 2.0 * L[(int64_t)slot_re(nn, m) * Ml] * cr;
+                S[A][B][1] += 2.0 * L[(int64_t)slot_im(nn, m) * Ml] * ci;
+                ar = br;
+                ai = bi;
+                br = cr;
+                bi = ci;
+            }
+        }
+    }
+    const int W = 2 * Hh;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int fx = (u >> 2) & 1, fy = (u >> 1) & 1, fz = u & 1;  // 1: the reflected side
+        double v = 0.0;
+#pragma unroll
+        for (int A = 0; A < 2; ++A)
+#pragma unroll
+            for (int B = 0; B < 2; ++B) {
+                const double sz = (fz && A) ? -1.0 : 1.0;
+                const double sre = sz * ((fx && B) ? -1.0 : 1.0);
+                const double sim = sz * ((fx && !B) ? -1.0 : 1.0) * (fy ? -1.0 : 1.0);
+                v += sre * S[A][B][0] + sim * S[A][B][1];
+            }
+        const int i = cx * W + Hh + (fx ? -1 - bx : bx), j = cy * W + Hh + (fy ? -1 - by : by),
+                  k = cz * W + Hh + (fz ? -1 - bz : bz);
+        const int64_t at = s2_site(g.nc, i, j, k);
+        phic[at] = first ? v : phic[at] + v;
+    }
+}
+
+void launch_coarse_sites(fmmkmc_ctx *c, const Geo &g)
+{
+    if (!c->per_level || !c->phicoarse) return;  // no coarser level with an interaction list
+    const int lstart = g.lstart;
+    if (c->s2) {
+        const int64_t orbits = (int64_t)c->lat_n * c->lat_n * c->lat_n / 8;  // per level
+        for (int l = g.L - 1; l >= lstart; --l)
+            FMMKMC_DISPATCH_P(c->p, launch(c, "coarse_s2", k_coarse_s2<P_>, dim3((unsigned)((orbits + 255) / 256)),
+                                           dim3(256), g, l, (const double *)c->psi_lv[l], l == g.L - 1 ? 1 : 0,
+                                           c->phicoarse));
+    } else {
+        const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+        FMMKMC_DISPATCH_P(c->p, launch(c, "coarse_sites", k_coarse_sites<P_>, dim3((unsigned)((ns + 255) / 256)),
+                                       dim3(256), g, (double *const *)c->d_psi_ptrs, 0, c->phicoarse));
     }
 }
 
@@ -1164,7 +1325,7 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
                                              const double *__restrict__ z, const double *__restrict__ q,
                                              const int32_t *__restrict__ cnt, const int32_t *__restrict__ slots,
                                              const double *__restrict__ R, const double *__restrict__ H,
-                                             double *__restrict__ out)
+                                             double *__restrict__ out, double *const *__restrict__ psi_lv)
 {
     const int nt = nterms(p);
     extern __shared__ double sm[];
@@ -1192,6 +1353,17 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
         const int64_t tcell = cell_id(g.nc, tcx, tcy, tcz), rcell = cell_id(g.nc, rcx, rcy, rcz);
         for (int k = threadIdx.x; k < nt; k += blockDim.x)
             part += qi * (psi[(int64_t)k * M + tcell] * Wa[k] - psi[(int64_t)k * M + rcell] * Wb[k]);
+        // per-level mode: the coarser levels at both endpoints, one lane per level and endpoint
+        if (g.per_level && (int)threadIdx.x < 2 * (g.L - g.lstart)) {
+            const int e = threadIdx.x & 1, l = g.lstart + (int)(threadIdx.x >> 1);
+            const int side = 1 << (l - 1), sh = g.L - l;
+            const double w = g.a / side;
+            const double px = e ? rx : tx, py = e ? ry : ty, pz = e ? rz : tz;
+            const int cx = (e ? rcx : tcx) >> sh, cy = (e ? rcy : tcy) >> sh, cz = (e ? rcz : tcz) >> sh;
+            const double v = l2p_runtime(p, psi_lv[l] + cell_id(side, cx, cy, cz), (int64_t)side * side * side,
+                                         px - (cx + 0.5) * w, py - (cy + 0.5) * w, pz - (cz + 0.5) * w);
+            part += e ? -qi * v : qi * v;
+        }
         // self terms: one copy nu of the old position per lane, or the exact
         // self-image change with its Ewald terms split over the block
         if (g.periodic && g.self_exact) {
@@ -1296,9 +1468,10 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
                                                  const double *__restrict__ y, const double *__restrict__ z,
                                                  const double *__restrict__ q, const int32_t *__restrict__ cnt,
                                                  const int32_t *__restrict__ slots, const double *__restrict__ R,
-                                                 const double *__restrict__ H, double *__restrict__ out, int part0)
+                                                 const double *__restrict__ H, double *__restrict__ out, int part0,
+                                                 double *const *__restrict__ psi_lv)
 {
-    move_dU_body(part0 + (int)blockIdx.x, g, p, M, i, tx, ty, tz, psi, x, y, z, q, cnt, slots, R, H, out);
+    move_dU_body(part0 + (int)blockIdx.x, g, p, M, i, tx, ty, tz, psi, x, y, z, q, cnt, slots, R, H, out, psi_lv);
 }
 
 void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out, hipStream_t st,
@@ -1307,7 +1480,7 @@ void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], d
     const size_t shm = sizeof(double) * (4 * c->nt + 256);
     launch_on(c, st ? st : c->stream, part0 == 0 ? "move_dU" : "move_dU_side", k_move_dU, dim3(nparts), dim3(256),
               shm, g, c->p, c->M, i, t[0], t[1], t[2], c->psi_lv[c->L], c->x, c->y, c->z, c->q, c->cell_cnt,
-              c->cell_slots, c->far.R, c->far.H, out, part0);
+              c->cell_slots, c->far.R, c->far.H, out, part0, (double *const *)c->d_psi_ptrs);
 }
 
 // ---- generic proposals ----------------------------------------------------
@@ -1529,10 +1702,10 @@ __global__ __launch_bounds__(256) void k_b_site(const RepDev *__restrict__ reps,
     const int64_t blk = blockIdx.x - base[r];
     if (d.s2)
         site_s2_body<P, MIXED, 4>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
-                                  d.phisite, d.phi_r, smem);
+                                  d.phisite, d.phi_r, d.phicoarse, smem);
     else
         site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.qsite, d.qsite32, d.cell_rng,
-                                    d.site_rank, d.phisite, d.phi_r, smem);
+                                    d.site_rank, d.phisite, d.phi_r, d.phicoarse, smem);
 }
 
 template <int TC>
@@ -1555,7 +1728,7 @@ __global__ __launch_bounds__(256) void k_b_move_dU(const RepDev *__restrict__ re
     if (!mv.valid) return;
     const RepDev &d = reps[r];
     move_dU_body(part, d.g, d.p, d.M, mv.i, mv.t[0], mv.t[1], mv.t[2], d.psi, d.x, d.y, d.z, d.q, d.cnt, d.slots,
-                 d.R, d.H, acc + (int64_t)r * kMoveParts);
+                 d.R, d.H, acc + (int64_t)r * kMoveParts, d.psi_lv);
 }
 
 // the moved charge's F row, one block per replica (periodic replicas)
@@ -1566,6 +1739,24 @@ __global__ __launch_bounds__(256) void k_b_frow(const RepDev *__restrict__ reps,
     const RepDev &d = reps[r];
     if (!mv.valid || !d.F) return;
     f_row1_body(d.g, d.p, mv.rank, mv.new_site, d.K, d.offsets, d.R, d.sigma, d.F);
+}
+
+// per-level mode: the coarser levels at every site of every replica, one lane per site
+template <int P>
+__global__ __launch_bounds__(256) void k_b_coarse(const RepDev *__restrict__ reps, int R,
+                                                  const int64_t *__restrict__ base)
+{
+    const int r = find_rep(base, R, blockIdx.x);
+    const RepDev &d = reps[r];
+    if (!d.phicoarse) return;
+    coarse_site_body<P>(d.g, d.psi_lv, (blockIdx.x - base[r]) * (int64_t)blockDim.x + threadIdx.x, d.s2, d.phicoarse);
+}
+
+void launch_b_coarse(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                     int p)
+{
+    FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_coarse", k_b_coarse<P_>, dim3((unsigned)blocks), dim3(256), 0, reps,
+                                     R, base));
 }
 
 void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,

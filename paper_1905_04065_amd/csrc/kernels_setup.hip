@@ -271,8 +271,10 @@ void launch_downward(fmmkmc_ctx *c)
         const int nc = 1 << (l - 1);
         const int64_t Mh = (int64_t)(nc / 2) * (nc / 2) * (nc / 2);
         const double *sin_ = c->scale + (int64_t)(2 * l) * c->nt, *sout = c->scale + (int64_t)(2 * l + 1) * c->nt;
-        const double *par = l > start ? c->psi_lv[l - 1] : nullptr;
-        const int wp = l > start ? 1 : 0, per = c->bc == FMMKMC_PERIODIC ? 1 : 0;
+        // per-level expansions keep each level's own interaction-list terms (no L2L from the parent)
+        const bool from_parent = l > start && !c->per_level;
+        const double *par = from_parent ? c->psi_lv[l - 1] : nullptr;
+        const int wp = from_parent ? 1 : 0, per = c->bc == FMMKMC_PERIODIC ? 1 : 0;
         if (c->nt <= 196) {  // p <= 13: 32 cells per block, <= 50 KB of LDS
             constexpr int C = 32;
             launch_shm(c, "m2l", k_m2l<C, 1>, dim3((unsigned)((Mh + C - 1) / C), 8), dim3(256),

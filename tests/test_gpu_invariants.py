@@ -54,9 +54,9 @@ def moves(sites, n, count, seed, periodic):
             if s % 2 == 0:
                 t, v = O.lattice_targets(cur[i:i + 1], n, W.HOPS6, periodic)
                 k = int(rng.integers(6))
-                if not v[0, k]:
-                    continue
                 new = int(t[0, k])
+                if not v[0, k] or new in occ:  # off the lattice, or onto another charge
+                    continue
             else:
                 new = int(rng.integers(n ** 3))
                 if new in occ:
