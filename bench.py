@@ -532,6 +532,9 @@ def main():
         pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, self_image="exact") for pr in precs}
     res_levels = {} if args.skip_per_level else {
         pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, per_level=True) for pr in precs}
+    res_both = {} if (args.skip_per_level or args.skip_exact_self) else {
+        pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, per_level=True, self_image="exact")
+        for pr in precs}
     copy_gbs = copy_bandwidth()
     if args.copy_calibration:
         copy_bandwidth(1 << 30, reps=3)
@@ -539,7 +542,7 @@ def main():
     slots = N * K
 
     def summary(pr, exact=False, levels=False):
-        r = (res_levels if levels else res_exact if exact else res)[pr]
+        r = (res_both if (levels and exact) else res_levels if levels else res_exact if exact else res)[pr]
         kt = r["kernels"]
         traffic = {} if (exact or levels) else profiled_traffic(tag, pr)
         roof = {k: roofline_entry(k, kt, n, N, K, p, pr, copy_gbs, traffic, exact)
@@ -618,6 +621,15 @@ def main():
                 "note": "per_level=1: local expansions kept per level; an accept updates the interaction-list cells "
                         "of each level (k_levels) instead of every fine cell (k_sweep); proposals add the coarser "
                         "levels per site (k_coarse_s2)"}
+    if res_both:
+        out["per_level_exact_self_image"] = {}
+        for pr in precs:
+            m = summary(pr, exact=True, levels=True)
+            out["per_level_exact_self_image"][pr] = {
+                "value": m["value"], "ms_per_step": m["ms_per_step"], "host_driven_ms_per_step": m["host_driven_ms_per_step"],
+                "propose_us": m["propose_us"], "commit_us": m["commit_us"], "setup_s": m["setup_s"],
+                "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"],
+                "note": "per_level=1 and self_image=1 together"}
     if not args.skip_batch:
         out["batched"] = batched_summary(args)
         out["slab"] = run_slab(max(args.steps, 5), args.warmup, W.BASE_SEED + 6)

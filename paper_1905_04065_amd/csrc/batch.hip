@@ -421,6 +421,7 @@ struct fmmkmc_batch {
     int cap_steps = 0;
     // phases
     Phase site, slot, count, sweep, path, far, cheb_a, cheb_b, coarse;
+    std::vector<Phase> coarse_s2;  // per depth below the fine level (2x2x2 replicas)
     int slot_tc = 64, sweep_block = 256;
     bool per_level = false;  // replicas keep their local expansions per level (no sweep)
     int Lmax = 0;
@@ -477,7 +478,11 @@ void record_step(fmmkmc_batch *b)
 {
     const hipStream_t s = b->stream;
     const int R = b->R;
-    if (b->per_level) launch_b_coarse(b->prof, s, b->reps, R, b->coarse.d, b->coarse.blocks, b->p);
+    if (b->per_level) {
+        launch_b_coarse(b->prof, s, b->reps, R, b->coarse.d, b->coarse.blocks, b->p);
+        for (int dpt = 0; dpt < (int)b->coarse_s2.size(); ++dpt)
+            launch_b_coarse_s2(b->prof, s, b->reps, R, b->coarse_s2[dpt].d, b->coarse_s2[dpt].blocks, b->p, dpt);
+    }
     launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->p, b->mixed);
     launch_b_slot(b->prof, s, b->reps, R, b->slot.d, b->slot.blocks, b->slot_tc);
     launch_prof(b->prof, s, "b_count", k_b_count, dim3((unsigned)b->count.blocks), dim3(256), 0, b->reps, R,
@@ -485,7 +490,7 @@ void record_step(fmmkmc_batch *b)
     launch_prof(b->prof, s, "b_select", k_b_select, dim3((unsigned)R), dim3(256), 0, b->reps, R, b->count.d,
                 b->wsum, b->rates, b->u, b->step, b->moves, b->Q);
     // the part of the move's dU that reads the fine-level expansions, before the sweep
-    launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt, 0, 1);
+    launch_b_move_dU(b->prof, s, b->reps, R, b->moves, b->acc, b->nt, 0, 1, b->per_level ? b->Lmax - 1 : 1);
     // beside the sweep, on the side stream: the rest of the move's dU (cell
     // lists and far-field tables, before the bookkeeping and the far-field
     // update change them), the F rows (they depend only on the moves), the
@@ -493,7 +498,7 @@ void record_step(fmmkmc_batch *b)
     // the fine-level expansions or what the sweep reads
     HIPCHK(hipEventRecord(b->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
-    launch_b_move_dU(b->prof, b->aux, b->reps, R, b->moves, b->acc, b->nt, 1, kMoveParts - 1);
+    launch_b_move_dU(b->prof, b->aux, b->reps, R, b->moves, b->acc, b->nt, 1, kMoveParts - 1, 1);
     launch_b_frow(b->prof, b->aux, b->reps, R, b->moves, b->nt, b->K);
     launch_b_path(b->prof, b->aux, b->reps, R, b->path.d, b->path.blocks, b->moves);
     launch_b_book(b->prof, b->aux, b->reps, R, b->moves);
@@ -578,6 +583,7 @@ void release_batch(fmmkmc_batch *b)
     dfree(b->out_site);
     dfree(b->out_dU);
     dfree(b->out_dt);
+    for (Phase &ph : b->coarse_s2) dfree(ph.d);
     for (Phase *ph : {&b->site, &b->slot, &b->count, &b->sweep, &b->path, &b->far, &b->cheb_a, &b->cheb_b,
                       &b->coarse})
         dfree(ph->d);
@@ -785,9 +791,23 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             nfar[r] = per ? (c->nt + c->far.ncz + 15) / 16 : 0;
             na[r] = per ? ((int64_t)c->lat_n * q * q + 255) / 256 : 0;
             nb[r] = per ? ((int64_t)c->lat_n * c->lat_n * q + 255) / 256 : 0;
-            ncoarse[r] = c->phicoarse ? (ns + 255) / 256 : 0;
+            ncoarse[r] = (c->phicoarse && !c->s2) ? (ns + 255) / 256 : 0;
         }
         set_phase(b->coarse, ncoarse, s);
+        if (b->per_level) {
+            // 2x2x2 replicas: levels L_r - 1 down to 2, one phase per depth
+            const int depths = b->Lmax - 1 - 2 + 1;
+            b->coarse_s2.assign(std::max(depths, 0), Phase{});
+            for (int dpt = 0; dpt < (int)b->coarse_s2.size(); ++dpt) {
+                std::vector<int64_t> nc2(n, 0);
+                for (int r = 0; r < n; ++r) {
+                    const fmmkmc_ctx *c = ctx[r];
+                    const int level = c->L - 1 - dpt, lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
+                    if (c->phicoarse && c->s2 && level >= lstart) nc2[r] = coarse_s2_level_blocks(c->L, level);
+                }
+                set_phase(b->coarse_s2[dpt], nc2, s);
+            }
+        }
         set_phase(b->site, nsite, s);
         set_phase(b->count, ncount, s);
         set_phase(b->path, npath, s);

@@ -79,8 +79,10 @@ void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, cons
 void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                    int tc);
 // parts [part0, part0 + nparts) of every replica's move dU
+// nlev_max: the most levels any replica evaluates in the dU of its move (1, or
+// L - 1 in per-level mode)
 void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, double *acc,
-                      int nt, int part0, int nparts);
+                      int nt, int part0, int nparts, int nlev_max);
 size_t f_row1_shm(int nt, int K);
 void launch_b_frow(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, int nt, int K);
 void launch_b_sweep(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
@@ -93,6 +95,11 @@ void launch_b_levels(Profiler &pr, hipStream_t st, const RepDev *reps, int R, in
 // per-level mode: the coarse levels' potential at every site of every replica
 void launch_b_coarse(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                      int p);
+// ... on 2x2x2 lattices, the orbit kernel for level L_r - 1 - depth of every replica
+void launch_b_coarse_s2(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                        int p, int depth);
+// blocks of the orbit kernel for one level of a 2x2x2 lattice with L levels
+int64_t coarse_s2_level_blocks(int L, int level);
 void launch_b_book(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves);
 void launch_b_far(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base_far,
                   int64_t blocks_far, const int64_t *base_a, int64_t blocks_a, const int64_t *base_b,

@@ -175,6 +175,9 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
                                      ((unsigned)((sy >> 1) - (by >> 1) + 1) <= 2u) &
                                      ((unsigned)((sz >> 1) - (bz >> 1) + 1) <= 2u);
             near = near | !parent_near;  // outside the interaction list: no contribution
+            // most copies lie in no target's interaction list on the finer levels:
+            // skip a copy that no lane of the wave takes (a wave-uniform branch)
+            if (!__any(!near)) continue;
         }
         // for a near copy the weights are exactly zero; 1/|d| is taken as 1 so
         // that every factor stays finite (|d| may be 0), and the zero weights

@@ -16,6 +16,8 @@
 // and the per-slot kernel only gathers; the hop-dependent but
 // charge-configuration-independent terms (self terms and the quadratic far-field
 // term) are tabulated per charge and hop in F.
+#include <string>
+
 #include "batch.hpp"
 #include "ewald.hpp"
 #include "kernels.hpp"
@@ -636,6 +638,15 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
         sT[e] = (Real)IS.v[s2_d2(u, nb, v)];
     }
     __syncthreads();
+    // per-level mode: this thread's sites' coarse-level sums, loaded now so that
+    // their latency hides behind the work below
+    constexpr int PER = CELLS * 8 / (64 * NW);
+    double pcv[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int64_t e = threadIdx.x + (int64_t)t * blockDim.x;
+        pcv[t] = (phic_ && blk * CELLS * 8 + e < M * 8) ? as_global(phic_)[blk * CELLS * 8 + e] : 0.0;
+    }
     const int wave = threadIdx.x >> 6;
     static_assert(NW == 4 || NW == 8, "4 or 8 waves per block");
     const bool class_wave = wave < 2 || (NW == 8 && wave >= 6);
@@ -778,10 +789,12 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
     }
     __syncthreads();
     const int nsite = (int)((M - c0 < CELLS ? M - c0 : CELLS) * 8);
-    for (int e = threadIdx.x; e < nsite; e += blockDim.x) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = threadIdx.x + t * blockDim.x;
+        if (e >= nsite) break;
         const int l = e >> 3, u = e & 7;
-        double phi = sFar[l * 9 + u] + sNear[l * 9 + u];
-        if (phic_) phi += as_global(phic_)[c0 * 8 + e];  // per-level mode: the coarser levels
+        const double phi = sFar[l * 9 + u] + sNear[l * 9 + u] + pcv[t];  // + the coarser levels (per-level mode)
         const int32_t rk = site_rank[c0 * 8 + e];
         if (rk >= 0) phi_r[rk] = phi;
         phisite[c0 * 8 + e] = rk >= 0 ? __builtin_nan("") : phi;
@@ -864,36 +877,115 @@ __global__ __launch_bounds__(256) void k_coarse_sites(Geo g, double *const *__re
 // the 8 values of an orbit are signed sums of 8 class sums of one set of
 // regular harmonics (classes: n+m parity, m parity, real or imaginary part).
 // One lane per (level-l cell, orbit); the orbit's base offset is
-// ((bx + 1/2) h, (by + 1/2) h, (bz + 1/2) h), bx, by, bz in [0, W/2).  The
-// first level launched writes, the others add.
-template <int P>
-__global__ __launch_bounds__(256) void k_coarse_s2(Geo g, int level, const double *__restrict__ psi, int first,
-                                                   double *__restrict__ phic)
+// ((bx + 1/2) h, (by + 1/2) h, (bz + 1/2) h), bx, by, bz in [0, W/2).  A block
+// covers whole cells (or a part of one cell's orbits) and first stages their
+// coefficients in LDS with coalesced loads.  The first level launched writes,
+// the others add.
+// 128 lanes per block: one cell's orbits in chunks of 128, or 128 / orbits whole
+// cells (their staged coefficients then take at most 16 x (p+1)^2 doubles)
+constexpr int kCoarseThreads = 128;
+__host__ __device__ inline int coarse_cells_per_block(int64_t orbits)
 {
+    return orbits >= kCoarseThreads ? 1 : (int)(kCoarseThreads / orbits);
+}
+
+// Regular harmonics carried rescaled along each column m: R_n^m = c_n Q_n with
+// c_m = c_{m+1} = 1 and c_n = c_{n-2} / ((n+m)(n-m)), so the three-term step
+// becomes Q_n = (g_n z) Q_{n-1} - r^2 Q_{n-2} with g_n = (2n-1) c_{n-1} / c_{n-2}
+// (one multiply shared by the real and imaginary parts, then a multiply and a
+// fused multiply-add each).  stage[k] folds c_n^m and the factor 2 of the
+// m > 0 terms into the coefficients when they are staged.
+template <int P>
+struct ScaledRegular {
+    double g[P + 1][P + 1];
+    double stage[(P + 1) * (P + 1)];
+    constexpr ScaledRegular() : g{}, stage{}
+    {
+        for (int m = 0; m <= P; ++m) {
+            double c2 = 1.0, c1 = 1.0;  // c_{n-2}, c_{n-1}
+            for (int n = m; n <= P; ++n) {
+                double cn = 1.0;
+                if (n >= m + 2) {
+                    cn = c2 / (double)((n + m) * (n - m));
+                    g[n][m] = (double)(2 * n - 1) * c1 / c2;
+                }
+                const double f = m > 0 ? 2.0 : 1.0;
+                if (m == 0) {
+                    stage[n * n] = cn * f;
+                } else {
+                    stage[n * n + 2 * m - 1] = cn * f;
+                    stage[n * n + 2 * m] = cn * f;
+                }
+                c2 = c1;
+                c1 = cn;
+            }
+        }
+    }
+};
+
+template <int P>
+__device__ inline void coarse_s2_body(const Geo &g, int level, const double *__restrict__ psi, int first,
+                                      double *__restrict__ phic, int64_t blk, double *sL)
+{
+    constexpr int NT = (P + 1) * (P + 1);
+    constexpr ScaledRegular<P> SR{};
     const int side = 1 << (level - 1), sh = g.L - level;
     const int Hh = 1 << sh;  // W / 2 = 2^(L-l)
     const int64_t orbits = (int64_t)Hh * Hh * Hh, Ml = (int64_t)side * side * side;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Ml * orbits) return;
-    const int64_t cell = t / orbits;
-    const int b = (int)(t - cell * orbits);
-    const int bx = b / (Hh * Hh), by = (b / Hh) % Hh, bz = b % Hh;
+    const int C = coarse_cells_per_block(orbits);
+    int64_t cell0, o0;
+    if (C > 1) {
+        cell0 = blk * C;
+        o0 = 0;
+    } else {
+        const int64_t chunks = orbits / kCoarseThreads;
+        cell0 = blk / chunks;
+        o0 = (blk - cell0 * chunks) * kCoarseThreads;
+    }
+    for (int e = threadIdx.x; e < C * NT; e += blockDim.x) {
+        const int k = e / C, c = e - k * C;
+        sL[c * NT + k] = cell0 + c < Ml ? psi[(int64_t)k * Ml + cell0 + c] * SR.stage[k] : 0.0;
+    }
+    __syncthreads();
+    const int cl = C > 1 ? (int)(threadIdx.x / orbits) : 0;
+    const int64_t cell = cell0 + cl;
+    if (cell >= Ml) return;
+    // orbit b: its low three bits are the parities of (bx, by, bz), so for each
+    // reflection eight consecutive lanes write the eight sites of one fine cell
+    // (64 contiguous bytes) and a wave writes eight z-consecutive fine cells
+    const int b = (int)(C > 1 ? threadIdx.x - cl * orbits : o0 + threadIdx.x);
+    const int h2 = Hh >> 1, q = b >> 3;
+    const int bx = 2 * (q / (h2 * h2)) + ((b >> 2) & 1), by = 2 * ((q / h2) % h2) + ((b >> 1) & 1),
+              bz = 2 * (q % h2) + (b & 1);
     const int cx = (int)(cell / ((int64_t)side * side)), cy = (int)((cell / side) % side), cz = (int)(cell % side);
     const double x = (bx + 0.5) * g.h, y = (by + 0.5) * g.h, z = (bz + 0.5) * g.h;
-    const double r2 = x * x + y * y + z * z;
-    const auto L = psi + cell;
+    const double nr2 = -(x * x + y * y + z * z);
+    const double *L = sL + cl * NT;
+    // the orbit's eight sites, and (after the first level) their running sums,
+    // loaded before the arithmetic so the loads overlap it
+    const int W = 2 * Hh;
+    int64_t at[8];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int fx = (u >> 2) & 1, fy = (u >> 1) & 1, fz = u & 1;  // 1: the reflected side
+        const int i = cx * W + Hh + (fx ? -1 - bx : bx), j = cy * W + Hh + (fy ? -1 - by : by),
+                  k = cz * W + Hh + (fz ? -1 - bz : bz);
+        at[u] = s2_site(g.nc, i, j, k);
+        v[u] = first ? 0.0 : phic[at[u]];
+    }
     // class sums S[A][B][C]: A = (n + m) & 1, B = m & 1, C = 0 real / 1 imaginary part
     double S[2][2][2] = {};
     {  // m = 0 column
-        double cm2 = 1.0, cm1 = z;
-        S[0][0][0] += L[0];
-        if (P >= 1) S[1][0][0] += L[(int64_t)slot0(1) * Ml] * z;
+        double q2 = 1.0, q1 = z;
+        S[0][0][0] = L[0];
+        if (P >= 1) S[1][0][0] = L[slot0(1)] * z;
 #pragma unroll
         for (int nn = 2; nn <= P; ++nn) {
-            const double c = ((2 * nn - 1) * z * cm1 - r2 * cm2) * rinv(nn, 0);
-            S[nn & 1][0][0] += L[(int64_t)slot0(nn) * Ml] * c;
-            cm2 = cm1;
-            cm1 = c;
+            const double qn = fma(SR.g[nn][0] * z, q1, nr2 * q2);
+            S[nn & 1][0][0] = fma(L[slot0(nn)], qn, S[nn & 1][0][0]);
+            q2 = q1;
+            q1 = qn;
         }
     }
     double dr = 1.0, di = 0.0;
@@ -905,19 +997,19 @@ __global__ __launch_bounds__(256) void k_coarse_s2(Geo g, int level, const doubl
         di = ndi;
         double ar = dr, ai = di;
         const int B = m & 1;
-        S[0][B][0] += 2.0 * L[(int64_t)slot_re(m, m) * Ml] * ar;  // n = m: n + m even
-        S[0][B][1] += 2.0 * L[(int64_t)slot_im(m, m) * Ml] * ai;
+        S[0][B][0] = fma(L[slot_re(m, m)], ar, S[0][B][0]);  // n = m: n + m even
+        S[0][B][1] = fma(L[slot_im(m, m)], ai, S[0][B][1]);
         if (m + 1 <= P) {
             double br = z * ar, bi = z * ai;
-            S[1][B][0] += 2.0 * L[(int64_t)slot_re(m + 1, m) * Ml] * br;
-            S[1][B][1] += 2.0 * L[(int64_t)slot_im(m + 1, m) * Ml] * bi;
+            S[1][B][0] = fma(L[slot_re(m + 1, m)], br, S[1][B][0]);
+            S[1][B][1] = fma(L[slot_im(m + 1, m)], bi, S[1][B][1]);
 #pragma unroll
             for (int nn = m + 2; nn <= P; ++nn) {
-                const double w = rinv(nn, m);
-                const double cr = ((2 * nn - 1) * z * br - r2 * ar) * w, ci = ((2 * nn - 1) * z * bi - r2 * ai) * w;
+                const double gz = SR.g[nn][m] * z;
+                const double cr = fma(gz, br, nr2 * ar), ci = fma(gz, bi, nr2 * ai);
                 const int A = (nn + m) & 1;
-                S[A][B][0] += 2.0 * L[(int64_t)slot_re(nn, m) * Ml] * cr;
-                S[A][B][1] += 2.0 * L[(int64_t)slot_im(nn, m) * Ml] * ci;
+                S[A][B][0] = fma(L[slot_re(nn, m)], cr, S[A][B][0]);
+                S[A][B][1] = fma(L[slot_im(nn, m)], ci, S[A][B][1]);
                 ar = br;
                 ai = bi;
                 br = cr;
@@ -925,11 +1017,10 @@ __global__ __launch_bounds__(256) void k_coarse_s2(Geo g, int level, const doubl
             }
         }
     }
-    const int W = 2 * Hh;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const int fx = (u >> 2) & 1, fy = (u >> 1) & 1, fz = u & 1;  // 1: the reflected side
-        double v = 0.0;
+        const int fx = (u >> 2) & 1, fy = (u >> 1) & 1, fz = u & 1;
+        double acc = 0.0;
 #pragma unroll
         for (int A = 0; A < 2; ++A)
 #pragma unroll
@@ -937,13 +1028,27 @@ __global__ __launch_bounds__(256) void k_coarse_s2(Geo g, int level, const doubl
                 const double sz = (fz && A) ? -1.0 : 1.0;
                 const double sre = sz * ((fx && B) ? -1.0 : 1.0);
                 const double sim = sz * ((fx && !B) ? -1.0 : 1.0) * (fy ? -1.0 : 1.0);
-                v += sre * S[A][B][0] + sim * S[A][B][1];
+                acc += sre * S[A][B][0] + sim * S[A][B][1];
             }
-        const int i = cx * W + Hh + (fx ? -1 - bx : bx), j = cy * W + Hh + (fy ? -1 - by : by),
-                  k = cz * W + Hh + (fz ? -1 - bz : bz);
-        const int64_t at = s2_site(g.nc, i, j, k);
-        phic[at] = first ? v : phic[at] + v;
+        phic[at[u]] = v[u] + acc;
     }
+}
+
+// blocks of the orbit kernel for one level of a 2x2x2 lattice with fine-cell count M
+__host__ __device__ inline int64_t coarse_s2_blocks(int L, int level)
+{
+    const int sh = L - level;
+    const int64_t orbits = (int64_t)1 << (3 * sh), Ml = (int64_t)1 << (3 * (level - 1));
+    const int C = coarse_cells_per_block(orbits);
+    return C > 1 ? (Ml + C - 1) / C : Ml * (orbits / kCoarseThreads);
+}
+
+template <int P>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_s2(Geo g, int level, const double *__restrict__ psi, int first,
+                                                   double *__restrict__ phic)
+{
+    extern __shared__ double sL[];
+    coarse_s2_body<P>(g, level, psi, first, phic, blockIdx.x, sL);
 }
 
 void launch_coarse_sites(fmmkmc_ctx *c, const Geo &g)
@@ -951,11 +1056,14 @@ void launch_coarse_sites(fmmkmc_ctx *c, const Geo &g)
     if (!c->per_level || !c->phicoarse) return;  // no coarser level with an interaction list
     const int lstart = g.lstart;
     if (c->s2) {
-        const int64_t orbits = (int64_t)c->lat_n * c->lat_n * c->lat_n / 8;  // per level
-        for (int l = g.L - 1; l >= lstart; --l)
-            FMMKMC_DISPATCH_P(c->p, launch(c, "coarse_s2", k_coarse_s2<P_>, dim3((unsigned)((orbits + 255) / 256)),
-                                           dim3(256), g, l, (const double *)c->psi_lv[l], l == g.L - 1 ? 1 : 0,
-                                           c->phicoarse));
+        for (int l = g.L - 1; l >= lstart; --l) {
+            const int64_t orbits = (int64_t)1 << (3 * (g.L - l));
+            const size_t shm = sizeof(double) * c->nt * coarse_cells_per_block(orbits);
+            const std::string name = "coarse_s2_l" + std::to_string(l);  // per level in the kernel timings
+            FMMKMC_DISPATCH_P(c->p, launch_shm(c, name.c_str(), k_coarse_s2<P_>,
+                                               dim3((unsigned)coarse_s2_blocks(g.L, l)), dim3(kCoarseThreads), shm, g, l,
+                                               (const double *)c->psi_lv[l], l == g.L - 1 ? 1 : 0, c->phicoarse));
+        }
     } else {
         const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
         FMMKMC_DISPATCH_P(c->p, launch(c, "coarse_sites", k_coarse_sites<P_>, dim3((unsigned)((ns + 255) / 256)),
@@ -1340,29 +1448,30 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     double part = 0.0;
     if (part_id == 0) {
-        // harmonics at t and r relative to their fine cells, one lane per column m
-        if (ln <= p) {
-            if (wv == 0)
-                harmonics_column(p, ln, tx - (tcx + 0.5) * g.w, ty - (tcy + 0.5) * g.w, tz - (tcz + 0.5) * g.w,
-                                 nullptr, Wa);
-            else if (wv == 1)
-                harmonics_column(p, ln, rx - (rcx + 0.5) * g.w, ry - (rcy + 0.5) * g.w, rz - (rcz + 0.5) * g.w,
-                                 nullptr, Wb);
+        // q (Psi(t) - Psi(r)): the fine level, and in per-level mode every coarser
+        // level too, each about the centre of the level's cell holding t or r.
+        // Harmonics of every (level, endpoint, column m) at once, one lane each,
+        // then the dot products over the block (every level's loads independent).
+        const int l0 = g.per_level ? g.lstart : g.L, nlev = g.L - l0 + 1;
+        double *Wl = sm + 256;  // [level][endpoint][nt]
+        for (int task = threadIdx.x; task < nlev * 2 * (p + 1); task += blockDim.x) {
+            const int li = task / (2 * (p + 1)), e = (task / (p + 1)) & 1, m = task % (p + 1);
+            const int l = l0 + li, side = 1 << (l - 1), sh = g.L - l;
+            const double w = g.a / side;
+            const int cx = (e ? rcx : tcx) >> sh, cy = (e ? rcy : tcy) >> sh, cz = (e ? rcz : tcz) >> sh;
+            harmonics_column(p, m, (e ? rx : tx) - (cx + 0.5) * w, (e ? ry : ty) - (cy + 0.5) * w,
+                             (e ? rz : tz) - (cz + 0.5) * w, nullptr, Wl + (int64_t)(2 * li + e) * nt);
         }
         __syncthreads();
-        const int64_t tcell = cell_id(g.nc, tcx, tcy, tcz), rcell = cell_id(g.nc, rcx, rcy, rcz);
-        for (int k = threadIdx.x; k < nt; k += blockDim.x)
-            part += qi * (psi[(int64_t)k * M + tcell] * Wa[k] - psi[(int64_t)k * M + rcell] * Wb[k]);
-        // per-level mode: the coarser levels at both endpoints, one lane per level and endpoint
-        if (g.per_level && (int)threadIdx.x < 2 * (g.L - g.lstart)) {
-            const int e = threadIdx.x & 1, l = g.lstart + (int)(threadIdx.x >> 1);
-            const int side = 1 << (l - 1), sh = g.L - l;
-            const double w = g.a / side;
-            const double px = e ? rx : tx, py = e ? ry : ty, pz = e ? rz : tz;
-            const int cx = (e ? rcx : tcx) >> sh, cy = (e ? rcy : tcy) >> sh, cz = (e ? rcz : tcz) >> sh;
-            const double v = l2p_runtime(p, psi_lv[l] + cell_id(side, cx, cy, cz), (int64_t)side * side * side,
-                                         px - (cx + 0.5) * w, py - (cy + 0.5) * w, pz - (cz + 0.5) * w);
-            part += e ? -qi * v : qi * v;
+        for (int li = 0; li < nlev; ++li) {
+            const int l = l0 + li, side = 1 << (l - 1), sh = g.L - l;
+            const int64_t Ml = (int64_t)side * side * side;
+            const int64_t tc = cell_id(side, tcx >> sh, tcy >> sh, tcz >> sh),
+                          rc = cell_id(side, rcx >> sh, rcy >> sh, rcz >> sh);
+            const double *pl = l == g.L ? psi : psi_lv[l];
+            const double *Wt = Wl + (int64_t)(2 * li) * nt, *Wr = Wt + nt;
+            for (int k = threadIdx.x; k < nt; k += blockDim.x)
+                part += qi * (pl[(int64_t)k * Ml + tc] * Wt[k] - pl[(int64_t)k * Ml + rc] * Wr[k]);
         }
         // self terms: one copy nu of the old position per lane, or the exact
         // self-image change with its Ewald terms split over the block
@@ -1474,10 +1583,14 @@ __global__ __launch_bounds__(256) void k_move_dU(Geo g, int p, int64_t M, int64_
     move_dU_body(part0 + (int)blockIdx.x, g, p, M, i, tx, ty, tz, psi, x, y, z, q, cnt, slots, R, H, out, psi_lv);
 }
 
+// LDS of a move-dU block: 256 reduction slots, then the four far-field vectors
+// or the harmonics of every level and endpoint (per-level mode)
+size_t move_dU_shm(int nt, int nlev) { return sizeof(double) * ((size_t)std::max(4, 2 * nlev) * nt + 256); }
+
 void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out, hipStream_t st,
                     int part0, int nparts)
 {
-    const size_t shm = sizeof(double) * (4 * c->nt + 256);
+    const size_t shm = move_dU_shm(c->nt, g.per_level ? g.L - g.lstart + 1 : 1);
     launch_on(c, st ? st : c->stream, part0 == 0 ? "move_dU" : "move_dU_side", k_move_dU, dim3(nparts), dim3(256),
               shm, g, c->p, c->M, i, t[0], t[1], t[2], c->psi_lv[c->L], c->x, c->y, c->z, c->q, c->cell_cnt,
               c->cell_slots, c->far.R, c->far.H, out, part0, (double *const *)c->d_psi_ptrs);
@@ -1741,7 +1854,10 @@ __global__ __launch_bounds__(256) void k_b_frow(const RepDev *__restrict__ reps,
     f_row1_body(d.g, d.p, mv.rank, mv.new_site, d.K, d.offsets, d.R, d.sigma, d.F);
 }
 
-// per-level mode: the coarser levels at every site of every replica, one lane per site
+// per-level mode: the coarser levels at every site of every replica.  General
+// lattices: one lane per site (blocks only for such replicas); 2x2x2 lattices:
+// the orbit kernel, one launch per depth below the fine level (level L_r - 1 -
+// depth of replica r; the cells per block depend on the depth only).
 template <int P>
 __global__ __launch_bounds__(256) void k_b_coarse(const RepDev *__restrict__ reps, int R,
                                                   const int64_t *__restrict__ base)
@@ -1752,12 +1868,35 @@ __global__ __launch_bounds__(256) void k_b_coarse(const RepDev *__restrict__ rep
     coarse_site_body<P>(d.g, d.psi_lv, (blockIdx.x - base[r]) * (int64_t)blockDim.x + threadIdx.x, d.s2, d.phicoarse);
 }
 
+template <int P>
+__global__ __launch_bounds__(kCoarseThreads) void k_b_coarse_s2(const RepDev *__restrict__ reps, int R,
+                                                     const int64_t *__restrict__ base, int depth)
+{
+    extern __shared__ double sL[];
+    const int r = find_rep(base, R, blockIdx.x);
+    const RepDev &d = reps[r];
+    const int level = d.g.L - 1 - depth;
+    coarse_s2_body<P>(d.g, level, d.psi_lv[level], depth == 0 ? 1 : 0, d.phicoarse, blockIdx.x - base[r], sL);
+}
+
 void launch_b_coarse(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                      int p)
 {
     FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_coarse", k_b_coarse<P_>, dim3((unsigned)blocks), dim3(256), 0, reps,
                                      R, base));
 }
+
+void launch_b_coarse_s2(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                        int p, int depth)
+{
+    const int64_t orbits = (int64_t)1 << (3 * (1 + depth));
+    const size_t shm = sizeof(double) * (p + 1) * (p + 1) * coarse_cells_per_block(orbits);
+    FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_coarse_s2", k_b_coarse_s2<P_>, dim3((unsigned)blocks),
+                                     dim3(kCoarseThreads), shm,
+                                     reps, R, base, depth));
+}
+
+int64_t coarse_s2_level_blocks(int L, int level) { return coarse_s2_blocks(L, level); }
 
 void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                    int p, bool mixed)
@@ -1783,9 +1922,9 @@ void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, cons
 }
 
 void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, double *acc,
-                      int nt, int part0, int nparts)
+                      int nt, int part0, int nparts, int nlev_max)
 {
-    const size_t shm = sizeof(double) * (4 * nt + 256);
+    const size_t shm = move_dU_shm(nt, nlev_max);
     launch_prof(pr, st, part0 == 0 ? "b_move_dU" : "b_move_dU_side", k_b_move_dU, dim3((unsigned)(R * nparts)),
                 dim3(256), shm, reps, moves, acc, part0, nparts);
 }
