@@ -137,6 +137,36 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
+def accuracy_sample(sites, n, L, hops):
+    """the bounded sample of the oracle leg: every valid hop of the charges in
+    the 2x2x2 block of fine cells at the middle of the box; returns (charge
+    index, target site, slot index i * K + k) of each slot"""
+    from oracle import lattice_targets  # the oracle leg's own bookkeeping
+    nc = 2 ** (L - 1)
+    w = n / nc
+    xyz = W.site_xyz(sites, n)
+    cells = np.floor(xyz / w).astype(int)
+    idx_c = np.nonzero(np.all((cells >= nc // 2) & (cells < nc // 2 + 2), axis=1))[0]
+    t, valid = lattice_targets(sites, n, hops, True)  # occupancy of every charge
+    t, valid = t[idx_c], valid[idx_c]
+    K = len(hops)
+    v = valid.reshape(-1)
+    charge = np.repeat(idx_c, K)[v]
+    slot = (np.repeat(idx_c, K) * K + np.tile(np.arange(K), len(idx_c)))[v]
+    return charge, t.reshape(-1)[v], slot
+
+
+def sample_slots(n, N, L, hops):
+    """slot indices of the oracle leg's sample, computed without the oracle: the
+    charges in the 2x2x2 block of fine cells at the middle of the box, every hop"""
+    sites, xyz, q = W.lattice_charges(n, N, W.BASE_SEED + 4)
+    nc = 2 ** (L - 1)
+    cells = np.floor(xyz / (n / nc)).astype(int)
+    idx_c = np.nonzero(np.all((cells >= nc // 2) & (cells < nc // 2 + 2), axis=1))[0]
+    K = len(hops)
+    return (idx_c[:, None] * K + np.arange(K)[None, :]).reshape(-1)
+
+
 def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed, self_image="expansion", host_loop=True,
             per_level=False):
     import torch
@@ -153,6 +183,9 @@ def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed, self_image="expans
     dU, mask = ctx.propose_lattice(hops)  # builds the per-charge hop table once
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    # the first pass's dU of the oracle leg's sample (accuracy report)
+    pick = torch.as_tensor(sample_slots(n, N, L, hops), device="cuda")
+    sample_dU = dU.reshape(-1)[pick].cpu().numpy()
     log(f"[{precision}] setup {setup_s:.2f} s, U0 = {U0:.6f}")
     occ = np.zeros(n ** 3, bool)
     occ[sites] = True
@@ -227,14 +260,25 @@ def run_gpu(precision, n, N, L, p, hops, steps, warmup, seed, self_image="expans
     b.step(u)
     torch.cuda.synchronize()
     graph_wall = time.perf_counter() - t0
+    # the kernels of the device-driven step, timed by HIP events as plain launches
+    b.set_profiling(True)
+    nprof = 5
+    b.step(rng.random((nprof, 1)))
+    graph_k = {}
+    for name in ["b_site", "b_slot", "b_count", "b_select", "b_move_dU", "b_move_dU_side", "b_frow", "b_sweep",
+                 "b_levels", "b_coarse_s2", "b_path", "b_book", "b_far_refresh", "b_cheb_a", "b_cheb_b", "b_finish"]:
+        ms, k = b.kernel_time(name)
+        if k:
+            graph_k[name] = {"us_per_step": ms / nprof * 1e3, "launches_per_step": k / nprof}
+    b.set_profiling(False)
     b.close()
     ctx.close()
     return dict(setup_s=setup_s, host_ms_per_step=1e3 * wall / steps, ms_per_step=1e3 * graph_wall / steps,
                 propose_ms=1e3 * propose_wall / steps, commit_us=1e6 * commit_wall / steps, kernels=ktimes,
-                valid_slots=valid, U0=U0, tuning=tuning)
+                valid_slots=valid, U0=U0, tuning=tuning, graph_kernels=graph_k, sample_dU=sample_dU)
 
 
-def batch_contexts(precision, p=10, count=256):
+def batch_contexts(precision, p=10, count=256, per_level=False, self_image="expansion"):
     """the replicas of the batched workload: N_r log-uniform in [1000, 65536],
     lattice side n_r = ceil((2 N_r)^(1/3)) (about 50 % occupancy), depth by the
     level rule, periodic, p = 10"""
@@ -244,7 +288,7 @@ def batch_contexts(precision, p=10, count=256):
     for r in range(count):
         sites, xyz, q = W.replica_system(r, Ns[r], ns[r])
         c = Context(xyz, q, a=float(ns[r]), levels=int(Ls[r]), order=p, bc="periodic", precision=precision,
-                    lattice_n=int(ns[r]), device=0)
+                    lattice_n=int(ns[r]), device=0, per_level=per_level, self_image=self_image)
         c.initialise()
         ctxs.append(c)
         if (r + 1) % 64 == 0:
@@ -252,13 +296,13 @@ def batch_contexts(precision, p=10, count=256):
     return ctxs, Ns, ns
 
 
-def run_batched(precision, steps, warmup, seed, tune=True, keep=False):
+def run_batched(precision, steps, warmup, seed, tune=True, keep=False, per_level=False, self_image="expansion"):
     """config-5 steps of all replicas as one captured graph per step"""
     import torch
 
     from paper_1905_04065_amd import Batch
     t0 = time.perf_counter()
-    ctxs, Ns, ns = batch_contexts(precision)
+    ctxs, Ns, ns = batch_contexts(precision, per_level=per_level, self_image=self_image)
     b = Batch(ctxs, W.HOPS6)
     setup_s = time.perf_counter() - t0
     info = b.tune(rounds=5) if tune else b.info()
@@ -275,8 +319,9 @@ def run_batched(precision, steps, warmup, seed, tune=True, keep=False):
     b.set_profiling(True)
     b.step(rng.random((3, R)))
     phases = {}
-    for name in ["b_site", "b_slot", "b_count", "b_select", "b_move_dU", "b_frow", "b_sweep", "b_path", "b_book",
-                 "b_far_refresh", "b_cheb_a", "b_cheb_b", "b_finish"]:
+    for name in ["b_coarse", "b_coarse_s2", "b_site", "b_slot", "b_count", "b_select", "b_move_dU", "b_move_dU_side",
+                 "b_frow", "b_sweep", "b_levels", "b_path", "b_book", "b_far_refresh", "b_cheb_a", "b_cheb_b",
+                 "b_finish"]:
         ms, n = b.kernel_time(name)
         if n:
             phases[name] = ms / n * 1e3
@@ -335,41 +380,226 @@ def run_unbatched_fp64(ctxs, steps, seed):
     return dict(ms_per_step=1e3 * wall / steps, slots_per_step=slots)
 
 
-def cpu_baseline(n, N, L, p, hops, seed, budget_s=20.0):
-    """The oracle (O-fmm, FP64, OpenMP) on the host cores, on a bounded sample:
-    all hops of the charges in a 2x2x2 block of fine cells, after the cells
-    those proposals touch have been formed (setup excluded on both sides)."""
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def guarded(d, ref, scale):
+    e = np.abs(d - ref) / np.maximum(np.abs(ref), scale)
+    return float(np.max(e)), float(np.mean(e))
+
+
+def paper_rel(d, ref):
+    """the per-proposal relative error of the paper's error study (Sec. 6.1): mean and max"""
+    r = np.abs(d - ref) / np.abs(ref)
+    return float(np.mean(r)), float(np.max(r))
+
+
+def cpu_baseline(n, N, L, p, hops, seed, runs, budget_s=20.0):
+    """The oracle leg.  Timing: O-fmm (FP64, OpenMP) on the host cores, on a
+    bounded sample (every valid hop of the charges in the 2x2x2 block of fine
+    cells at the middle of the box), after the cells those proposals touch have
+    been formed; O-exact (tin-foil Ewald, FFT lattice form) on the same sample.
+    Accuracy: the GPU's dU of the same sample slots (first proposal pass of each
+    variant's context) against O-fmm of the same variant and against O-exact."""
     import oracle as O
 
     sites, xyz, q = W.lattice_charges(n, N, seed)
+    charge, tsite, slot = accuracy_sample(sites, n, L, hops)
+    pos = np.searchsorted(sample_slots(n, N, L, hops), slot)
+    tgt = W.site_xyz(tsite, n)
     t0 = time.perf_counter()
     f = O.FmmKmc(xyz, q, float(n), L, p, "periodic", lazy=True)
     setup = time.perf_counter() - t0
-    nc = 2 ** (L - 1)
-    w = n / nc
-    cells = np.floor(xyz / w).astype(int)
-    inblock = np.all((cells >= nc // 2) & (cells < nc // 2 + 2), axis=1)
-    idx_c = np.nonzero(inblock)[0]
-    t, valid = O.lattice_targets(sites[idx_c], n, hops, True)
-    idx = np.repeat(idx_c, len(hops))[valid.reshape(-1)]
-    tgt = W.site_xyz(t.reshape(-1)[valid.reshape(-1)], n)
-    for x in np.concatenate([xyz[idx_c], tgt]):
+    for x in np.concatenate([xyz[np.unique(charge)], tgt]):
         f.local(f.fine_cell_of(x))
     t0 = time.perf_counter()
     reps = 0
     while True:
-        f.propose(idx, tgt)
+        d_fmm = f.propose(charge, tgt)
         reps += 1
         el = time.perf_counter() - t0
         if el > budget_s / 4 or reps >= 50:
             break
-    rate = reps * len(idx) / el
-    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    rate = reps * len(charge) / el
     f.close()
-    return dict(value=rate, unit="proposals/s", cores=threads, kind="oracle",
-                sample=f"{len(idx)} valid slots (all 26 hops of the {len(idx_c)} charges in a 2x2x2 block of fine "
-                       f"cells) x {reps} repetitions, FP64 O-fmm with OpenMP; octree upward pass ({setup:.1f} s) and "
-                       f"formation of the touched cells' local expansions excluded")
+    t0 = time.perf_counter()
+    E = O.LatticeEwald(sites, q, n)
+    exact = E.dU_many(charge, tsite)
+    t_exact = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    base = dict(value=rate, unit="proposals/s", cores=threads, kind="oracle",
+                sample=f"{len(charge)} valid slots (all {len(hops)} hops of the charges in a 2x2x2 block of fine cells) "
+                       f"x {reps} repetitions, FP64 O-fmm with OpenMP; octree upward pass ({setup:.1f} s) and "
+                       f"formation of the touched cells' local expansions excluded",
+                o_exact_proposals_per_s=len(charge) / t_exact,
+                o_exact_note="tin-foil Ewald, FFT lattice form (one 3-D FFT of the site charges, then the "
+                             "real-space sum per slot), single thread numpy; setup included", **cpu_info())
+    # accuracy of every variant the GPU ran, on the same sample
+    acc = {}
+    scale = float(np.mean(np.abs(exact)))
+    for variant, (self_image, per_level) in {"paper": ("expansion", False), "exact_self_image": ("exact", False),
+                                             "per_level": ("expansion", True),
+                                             "per_level_exact_self_image": ("exact", True)}.items():
+        if variant not in runs:
+            continue
+        ref = d_fmm if variant == "paper" else None
+        if ref is None:
+            g = O.FmmKmc(xyz, q, float(n), L, p, "periodic", lazy=True, self_image=self_image, per_level=per_level)
+            ref = g.propose(charge, tgt)
+            g.close()
+        o_mean, o_max = paper_rel(ref, exact)
+        acc[variant] = {"o_fmm_vs_o_exact_mean_rel": o_mean, "o_fmm_vs_o_exact_max_rel": o_max}
+        for pr, r in runs[variant].items():
+            d = r["sample_dU"][pos]
+            gmax, gmean = guarded(d, ref, scale)
+            e_mean, e_max = paper_rel(d, exact)
+            acc[variant][pr] = {"vs_o_fmm_guarded_max": gmax, "vs_o_fmm_guarded_mean": gmean,
+                                "vs_o_fmm_guarded_max_floor_1e-3_mean": guarded(d, ref, 1e-3 * scale)[0],
+                                "vs_o_exact_mean_rel": e_mean, "vs_o_exact_max_rel": e_max}
+    acc["sample"] = f"{len(charge)} slots of the first proposal pass (initial configuration); guarded error floor " \
+                    f"<|dU|> = {scale:.4f}"
+    return base, acc
+
+
+def accuracy_small_configs():
+    """configs 1, 2, 3 and two replicas of config 5 against the oracles, as the GPU
+    parity tests run them (oracle leg of the benchmark)"""
+    import torch
+
+    import oracle as O
+    from paper_1905_04065_amd import Batch, Context
+    out = {}
+
+    def lattice_pass(ctx, hops):
+        dU, mask = ctx.propose_lattice(hops)
+        torch.cuda.synchronize()
+        return dU.cpu().numpy().reshape(-1), mask.cpu().numpy().reshape(-1).astype(bool)
+
+    # config 1: every slot vs O-fmm and vs the direct sum
+    sites, xyz, q, c = W.config_system(1)
+    hops = W.hops(c["hops"])
+    ctx = Context(xyz, q, a=c["a"], levels=c["L"], order=c["p"], bc="free", lattice_n=c["n"], device=0)
+    ctx.initialise()
+    d, m = lattice_pass(ctx, hops)
+    ctx.close()
+    t, v = O.lattice_targets(sites, c["n"], hops, False)
+    v = v.reshape(-1)
+    idx = np.repeat(np.arange(len(q)), len(hops))[v]
+    tgt = W.site_xyz(t.reshape(-1)[v], c["n"])
+    ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "free").propose(idx, tgt)
+    ex = O.direct_dU(xyz, q, idx, tgt)
+    sc = float(np.mean(np.abs(ref)))
+    out["config1"] = {"slots": int(v.sum()), "vs_o_fmm_guarded_max": guarded(d[v], ref, sc)[0],
+                      "vs_o_fmm_guarded_mean": guarded(d[v], ref, sc)[1],
+                      "vs_o_exact_mean_rel": paper_rel(d[v], ex)[0], "vs_o_exact_max_rel": paper_rel(d[v], ex)[1]}
+    # config 3: mixed, every slot before and after 10^4 accepted moves replayed by O-fmm; energy drift
+    sites, xyz, q, c = W.config_system(3)
+    ctx = Context(xyz, q, a=c["a"], levels=c["L"], order=c["p"], bc="free", precision="mixed", lattice_n=c["n"],
+                  device=0)
+    ctx.initialise()
+    ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "free")
+    d0, _ = lattice_pass(ctx, hops)
+    t, v = O.lattice_targets(sites, c["n"], hops, False)
+    v = v.reshape(-1)
+    idx = np.repeat(np.arange(len(q)), len(hops))
+    r0 = ref.propose(idx[v], W.site_xyz(t.reshape(-1)[v], c["n"]))
+    sc = float(np.mean(np.abs(r0)))
+    ex0 = O.direct_dU(xyz, q, idx[v], W.site_xyz(t.reshape(-1)[v], c["n"]))
+    u = W.commit_choices(c["commits"], W.BASE_SEED + 3)
+    cur = sites.copy()
+    worst = 0.0
+    for s_ in range(c["commits"]):
+        t, vv = O.lattice_targets(cur, c["n"], hops, False)
+        vs = np.nonzero(vv.reshape(-1))[0]
+        s = vs[int(u[s_] * len(vs))]
+        i = int(s // len(hops))
+        new = W.site_xyz([t.reshape(-1)[s]], c["n"])[0]
+        dg, dr = ctx.accept(i, new), ref.accept(i, new)
+        worst = max(worst, abs(dg - dr) / max(abs(dr), sc))
+        cur[i] = t.reshape(-1)[s]
+    d1, _ = lattice_pass(ctx, hops)
+    t, v1 = O.lattice_targets(cur, c["n"], hops, False)
+    v1 = v1.reshape(-1)
+    r1 = ref.propose(idx[v1], W.site_xyz(t.reshape(-1)[v1], c["n"]))
+    out["config3_mixed"] = {"vs_o_fmm_guarded_max_before": guarded(d0[v], r0, sc)[0],
+                            "vs_o_exact_mean_rel_before": paper_rel(d0[v], ex0)[0],
+                            "vs_o_fmm_guarded_max_after_1e4_commits": guarded(d1[v1], r1, sc)[0],
+                            "accepted_dU_vs_o_fmm_max": worst,
+                            "energy_drift_after_1e4_commits": abs(ctx.energy - ref.energy)}
+    ctx.close()
+    ref.close()
+    # config 2: 100 steps with commit, then 512 sampled slots vs O-fmm and tin-foil Ewald
+    sites, xyz, q, c = W.config_system(2)
+    hops = W.hops(c["hops"])
+    K = len(hops)
+    ctx = Context(xyz, q, a=c["a"], levels=c["L"], order=c["p"], bc="periodic", lattice_n=c["n"], device=0)
+    ctx.initialise()
+    ref = O.FmmKmc(xyz, q, c["a"], c["L"], c["p"], "periodic", lazy=True)
+    u = W.commit_choices(c["steps"], W.BASE_SEED + 2)
+    cur = sites.copy()
+    worst = 0.0
+    for s_ in range(c["steps"]):
+        d, m = lattice_pass(ctx, hops)
+        t, vv = O.lattice_targets(cur, c["n"], hops, True)
+        vs = np.nonzero(vv.reshape(-1))[0]
+        s = vs[int(u[s_] * len(vs))]
+        i = int(s // K)
+        new = W.site_xyz([t.reshape(-1)[s]], c["n"])[0]
+        dg, dr = ctx.accept(i, new), ref.accept(i, new)
+        worst = max(worst, abs(dg - dr) / max(abs(dr), 0.05))
+        cur[i] = t.reshape(-1)[s]
+    d, m = lattice_pass(ctx, hops)
+    t, vv = O.lattice_targets(cur, c["n"], hops, True)
+    vv = vv.reshape(-1)
+    pick = np.random.default_rng(W.BASE_SEED + 20).choice(np.nonzero(vv)[0], 512, replace=False)
+    dr = ref.propose(pick // K, W.site_xyz(t.reshape(-1)[pick], c["n"]))
+    ex = O.LatticeEwald(cur, q, c["n"]).dU_many(pick // K, t.reshape(-1)[pick])
+    sc = float(np.mean(np.abs(d[vv])))
+    out["config2"] = {"accepted_dU_vs_o_fmm_max_100_steps": worst,
+                      "vs_o_fmm_guarded_max_512_sampled_after": guarded(d[pick], dr, sc)[0],
+                      "vs_o_exact_mean_rel_512_sampled": paper_rel(d[pick], ex)[0],
+                      "vs_o_exact_max_rel_512_sampled": paper_rel(d[pick], ex)[1]}
+    ctx.close()
+    ref.close()
+    # config 5: the largest and the smallest replica (p = 10, mixed, batched), 256 sampled slots each
+    Ns, ns, Ls = W.replica_sizes()
+    res5 = {}
+    for r in (int(np.argmax(Ns)), int(np.argmin(Ns))):
+        sites, xyz, q = W.replica_system(r, Ns[r], ns[r])
+        n = int(ns[r])
+        ctx = Context(xyz, q, a=float(n), levels=int(Ls[r]), order=10, bc="periodic", precision="mixed",
+                      lattice_n=n, device=0)
+        ctx.initialise()
+        b = Batch([ctx], W.HOPS6)
+        mv, st, _ = (x.cpu().numpy() for x in b.step(np.full((1, 1), 0.37)))
+        dnow, mnow = lattice_pass(ctx, W.HOPS6)
+        b.close()
+        cur = np.floor(ctx.positions().cpu().numpy()).astype(np.int64) @ np.array([n * n, n, 1])
+        ctx.close()
+        t, vv = O.lattice_targets(cur, n, W.HOPS6, True)
+        vv = vv.reshape(-1)
+        pick = np.random.default_rng(W.BASE_SEED + 70 + r).choice(np.nonzero(vv)[0], 256, replace=False)
+        ref = O.FmmKmc(xyz, q, float(n), int(Ls[r]), 10, "periodic", lazy=True)
+        ref.accept(int(mv[0, 0]), W.site_xyz([int(st[0, 0])], n)[0])  # the same move, replayed
+        dr = ref.propose(pick // 6, W.site_xyz(t.reshape(-1)[pick], n))
+        ref.close()
+        ex = O.LatticeEwald(cur, q, n).dU_many(pick // 6, t.reshape(-1)[pick])
+        sc = float(np.mean(np.abs(dnow[vv])))
+        res5[f"replica{r}_n{n}_N{int(Ns[r])}_L{int(Ls[r])}"] = {
+            "vs_o_fmm_guarded_max_256_sampled": guarded(dnow[pick], dr, sc)[0],
+            "vs_o_exact_mean_rel_256_sampled": paper_rel(dnow[pick], ex)[0]}
+    out["config5_mixed_after_one_batched_step"] = res5
+    return out
 
 
 def roofline_entry(kernel, kt, n, N, K, p, precision, copy_gbs, traffic, exact_self=False):
@@ -482,6 +712,10 @@ def batched_summary(args):
     plain = run_unbatched_fp64(ctxs, 2, seed)
     for c in ctxs:
         c.close()
+    log("[batch] mixed, exact self-image term")
+    mixed_exact = run_batched("mixed", steps, args.warmup, seed, self_image="exact")
+    log("[batch] mixed, per-level expansions and exact self-image term")
+    mixed_levels = run_batched("mixed", steps, args.warmup, seed, per_level=True, self_image="exact")
     slots = mixed["slots_per_step"]
     return {
         "workload": f"{mixed['replicas']} periodic replicas, N_r log-uniform in [1000, 65536] (sum {slots // 6}), "
@@ -489,8 +723,15 @@ def batched_summary(args):
         "slots_per_step": slots,
         "mixed_batched": {"proposals_per_s": slots / (mixed["ms_per_step"] / 1e3), **mixed},
         "fp64_batched": {"proposals_per_s": slots / (fp64["ms_per_step"] / 1e3), **fp64},
-        "fp64_one_replica_at_a_time": {"proposals_per_s": slots / (plain["ms_per_step"] / 1e3), **plain},
-        "speedup_mixed_batched_vs_plain_fp64": plain["ms_per_step"] / mixed["ms_per_step"],
+        "fp64_host_driven_one_replica_at_a_time": {
+            "proposals_per_s": slots / (plain["ms_per_step"] / 1e3), **plain,
+            "note": "each replica through the single-context API with the selection on the host (one host "
+                    "synchronisation per replica): mostly host overhead, not a kernel comparison"},
+        "speedup_mixed_batched_vs_fp64_batched": fp64["ms_per_step"] / mixed["ms_per_step"],
+        "mixed_batched_exact_self_image": {"proposals_per_s": slots / (mixed_exact["ms_per_step"] / 1e3),
+                                           **mixed_exact},
+        "mixed_batched_per_level_exact_self_image": {"proposals_per_s": slots / (mixed_levels["ms_per_step"] / 1e3),
+                                                     **mixed_levels},
     }
 
 
@@ -557,9 +798,45 @@ def main():
                     kernel_avg_us={k: (v[0] / max(v[1], 1) * 1e3) for k, v in kt.items() if v[1] > 0},
                     dominant=dom, rooflines=roof)
 
+    def graph_rooflines(r, pr, exact):
+        """rooflines of the kernels the device-driven step runs (HIP events around
+        plain launches of the batched kernels, one launch each per step)"""
+        gk = r["graph_kernels"]
+        out_ = {}
+        for name, kern in (("b_site", "site_phi_s2"), ("b_slot", "slot_lattice"), ("b_sweep", "sweep")):
+            if name not in gk:
+                continue
+            us = gk[name]["us_per_step"]
+            bound, amount, unit = kernel_work(kern, n, N, K, p, pr, exact)
+            if bound == "hbm":
+                ach = amount / (us * 1e-6) / 1e9
+                out_[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": ach / HBM_PEAK_GBS, "frac_of_copy": ach / copy_gbs, "avg_us": us,
+                              "algorithmic_bytes": amount, "traffic": None}
+            else:
+                ach = amount / (us * 1e-6) / 1e12
+                out_[name] = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": ach / FP64_PEAK_TFLOPS, "avg_us": us, "algorithmic_flop": amount,
+                              "traffic": None}
+        if "b_site" in out_ and "b_slot" in out_:
+            tb = out_["b_site"]["algorithmic_bytes"] + out_["b_slot"]["algorithmic_bytes"]
+            tus = out_["b_site"]["avg_us"] + out_["b_slot"]["avg_us"]
+            # the survey's count of the proposal pass (S0-S3): 640 MB FP64, 460 MB mixed at this size
+            sb = (640e6 if pr == "fp64" else 460e6) * (N * K) / 26e6
+            out_["proposal_pass"] = {"bound": "hbm", "algorithmic_bytes": tb, "avg_us": tus,
+                                     "achieved": tb / (tus * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": tb / (tus * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                     "frac_with_survey_bytes": sb / (tus * 1e-6) / 1e9 / HBM_PEAK_GBS}
+        return out_
+
     head = summary(head_prec)
-    dom = head["dominant"]
-    droof = dict(head["rooflines"][dom])
+    groof = graph_rooflines(res[head_prec], head_prec, False)
+    # the kernel of the headline (device-driven) step with the largest time per step
+    gdom = max((k for k in ("b_site", "b_slot", "b_sweep") if k in groof), key=lambda k: groof[k]["avg_us"])
+    droof = dict(groof[gdom])
+    if gdom == "b_sweep":
+        # HBM traffic from the committed counters of the same kernel body (single-context sweep)
+        droof["traffic"] = head["rooflines"]["sweep"]["traffic"] if head["rooflines"].get("sweep") else None
     out = {
         "metric": "dU proposals/sec at N=1e6, p=12 (FP64 vs mixed); accepted-move commit us",
         "value": head["value"],
@@ -577,7 +854,8 @@ def main():
         "dtype": "f64" if head_prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"periodic {n}^3 lattice, N={N} +-1 charges, {K} hops/charge ({slots} slots/step), "
-                               f"L={L}, p={p}, one accepted move per step",
+                               f"L={L}, p={p}, one accepted move per step; the paper's terms (fine-level sweep "
+                               "at each accept, Sec. 3.1 self terms)",
                    "global_batch": slots, "parallelism": "single GPU"},
         "valid_proposals_per_s": head["valid_per_s"],
         "valid_slots": res[head_prec]["valid_slots"],
@@ -586,10 +864,12 @@ def main():
         "commit_us": head["commit_us"],
         "setup_s": head["setup_s"],
         "copy_GBps": copy_gbs,
-        "kernel_avg_us": head["kernel_avg_us"],
         "roofline": {k: droof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "roofline_kernel": dom,
-        "rooflines": head["rooflines"],
+        "roofline_kernel": gdom,
+        "graph_step_rooflines": groof,
+        "graph_step_kernel_us": res[head_prec]["graph_kernels"],
+        "host_driven_kernel_avg_us": head["kernel_avg_us"],
+        "host_driven_rooflines": head["rooflines"],
     }
     if "mixed" in res and head_prec != "mixed":
         m = summary("mixed")
@@ -599,43 +879,49 @@ def main():
                         "propose_only_per_s": m["propose_only_per_s"], "propose_us": m["propose_us"],
                         "commit_us": m["commit_us"],
                         "dtype": "f32 fine-level evaluation, f64 difference/far field/commit",
-                        "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"]}
-    if res_exact:
-        out["exact_self_image"] = {}
+                        "speedup_vs_fp64": head["ms_per_step"] / m["ms_per_step"],
+                        "graph_step_rooflines": graph_rooflines(res["mixed"], "mixed", False),
+                        "graph_step_kernel_us": res["mixed"]["graph_kernels"],
+                        "host_driven_kernel_avg_us": m["kernel_avg_us"]}
+    notes = {"exact_self_image": "self_image=1: the moving charge's own copies by the exact Ewald change per hop "
+                                 "instead of the V_box sum + constant + 1/2 dE.R'dK (no per-charge hop table)",
+             "per_level": "per_level=1: local expansions kept per level; an accept updates the interaction-list cells "
+                          "of each level (k_levels) instead of every fine cell (k_sweep); proposals add the coarser "
+                          "levels per site (k_coarse_s2)",
+             "per_level_exact_self_image": "per_level=1 and self_image=1 together"}
+    runs = {"paper": res}
+    variants = {}
+    for key, rr, exact, levels in (("exact_self_image", res_exact, True, False), ("per_level", res_levels, False, True),
+                                   ("per_level_exact_self_image", res_both, True, True)):
+        if not rr:
+            continue
+        runs[key] = rr
+        variants[key] = {"note": notes[key]}
         for pr in precs:
-            m = summary(pr, exact=True)
-            out["exact_self_image"][pr] = {
-                "value": m["value"], "ms_per_step": m["ms_per_step"], "host_driven_ms_per_step": m["host_driven_ms_per_step"],
-                "propose_us": m["propose_us"], "commit_us": m["commit_us"], "setup_s": m["setup_s"],
-                "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"],
-                "note": "self_image=1: the moving charge's own copies by the exact Ewald change per hop instead of the "
-                        "V_box sum + constant + 1/2 dE.R'dK (no per-charge hop table)"}
-    if res_levels:
-        out["per_level"] = {}
-        for pr in precs:
-            m = summary(pr, levels=True)
-            out["per_level"][pr] = {
-                "value": m["value"], "ms_per_step": m["ms_per_step"], "host_driven_ms_per_step": m["host_driven_ms_per_step"],
-                "propose_us": m["propose_us"], "commit_us": m["commit_us"], "setup_s": m["setup_s"],
-                "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"],
-                "note": "per_level=1: local expansions kept per level; an accept updates the interaction-list cells "
-                        "of each level (k_levels) instead of every fine cell (k_sweep); proposals add the coarser "
-                        "levels per site (k_coarse_s2)"}
-    if res_both:
-        out["per_level_exact_self_image"] = {}
-        for pr in precs:
-            m = summary(pr, exact=True, levels=True)
-            out["per_level_exact_self_image"][pr] = {
-                "value": m["value"], "ms_per_step": m["ms_per_step"], "host_driven_ms_per_step": m["host_driven_ms_per_step"],
-                "propose_us": m["propose_us"], "commit_us": m["commit_us"], "setup_s": m["setup_s"],
-                "kernel_avg_us": m["kernel_avg_us"], "rooflines": m["rooflines"],
-                "note": "per_level=1 and self_image=1 together"}
+            m = summary(pr, exact=exact, levels=levels)
+            variants[key][pr] = {"value": m["value"], "ms_per_step": m["ms_per_step"],
+                                 "speedup_vs_paper_fp64": head["ms_per_step"] / m["ms_per_step"],
+                                 "host_driven_ms_per_step": m["host_driven_ms_per_step"],
+                                 "propose_us": m["propose_us"], "commit_us": m["commit_us"], "setup_s": m["setup_s"],
+                                 "graph_step_kernel_us": rr[pr]["graph_kernels"],
+                                 "graph_step_rooflines": graph_rooflines(rr[pr], pr, exact),
+                                 "host_driven_kernel_avg_us": m["kernel_avg_us"]}
+    if variants:
+        out["variants"] = variants
+        best = min(((k, pr) for k in variants for pr in precs), key=lambda kp: variants[kp[0]][kp[1]]["ms_per_step"])
+        out["best_variant"] = {"variant": best[0], "precision": best[1],
+                               "value": variants[best[0]][best[1]]["value"],
+                               "ms_per_step": variants[best[0]][best[1]]["ms_per_step"],
+                               "speedup_vs_paper_fp64": variants[best[0]][best[1]]["speedup_vs_paper_fp64"]}
     if not args.skip_batch:
         out["batched"] = batched_summary(args)
         out["slab"] = run_slab(max(args.steps, 5), args.warmup, W.BASE_SEED + 6)
     if not args.skip_cpu:
         try:
-            out["cpu_baseline"] = cpu_baseline(n, N, L, p, hops, seed)
+            out["cpu_baseline"], acc = cpu_baseline(n, N, L, p, hops, seed, runs)
+            out["accuracy"] = {"config4_sample": acc}
+            if not args.quick:
+                out["accuracy"].update(accuracy_small_configs())
         except Exception as e:  # the oracle is optional for the GPU figures
             out["cpu_baseline"] = {"error": str(e)}
     print(json.dumps(out), flush=True)

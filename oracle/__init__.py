@@ -18,6 +18,7 @@ import os
 import numpy as np
 
 from . import build as _build
+from .ewald_lattice import LatticeEwald  # noqa: F401
 from .kmc import cumulative, lattice_targets, propensities, select_slot, time_increment  # noqa: F401
 
 _lib = None

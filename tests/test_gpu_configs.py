@@ -121,6 +121,11 @@ def test_config2_hundred_steps_with_commit():
     err = guarded_err(dU[pick], d_ref, scale=float(np.nanmean(np.abs(dU[v]))))
     print(f"  after the steps, 512 sampled slots: max guarded rel err {err:.3e}", flush=True)
     assert err < 1e-10
+    # the same slots against O-exact (tin-foil Ewald of the final configuration)
+    ex = O.LatticeEwald(cur, q, n).dU_many(pick // K, t.reshape(-1)[pick])
+    g_mean, g_max = paper_rel_err(dU[pick], ex)
+    print(f"  vs O-exact (tin-foil Ewald): mean/max rel err {g_mean:.3e}/{g_max:.3e}", flush=True)
+    assert g_mean < 1e-3  # truncation at p = 12 (Sec. 6.1: ~1e-4)
     ctx.close()
     ref.close()
 
@@ -193,6 +198,10 @@ def test_config4_sampled_slots_and_full_mask(precision, tol):
     print(f"  384 sampled slots of {v.sum()} valid: max guarded rel err {err:.3e} (mean |dU| {scale:.4f})",
           flush=True)
     assert err < tol
+    ex = O.LatticeEwald(sites, q, n).dU_many(pick // K, t.reshape(-1)[pick])
+    g_mean, g_max = paper_rel_err(dU[pick], ex)
+    print(f"  vs O-exact (tin-foil Ewald): mean/max rel err {g_mean:.3e}/{g_max:.3e}", flush=True)
+    assert g_mean < 1e-3  # truncation at p = 12 (Sec. 6.1: ~1e-4)
     # three accepted moves, then a second sample
     u = W.commit_choices(3, W.BASE_SEED + 41)
     cur = sites.copy()

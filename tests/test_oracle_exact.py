@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import workloads as W
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "madelung.json")))
 
@@ -130,3 +131,21 @@ def test_periodic_self_change_small_displacement():
     assert abs(rem[0]) < 4.0 * 0.25 ** 4 / a ** 5
     assert rem[1] / rem[0] == pytest.approx(16.0, rel=0.02)
     assert rem[2] / rem[1] == pytest.approx(16.0, rel=0.02)
+
+
+@pytest.mark.parametrize("n,N,hops", [(8, 100, "26"), (12, 300, "6"), (10, 500, "26")])
+def test_lattice_ewald_matches_pair_ewald(n, N, hops):
+    """The FFT lattice Ewald (reciprocal part by one 3-D FFT of the site charges)
+    against the pair-by-pair Ewald sum (pinned by the Madelung constants), and
+    independent of the splitting parameter"""
+    sites, xyz, q = W.lattice_charges(n, N, 71 + n)
+    t, v = O.lattice_targets(sites, n, W.hops(hops), True)
+    v = v.reshape(-1)
+    idx = np.repeat(np.arange(N), len(W.hops(hops)))[v][:150]
+    ts = t.reshape(-1)[v][:150]
+    a = O.LatticeEwald(sites, q, n).dU_many(idx, ts)
+    b = O.ewald_dU(xyz, q, n, idx, W.site_xyz(ts, n))
+    c = O.LatticeEwald(sites, q, n, alpha_h=0.2).dU_many(idx, ts)
+    scale = np.mean(np.abs(b))
+    assert np.max(np.abs(a - b)) < 1e-13 * scale
+    assert np.max(np.abs(a - c)) < 1e-13 * scale
