@@ -146,6 +146,15 @@ int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double 
  * Errors: EINVAL (bad i), EDOMAIN, ECOINCIDENT (target occupied), ECAPACITY. */
 int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_out);
 
+/* Uniform external field E (HOST, 3 doubles; the applied field of Sec. 6.3,
+ * here on any box): from the next call on, every proposal and accept adds the
+ * work -q E.d done against the field over the hop, d = r' - r (periodic boxes:
+ * the minimum-image displacement, i.e. the hop itself for hops shorter than
+ * half the box).  The energy reported by fmmkmc_energy() then includes the
+ * field's work along the accepted moves (the initial energy does not contain a
+ * field term).  Default 0.  Errors: EINVAL (non-finite component). */
+int fmmkmc_set_field(fmmkmc_ctx *c, const double E[3]);
+
 /* Current total energy (initial energy plus the accepted dU's), host. */
 int fmmkmc_energy(fmmkmc_ctx *c, double *U);
 

@@ -47,6 +47,7 @@ def lib():
             "or_ewald_dU": (None, [i, vp, vp, d, d, d, d, i, vp, vp, vp]),
             "or_periodic_self_change": (d, [d, vp]),
             "of_set_self_image": (None, [vp, i]),
+            "of_set_field": (None, [vp, vp]),
             "of_create": (vp, [i, d, i, i, i, vp, vp, i]),
             "of_create_levels": (vp, [i, d, i, i, i, vp, vp, i, i]),
             "of_destroy": (None, [vp]),
@@ -223,7 +224,8 @@ class FmmKmc:
     level's interaction-list cells at an accept (instead of every fine cell).
     """
 
-    def __init__(self, xyz, q, a, L, p, bc="free", lazy=False, self_image="expansion", per_level=False):
+    def __init__(self, xyz, q, a, L, p, bc="free", lazy=False, self_image="expansion", per_level=False,
+                 field=(0.0, 0.0, 0.0)):
         self.xyz = _f64(xyz, (-1, 3)).copy()
         self.q = _f64(q).copy()
         self.a, self.L, self.p = float(a), int(L), int(p)
@@ -240,6 +242,8 @@ class FmmKmc:
         # periodic boxes: the moving charge's own copies by the paper's terms
         # (V_box sum, constant, 1/2 dE.R'dK) or by the exact Ewald change
         lib().of_set_self_image(self._c, 1 if self_image == "exact" else 0)
+        # uniform external field: -q E.d per hop (Sec. 6.3 applies one)
+        lib().of_set_field(self._c, _p(_f64(field, (3,))))
 
     def close(self):
         if getattr(self, "_c", None):

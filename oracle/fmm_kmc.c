@@ -57,6 +57,9 @@
  *   beta.  This touches at most 189 cells per level and copy instead of every
  *   fine cell; the truncation differs from the fine-level rule, so results
  *   move at truncation level.
+ * Uniform external field E (the applied field of Sec. 6.3): a proposal adds the
+ *   work -q E.d done against it over the hop, d = r' - r (periodic: the minimum
+ *   image); the total energy counts it through the accepted dU's.
  * Energy (Alg. "fmm_evaluation", with the charge q_i that the printed line 4
  *   leaves out): U = sum_i 1/2 q_i (Psi(r_i) + sum_{near, j != i} q_j / r_ij)
  *   + 1/2 sum E H.
@@ -84,6 +87,7 @@ struct of_ctx {
     int U_valid;
     int self_exact;
     int per_level; /* keep Psi_l of every level apart (no L2L) */
+    double field[3]; /* uniform external field E */
 };
 
 static int side(int l) { return 1 << (l - 1); }
@@ -441,6 +445,11 @@ of_ctx *of_create_levels(int bc, double a, int L, int p, int n, const double *xy
 
 void of_set_self_image(of_ctx *c, int exact) { c->self_exact = exact ? 1 : 0; }
 
+void of_set_field(of_ctx *c, const double E[3])
+{
+    for (int k = 0; k < 3; ++k) c->field[k] = E[k];
+}
+
 void of_destroy(of_ctx *c)
 {
     if (!c) return;
@@ -603,8 +612,18 @@ static double propose_one(of_ctx *c, int64_t i, const double t[3])
     if (!c->bc) {
         double d0 = tw[0] - r[0], d1 = tw[1] - r[1], d2 = tw[2] - r[2];
         dU -= q * q / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        dU -= q * (c->field[0] * d0 + c->field[1] * d1 + c->field[2] * d2);
         free(Y);
         return dU;
+    }
+    /* uniform field: the work -q E.d over the hop, d the minimum-image displacement */
+    {
+        double d[3];
+        for (int k = 0; k < 3; ++k) {
+            d[k] = tw[k] - r[k];
+            d[k] -= c->a * floor(d[k] / c->a + 0.5);
+        }
+        dU -= q * (c->field[0] * d[0] + c->field[1] * d[1] + c->field[2] * d[2]);
     }
     /* periodic: self terms of Eq. (proposed_energy_sr) */
     if (c->self_exact) {

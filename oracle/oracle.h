@@ -95,6 +95,9 @@ void of_destroy(of_ctx *c);
  * constant and 1/2 dE.R'dK (Sec. 3.1); 1 the exact change q^2 (psi_self -
  * psi(r' - r)) of the moving charge's interaction with its own copies */
 void of_set_self_image(of_ctx *c, int exact);
+/* uniform external field E: every proposal adds -q E.d, d the hop (periodic:
+ * minimum image) */
+void of_set_field(of_ctx *c, const double E[3]);
 double of_energy(of_ctx *c);
 void of_propose(of_ctx *c, int np, const int64_t *idx, const double *tgt, double *dU);
 double of_accept(of_ctx *c, int64_t i, const double newpos[3]);

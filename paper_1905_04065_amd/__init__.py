@@ -66,6 +66,7 @@ def load_library():
         "fmmkmc_positions": (i32, [vp, vp]),
         "fmmkmc_potential": (i32, [vp, i64, vp, vp, vp]),
         "fmmkmc_multipole": (i32, [vp, i32, i64, vp]),
+        "fmmkmc_set_field": (i32, [vp, vp]),
         "fmmkmc_set_profiling": (i32, [vp, i32]),
         "fmmkmc_kernel_time": (i32, [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64)]),
         "fmmkmc_last_error": (C.c_char_p, [vp]),
@@ -274,6 +275,11 @@ class Context:
             ex = self._dev(exclude, torch.int64).reshape(-1)
         self._check(self._L.fmmkmc_potential(self._h, m, _ptr(xyz), _ptr(ex) if ex is not None else None, _ptr(out)))
         return out
+
+    def set_field(self, E):
+        """uniform external field: every hop adds -q E.d (see fmmkmc_set_field)"""
+        e = _host_f64(E, (3,))
+        self._check(self._L.fmmkmc_set_field(self._h, e.ctypes.data_as(C.c_void_p)))
 
     def multipole(self, level, cell):
         """Phi of one octree cell in the library's real storage ((p+1)^2 doubles, see

@@ -645,6 +645,7 @@ Geo make_geo(const fmmkmc_ctx *c)
     g.per_level = c->per_level;
     g.L = c->L;
     g.lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
+    for (int k = 0; k < 3; ++k) g.field[k] = c->field[k];
     return g;
 }
 
@@ -1002,6 +1003,15 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
         c->U += dUh;
         return FMMKMC_OK;
     })
+}
+
+int fmmkmc_set_field(fmmkmc_ctx *c, const double E[3])
+{
+    if (!c || !E) return FMMKMC_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(E[k])) return fail(c, FMMKMC_EINVAL, "field components must be finite");
+    for (int k = 0; k < 3; ++k) c->field[k] = E[k];
+    return FMMKMC_OK;
 }
 
 int fmmkmc_energy(fmmkmc_ctx *c, double *U)

@@ -424,6 +424,7 @@ struct fmmkmc_batch {
     std::vector<Phase> coarse_s2;  // per depth below the fine level (2x2x2 replicas)
     int slot_tc = 64, sweep_block = 256;
     bool per_level = false;  // replicas keep their local expansions per level (no sweep)
+    bool all_s2 = false;     // every replica has 2 x 2 x 2 sites per fine cell
     int Lmax = 0;
     int64_t slots_per_step = 0;
     // graph of one step
@@ -483,7 +484,7 @@ void record_step(fmmkmc_batch *b)
         for (int dpt = 0; dpt < (int)b->coarse_s2.size(); ++dpt)
             launch_b_coarse_s2(b->prof, s, b->reps, R, b->coarse_s2[dpt].d, b->coarse_s2[dpt].blocks, b->p, dpt);
     }
-    launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->p, b->mixed);
+    launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->p, b->mixed, b->all_s2);
     launch_b_slot(b->prof, s, b->reps, R, b->slot.d, b->slot.blocks, b->slot_tc);
     launch_prof(b->prof, s, "b_count", k_b_count, dim3((unsigned)b->count.blocks), dim3(256), 0, b->reps, R,
                 b->count.d, b->rates, b->wsum);
@@ -738,6 +739,8 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
     b->device = ctx[0]->device;
     b->mixed = ctx[0]->prec == FMMKMC_MIXED;
     b->per_level = ctx[0]->per_level != 0;
+    b->all_s2 = true;
+    for (int r = 0; r < n; ++r) b->all_s2 = b->all_s2 && ctx[r]->s2;
     for (int r = 0; r < n; ++r) b->Lmax = std::max(b->Lmax, ctx[r]->L);
     b->stream = (hipStream_t)stream;
     b->ctx.assign(ctx, ctx + n);
@@ -784,7 +787,7 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             const fmmkmc_ctx *c = ctx[r];
             const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
             const int q = c->p + 1;
-            nsite[r] = c->s2 ? (c->M + 127) / 128 : general_site_blocks(c->lat_n);
+            nsite[r] = c->s2 ? (b->all_s2 ? (c->M + 255) / 256 : (c->M + 127) / 128) : general_site_blocks(c->lat_n);
             ncount[r] = (c->N * K + kSelChunk - 1) / kSelChunk;
             npath[r] = ((int64_t)c->L * (q * (q + 1) / 2) + 255) / 256;
             const bool per = c->bc == FMMKMC_PERIODIC;
@@ -916,7 +919,7 @@ int fmmkmc_batch_tune(fmmkmc_batch *b, int rounds)
         const bool was = b->prof.on;
         b->prof.on = false;
         // slot gather: charges per block (reads the site potentials of the current configuration)
-        launch_b_site(b->prof, s, b->reps, b->R, b->site.d, b->site.blocks, b->p, b->mixed);
+        launch_b_site(b->prof, s, b->reps, b->R, b->site.d, b->site.blocks, b->p, b->mixed, b->all_s2);
         float best = 0;
         int best_tc = b->slot_tc;
         for (int tc : {32, 64, 128}) {

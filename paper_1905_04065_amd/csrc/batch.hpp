@@ -74,8 +74,10 @@ __device__ inline int find_rep(const int64_t *__restrict__ base, int R, int64_t 
 }
 
 // launchers of the batched kernels (grids: one block range per replica)
+// all_s2: every replica has 2 x 2 x 2 sites per fine cell (256 cells per block, 512 threads);
+// else 128 cells per block of such replicas and the general body's blocks for the others
 void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
-                   int p, bool mixed);
+                   int p, bool mixed, bool all_s2);
 void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                    int tc);
 // parts [part0, part0 + nparts) of every replica's move dU

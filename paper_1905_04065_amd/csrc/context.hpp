@@ -33,7 +33,20 @@ struct Geo {
     int per_level;   // local expansions kept per level (no L2L); evaluation sums the levels
     int L;           // levels (root = 1): the fine level
     int lstart;      // first level with an interaction list (periodic 2, free space 3)
+    double field[3];  // uniform external field E: a hop by d adds -q E.d
 };
+
+// displacement of a hop from r to t: t - r, in periodic boxes its minimum image
+__host__ __device__ inline double hop_component(const Geo &g, double d)
+{
+    return g.periodic ? d - g.a * floor(d / g.a + 0.5) : d;
+}
+
+// -E.d of a hop from r to t (times q: the field's share of its dU)
+__host__ __device__ inline double field_work(const Geo &g, double dx, double dy, double dz)
+{
+    return -(g.field[0] * hop_component(g, dx) + g.field[1] * hop_component(g, dy) + g.field[2] * hop_component(g, dz));
+}
 
 // entries of the 1/sqrt(k) table of the lattice near field (integer squared offsets)
 constexpr int kInvTab = 512;
@@ -80,6 +93,7 @@ struct fmmkmc_ctx {
     bool dev_ahead = false;  // batched steps moved charges: host mirrors are stale
     int near_tab_ok = 0;     // lattice: see Geo::tab_ok
     double U = 0;
+    double field[3] = {0.0, 0.0, 0.0};  // uniform external field (fmmkmc_set_field)
     std::string err;
     fmmkmc::Profiler prof;
 

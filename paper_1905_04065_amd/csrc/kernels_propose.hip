@@ -88,7 +88,6 @@ __global__ __launch_bounds__(256) void k_point_phi(Geo g, int64_t M, int64_t m, 
     if (g.per_level) phi += coarse_part<P>(g, psi_lv, px, py, pz, cx, cy, cz);
     // near field over the 27 neighbour cells
     double nearv = 0.0;
-    float nearf = 0.0f;
     for (int dx = -1; dx <= 1; ++dx)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dz = -1; dz <= 1; ++dz) {
@@ -106,19 +105,22 @@ __global__ __launch_bounds__(256) void k_point_phi(Geo g, int64_t M, int64_t m, 
                 const int64_t nb = cell_id(g.nc, ax, ay, az);
                 const bool unshifted = (shx == 0 && shy == 0 && shz == 0);
                 const int cn = cnt[nb];
+                // mixed: each cell's charges summed in FP32, the cells in FP64
+                float cellf = 0.0f;
                 for (int s = 0; s < cn; ++s) {
                     const int j = slots[nb * g.cap + s];
                     if (j == ex && unshifted) continue;
                     const double ex_ = px - (x[j] + shx), ey_ = py - (y[j] + shy), ez_ = pz - (z[j] + shz);
                     if (MIXED) {
                         const float fx = (float)ex_, fy = (float)ey_, fz = (float)ez_;
-                        nearf += (float)q[j] * __frsqrt_rn(fx * fx + fy * fy + fz * fz);
+                        cellf += (float)q[j] * __frsqrt_rn(fx * fx + fy * fy + fz * fz);
                     } else {
                         nearv += q[j] / sqrt(ex_ * ex_ + ey_ * ey_ + ez_ * ez_);
                     }
                 }
+                if (MIXED) nearv += (double)cellf;
             }
-    phi += MIXED ? (double)nearf : nearv;
+    phi += nearv;
     if (with_far) {
         const double hx = px - 0.5 * g.a, hy = py - 0.5 * g.a, hz = pz - 0.5 * g.a;
         phi += l2p<P, double>(H, 1, hx, hy, hz);
@@ -1093,7 +1095,7 @@ __device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_
     const auto dU = as_global(dU_);
     const auto mask = as_global(mask_);
     __shared__ int32_t soff[3 * kMaxHops];
-    __shared__ double sfhop[kMaxHops];
+    __shared__ double sfhop[kMaxHops], sfield[kMaxHops];
     __shared__ int32_t s_ijk[TC], s_ord[TC];
     __shared__ double s_q[TC], s_phi[TC];
     const int64_t r0 = blk * TC;
@@ -1109,6 +1111,7 @@ __device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_
             v = Fhop_[e];
         }
         sfhop[e] = v;
+        sfield[e] = field_work(g, g.h * offs[3 * e], g.h * offs[3 * e + 1], g.h * offs[3 * e + 2]);
     }
     if ((int)threadIdx.x < nloc) {
         const int64_t r = r0 + threadIdx.x;
@@ -1166,7 +1169,7 @@ __device__ __forceinline__ void slot_body(int64_t blk, Geo g, int64_t N, uint32_
             const double qi = s_q[c];
             const double corr = per_charge ? f[b] : sfhop[k];
             const bool valid = !__builtin_isnan(v[b]);
-            const double out = valid ? qi * (v[b] - s_phi[c]) + qi * qi * corr : nanv;
+            const double out = valid ? qi * (v[b] - s_phi[c] + sfield[k]) + qi * qi * corr : nanv;
             const int64_t o = (int64_t)s_ord[c] * K + k;
             dU[o] = out;
             if (mask) mask[o] = valid ? 1 : 0;
@@ -1473,6 +1476,7 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
             for (int k = threadIdx.x; k < nt; k += blockDim.x)
                 part += qi * (pl[(int64_t)k * Ml + tc] * Wt[k] - pl[(int64_t)k * Ml + rc] * Wr[k]);
         }
+        if (threadIdx.x == 0) part += qi * field_work(g, tx - rx, ty - ry, tz - rz);  // uniform field
         // self terms: one copy nu of the old position per lane, or the exact
         // self-image change with its Ewald terms split over the block
         if (g.periodic && g.self_exact) {
@@ -1709,7 +1713,7 @@ __global__ __launch_bounds__(256) void k_generic_combine(Geo g, int64_t S, const
     const int64_t i = charge[s];
     const double qi = q[i];
     const double tx = tw[3 * s], ty = tw[3 * s + 1], tz = tw[3 * s + 2];
-    double d = qi * (phit[s] - phir[s]);
+    double d = qi * (phit[s] - phir[s] + field_work(g, tx - x[i], ty - y[i], tz - z[i]));
     if (g.periodic && g.self_exact) {
         d += qi * qi * periodic_self_change(g.a, tx - x[i], ty - y[i], tz - z[i]) + far[s];
     } else if (g.periodic) {
@@ -1898,9 +1902,32 @@ void launch_b_coarse_s2(Profiler &pr, hipStream_t st, const RepDev *reps, int R,
 
 int64_t coarse_s2_level_blocks(int L, int level) { return coarse_s2_blocks(L, level); }
 
-void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
-                   int p, bool mixed)
+// every replica with 2 x 2 x 2 sites per fine cell: the 8-wave form of that
+// body (256 cells per block), as the single-context kernel runs it
+template <int P, bool MIXED>
+__global__ __launch_bounds__(512) void k_b_site_s2(const RepDev *__restrict__ reps, int R,
+                                                   const int64_t *__restrict__ base)
 {
+    __shared__ __align__(16) unsigned char smem[s2_smem_bytes<MIXED, 8>()];
+    const int r = find_rep(base, R, blockIdx.x);
+    const RepDev &d = reps[r];
+    site_s2_body<P, MIXED, 8>(blockIdx.x - base[r], d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz,
+                              d.Tax, d.phisite, d.phi_r, d.phicoarse, smem);
+}
+
+void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
+                   int p, bool mixed, bool all_s2)
+{
+    if (all_s2) {
+        if (mixed) {
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_s2<P_, true>, dim3((unsigned)blocks),
+                                             dim3(512), 0, reps, R, base));
+        } else {
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_s2<P_, false>, dim3((unsigned)blocks),
+                                             dim3(512), 0, reps, R, base));
+        }
+        return;
+    }
     if (mixed) {
         FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site<P_, true>, dim3((unsigned)blocks), dim3(256), 0,
                                        reps, R, base));

@@ -453,3 +453,26 @@ def test_per_level_round_trip_restores_state():
     f.accept(idx[s], xyz[idx[s]])
     for (l, c), b in zip(cells, before):
         assert np.max(np.abs(f.level_local(l, c) - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("bc", ["free", "periodic"])
+def test_uniform_field_adds_the_work_over_the_hop(bc):
+    """A uniform field E adds -q E.d to every proposal (d the hop; across a
+    periodic face the minimum image), exactly, and the energy of accepted moves
+    follows; the field term does not change the electrostatic part"""
+    n, N = 8, 40
+    sites, xyz, q = lattice(n, N, 29)
+    idx, tgt, valid = proposals(sites, n, bc == "periodic", W.HOPS26)
+    E = np.array([0.3, -0.2, 0.7])
+    f0 = O.FmmKmc(xyz, q, n, 3, 8, bc)
+    f1 = O.FmmKmc(xyz, q, n, 3, 8, bc, field=E)
+    d0 = f0.propose(idx[valid], tgt[valid])
+    d1 = f1.propose(idx[valid], tgt[valid])
+    disp = tgt[valid] - xyz[idx[valid]]
+    disp -= n * np.round(disp / n)  # the hop itself (the targets of wrapped hops lie across the box)
+    assert np.all(np.abs(disp) <= 1.0)
+    np.testing.assert_allclose(d1 - d0, -q[idx[valid]] * (disp @ E), rtol=0, atol=1e-13)
+    s = np.nonzero(valid)[0][3]
+    a0, a1 = f0.accept(idx[s], tgt[s]), f1.accept(idx[s], tgt[s])
+    assert a1 - a0 == pytest.approx(-q[idx[s]] * float((tgt[s] - xyz[idx[s]] - n * np.round((tgt[s] - xyz[idx[s]]) / n)) @ E),
+                                    abs=1e-13)
