@@ -44,7 +44,8 @@ FP32_PEAK_TFLOPS = 157.3
 P2L_FLOP = 850             # one P2L of a point charge at p = 12 (irregular recurrences + accumulation)
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {"site_phi_s2": "kernels_propose.hip", "slot_lattice": "kernels_propose.hip",
-                  "sweep": "kernels_commit.hip"}
+                  "sweep": "kernels_commit.hip", "b_site": "kernels_propose.hip", "b_slot": "kernels_propose.hip",
+                  "b_sweep": "kernels_commit.hip"}
 
 
 def log(msg):
@@ -752,6 +753,9 @@ def main():
                     help="leave out the runs with the exact self-image option")
     ap.add_argument("--skip-per-level", action="store_true",
                     help="leave out the runs with per-level local expansions")
+    ap.add_argument("--variants", default="exact,per_level,both",
+                    help="variants run beside the paper's terms: comma list of exact (exact self-image term), "
+                         "per_level (per-level expansions), both")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is "
@@ -769,11 +773,16 @@ def main():
     K = len(hops)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     res = {pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed) for pr in precs}
-    res_exact = {} if args.skip_exact_self else {
+    want = set(v.strip() for v in args.variants.split(",") if v.strip())
+    if args.skip_exact_self:
+        want -= {"exact", "both"}
+    if args.skip_per_level:
+        want -= {"per_level", "both"}
+    res_exact = {} if "exact" not in want else {
         pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, self_image="exact") for pr in precs}
-    res_levels = {} if args.skip_per_level else {
+    res_levels = {} if "per_level" not in want else {
         pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, per_level=True) for pr in precs}
-    res_both = {} if (args.skip_per_level or args.skip_exact_self) else {
+    res_both = {} if "both" not in want else {
         pr: run_gpu(pr, n, N, L, p, hops, args.steps, args.warmup, seed, per_level=True, self_image="exact")
         for pr in precs}
     copy_gbs = copy_bandwidth()
@@ -798,10 +807,12 @@ def main():
                     kernel_avg_us={k: (v[0] / max(v[1], 1) * 1e3) for k, v in kt.items() if v[1] > 0},
                     dominant=dom, rooflines=roof)
 
-    def graph_rooflines(r, pr, exact):
+    def graph_rooflines(r, pr, exact, counters=False):
         """rooflines of the kernels the device-driven step runs (HIP events around
-        plain launches of the batched kernels, one launch each per step)"""
+        plain launches of the batched kernels, one launch each per step);
+        counters: take HBM traffic from the committed rocprofv3 counters"""
         gk = r["graph_kernels"]
+        traffic = profiled_traffic(tag, pr) if counters else {}
         out_ = {}
         for name, kern in (("b_site", "site_phi_s2"), ("b_slot", "slot_lattice"), ("b_sweep", "sweep")):
             if name not in gk:
@@ -812,12 +823,12 @@ def main():
                 ach = amount / (us * 1e-6) / 1e9
                 out_[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": ach / HBM_PEAK_GBS, "frac_of_copy": ach / copy_gbs, "avg_us": us,
-                              "algorithmic_bytes": amount, "traffic": None}
+                              "algorithmic_bytes": amount, "traffic": traffic.get(name)}
             else:
                 ach = amount / (us * 1e-6) / 1e12
                 out_[name] = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": ach / FP64_PEAK_TFLOPS, "avg_us": us, "algorithmic_flop": amount,
-                              "traffic": None}
+                              "hbm_bytes": sweep_bytes(n, p, pr), "traffic": traffic.get(name)}
         if "b_site" in out_ and "b_slot" in out_:
             tb = out_["b_site"]["algorithmic_bytes"] + out_["b_slot"]["algorithmic_bytes"]
             tus = out_["b_site"]["avg_us"] + out_["b_slot"]["avg_us"]
@@ -830,13 +841,10 @@ def main():
         return out_
 
     head = summary(head_prec)
-    groof = graph_rooflines(res[head_prec], head_prec, False)
+    groof = graph_rooflines(res[head_prec], head_prec, False, counters=True)
     # the kernel of the headline (device-driven) step with the largest time per step
     gdom = max((k for k in ("b_site", "b_slot", "b_sweep") if k in groof), key=lambda k: groof[k]["avg_us"])
     droof = dict(groof[gdom])
-    if gdom == "b_sweep":
-        # HBM traffic from the committed counters of the same kernel body (single-context sweep)
-        droof["traffic"] = head["rooflines"]["sweep"]["traffic"] if head["rooflines"].get("sweep") else None
     out = {
         "metric": "dU proposals/sec at N=1e6, p=12 (FP64 vs mixed); accepted-move commit us",
         "value": head["value"],
@@ -880,7 +888,7 @@ def main():
                         "commit_us": m["commit_us"],
                         "dtype": "f32 fine-level evaluation, f64 difference/far field/commit",
                         "speedup_vs_fp64": head["ms_per_step"] / m["ms_per_step"],
-                        "graph_step_rooflines": graph_rooflines(res["mixed"], "mixed", False),
+                        "graph_step_rooflines": graph_rooflines(res["mixed"], "mixed", False, counters=True),
                         "graph_step_kernel_us": res["mixed"]["graph_kernels"],
                         "host_driven_kernel_avg_us": m["kernel_avg_us"]}
     notes = {"exact_self_image": "self_image=1: the moving charge's own copies by the exact Ewald change per hop "
