@@ -172,6 +172,7 @@ void release(fmmkmc_ctx *c)
     c->far.K = nullptr;  // alias of phi_lv[1]
     dfree(c->F);
     dfree(c->Fhop);
+    dfree(c->frow_w);
     dfree(c->d_offsets);
     dfree(c->scr);
     dfree(c->flags);
@@ -864,6 +865,7 @@ int fmmkmc_propose_lattice(fmmkmc_ctx *c, int K, const int32_t *offsets, double 
                 }
                 dfree(c->F);
                 c->F = dalloc<double>((size_t)c->N * K);
+                if (!c->frow_w) c->frow_w = dalloc<double>(c->nt);
                 launch_f_rows(c, g, c->N, K, 0);
             }
             c->F_offsets = off;
@@ -930,11 +932,10 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
         // fine-level expansions or what the sweep reads.
         const bool need_row = c->bc == FMMKMC_PERIODIC && !c->self_exact && c->F && !c->F_offsets.empty();
         const int Krow = (int)c->F_offsets.size() / 3;
-        bool row_launched = false;
         HIPCHK(hipEventRecord(c->ev_fork, c->stream));
         HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
         launch_move_dU(c, g, i, np, dUd, c->aux, 1, kMoveParts - 1);
-        if (need_row) row_launched = launch_f_row1(c, g, Krow, c->hrank[i], new_site, c->aux);
+        if (need_row) launch_f_row1(c, g, Krow, c->hrank[i], new_site, c->aux);
         // C2 + C3
         CommitArgs a;
         a.i = i;
@@ -993,7 +994,6 @@ int fmmkmc_accept(fmmkmc_ctx *c, int64_t i, const double new_xyz[3], double *dU_
             c->hsite_charge[new_site] = (int32_t)i;
             c->hsite[i] = (int32_t)new_site;
         }
-        if (need_row && !row_launched) launch_f_rows(c, g, 1, Krow, c->hrank[i]);  // reads the updated site table
         double parts[kMoveParts];
         HIPCHK(hipMemcpyAsync(parts, dUd, sizeof(parts), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));

@@ -643,6 +643,7 @@ RepDev make_rep(const fmmkmc_ctx *c, int K, double *dU, uint8_t *mask)
     d.phi_r = c->phi_r;
     d.F = (c->bc == FMMKMC_PERIODIC && !c->self_exact) ? c->F : nullptr;
     d.Fhop = (c->bc == FMMKMC_PERIODIC && c->self_exact) ? c->Fhop : nullptr;
+    d.frow_w = c->frow_w;
     d.offsets = c->d_offsets;
     d.dU = dU;
     d.mask = mask;
@@ -729,7 +730,6 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
         if (c->N * (int64_t)K >= ((int64_t)1 << 32)) return FMMKMC_EINVAL;
         if (c->per_level != ctx[0]->per_level) return FMMKMC_EINVAL;
     }
-    if (f_row1_shm(ctx[0]->nt, K) > 64 * 1024) return FMMKMC_EINVAL;
     fmmkmc_batch *b = new (std::nothrow) fmmkmc_batch();
     if (!b) return FMMKMC_ENOMEM;
     b->R = n;

@@ -37,6 +37,7 @@ struct RepDev {
     int32_t *order, *ijk_r;
     double *q_r, *phi_r, *F;
     double *Fhop;  // exact self-image option: per-hop table instead of F
+    double *frow_w;  // the F row of a moved charge: R K1 at its new site (nt)
     // hops and the proposal output of this replica ([charge][hop])
     int32_t *offsets;
     double *dU;
@@ -85,7 +86,6 @@ void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, cons
 // L - 1 in per-level mode)
 void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, double *acc,
                       int nt, int part0, int nparts, int nlev_max);
-size_t f_row1_shm(int nt, int K);
 void launch_b_frow(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, int nt, int K);
 void launch_b_sweep(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                     int p, const MoveDev *moves, int block);

@@ -138,6 +138,7 @@ struct fmmkmc_ctx {
     int self_exact = 0;
     double *F = nullptr;
     double *Fhop = nullptr;
+    double *frow_w = nullptr;         // F row of a moved charge: R K1 at its new site (nt)
     std::vector<int32_t> F_offsets;   // 3K ints the table was built for
     int32_t *d_offsets = nullptr;     // device copy of the current hop offsets
     int d_offsets_K = 0;

@@ -125,9 +125,8 @@ void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int n
 constexpr int kMoveParts = 4;
 void launch_move_dU(fmmkmc_ctx *c, const Geo &g, int64_t i, const double t[3], double *out,
                     hipStream_t st = nullptr, int part0 = 0, int nparts = kMoveParts);
-// F row of one charge (rank, lattice site s) on stream st; false (nothing
-// launched) when its tables exceed the kernel's LDS, then use launch_f_rows
-bool launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t s, hipStream_t st);
+// F row of one charge (rank, its new lattice site s) on stream st
+void launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t s, hipStream_t st);
 // sweep on the context stream; path and bookkeeping on side (they touch neither
 // the fine-level expansions nor anything the sweep reads)
 void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a, hipStream_t side);

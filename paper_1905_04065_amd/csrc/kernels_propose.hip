@@ -1304,86 +1304,95 @@ __global__ __launch_bounds__(256) void k_f_rows(Geo g, int p, int64_t count, con
     }
 }
 
-// F row of one charge (after an accept): K target harmonics in LDS, w = R K1(r)
-// with each output split over 16 lanes, then one dot product per hop.
-__device__ __forceinline__ void f_row1_body(Geo g, int p, int64_t rank, int64_t s_site, int K,
-                                            const int32_t *__restrict__ offs, const double *__restrict__ R,
-                                            const double *__restrict__ sigma, double *__restrict__ F)
+// F row of one charge (after an accept), in two launches so that no block
+// walks a long chain of dependent loads:
+//   1. w = R K1(r), the V_inf local expansion of a unit charge at the charge's
+//      new site r: kFrowRows rows of w per block, each row split over 16 lanes;
+//   2. one 64-lane block per hop k: the weights W(t_k) of its wrapped target,
+//      B_k = W(t_k) . w, the 27 self distances, and F[rank][k].
+constexpr int kFrowRows = 16;
+
+__host__ __device__ constexpr int frow_w_blocks(int nt)
+{
+    return (nt + kFrowRows - 1) / kFrowRows;
+}
+
+__device__ __forceinline__ void frow_w_body(int blk, Geo g, int p, int64_t s_site, const double *__restrict__ R,
+                                            double *__restrict__ w)
 {
     const int nt = nterms(p);
-    extern __shared__ double sm[];
-    double *Wt = sm, *K1 = sm + (int64_t)K * nt, *w = K1 + nt, *Wr = w + nt, *red = Wr + nt;  // red: 256
-    double *selfv = red + 256;                                                              // 27 K
-    const int n = g.n;
-    const int s = (int)s_site;
+    __shared__ double K1[(kMaxOrder + 1) * (kMaxOrder + 1)], Wd[(kMaxOrder + 1) * (kMaxOrder + 1)];
+    __shared__ double red[256];
+    const int n = g.n, s = (int)s_site;
     const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
     const double c = 0.5 * g.a;
-    const double rx = (si + 0.5) * g.h, ry = (sj + 0.5) * g.h, rz = (sk + 0.5) * g.h;
     const int tid = threadIdx.x;
-    // weights of every hop target and the unit multipole of the charge's site,
-    // one lane per (point, column m); then 1/|t - r - a nu| per (hop, copy nu)
-    const int ncol = p + 1;
-    for (int task = tid; task < (K + 1) * ncol; task += blockDim.x) {
-        const int pt = task / ncol, m = task - pt * ncol;
-        if (pt < K) {
-            const int ti = posmod(si + offs[3 * pt], n), tj = posmod(sj + offs[3 * pt + 1], n),
-                      tk = posmod(sk + offs[3 * pt + 2], n);
-            harmonics_column(p, m, (ti + 0.5) * g.h - c, (tj + 0.5) * g.h - c, (tk + 0.5) * g.h - c, nullptr,
-                             Wt + (int64_t)pt * nt);
-        } else {
-            harmonics_column(p, m, rx - c, ry - c, rz - c, K1, Wr);
-        }
-    }
-    for (int task = tid; task < 27 * K; task += blockDim.x) {
-        const int hk = task / 27, nu = task - hk * 27;
-        const int ti = posmod(si + offs[3 * hk], n), tj = posmod(sj + offs[3 * hk + 1], n),
-                  tk = posmod(sk + offs[3 * hk + 2], n);
-        const double d0 = (ti + 0.5) * g.h - rx - g.a * (nu / 9 - 1), d1 = (tj + 0.5) * g.h - ry - g.a * ((nu / 3) % 3 - 1),
-                     d2 = (tk + 0.5) * g.h - rz - g.a * (nu % 3 - 1);
-        selfv[task] = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    }
+    if (tid <= p) harmonics_column(p, tid, (si + 0.5) * g.h - c, (sj + 0.5) * g.h - c, (sk + 0.5) * g.h - c, K1, Wd);
     __syncthreads();
-    // w = R K1: rows split over 16 lanes
-    for (int r0 = 0; r0 < nt; r0 += 16) {
-        const int lr = tid & 15, ls = tid >> 4, row = r0 + lr;
-        double acc = 0.0;
-        if (row < nt)
-            for (int m = ls; m < nt; m += 16) acc += R[(int64_t)m * nt + row] * K1[m];
-        red[tid] = acc;
-        __syncthreads();
-        if (ls == 0 && row < nt) {
-            double sum = 0.0;
-            for (int t = 0; t < 16; ++t) sum += red[t * 16 + lr];
-            w[row] = sum;
-        }
-        __syncthreads();
-    }
-    // B_k = W(t_k) . w, hops split over 256 / K lanes each (at least 4)
-    const int per = blockDim.x / K;
-    double b = 0.0;
-    const int hk = tid / per, ls = tid % per;
-    if (hk < K)
-        for (int m = ls; m < nt; m += per) b += Wt[(int64_t)hk * nt + m] * w[m];
-    red[tid] = b;
+    const int lr = tid & 15, ls = tid >> 4, row = blk * kFrowRows + lr;
+    double acc = 0.0;
+    if (row < nt)
+        for (int m = ls; m < nt; m += 16) acc += R[(int64_t)m * nt + row] * K1[m];
+    red[tid] = acc;
     __syncthreads();
-    if (tid < K) {
-        double B = 0.0;
-        for (int t = 0; t < per; ++t) B += red[tid * per + t];
-        const int ti = posmod(si + offs[3 * tid], n), tj = posmod(sj + offs[3 * tid + 1], n),
-                  tk = posmod(sk + offs[3 * tid + 2], n);
-        double self = 0.0;
-        for (int nu = 0; nu < 27; ++nu) self += selfv[tid * 27 + nu];
-        const double cbox = (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
-        const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
-        F[rank * K + tid] = -self + cbox + 0.5 * (sigma[ts] + sigma[s]) - B;
+    if (ls == 0 && row < nt) {
+        double sum = 0.0;
+        for (int t = 0; t < 16; ++t) sum += red[t * 16 + lr];
+        w[row] = sum;
     }
 }
 
-__global__ __launch_bounds__(256) void k_f_row1(Geo g, int p, int64_t rank, int64_t s_site, int K,
-                                                const int32_t *__restrict__ offs, const double *__restrict__ R,
-                                                const double *__restrict__ sigma, double *__restrict__ F)
+__device__ __forceinline__ void frow_b_body(int k, Geo g, int p, int64_t rank, int64_t s_site, int K,
+                                            const int32_t *__restrict__ offs, const double *__restrict__ w,
+                                            const double *__restrict__ sigma, double *__restrict__ F)
 {
-    f_row1_body(g, p, rank, s_site, K, offs, R, sigma, F);
+    const int nt = nterms(p);
+    __shared__ double Wt[(kMaxOrder + 1) * (kMaxOrder + 1)];
+    __shared__ double red[64], selfv[27];
+    const int n = g.n, s = (int)s_site;
+    const int si = s / (n * n), sj = (s / n) % n, sk = s % n;
+    const double c = 0.5 * g.a;
+    const int tid = threadIdx.x;
+    const int ti = posmod(si + offs[3 * k], n), tj = posmod(sj + offs[3 * k + 1], n),
+              tk = posmod(sk + offs[3 * k + 2], n);
+    const double tx = (ti + 0.5) * g.h, ty = (tj + 0.5) * g.h, tz = (tk + 0.5) * g.h;
+    if (tid <= p) harmonics_column(p, tid, tx - c, ty - c, tz - c, nullptr, Wt);
+    if (tid >= 32 && tid < 32 + 27) {
+        const int nu = tid - 32;
+        const double d0 = tx - (si + 0.5) * g.h - g.a * (nu / 9 - 1),
+                     d1 = ty - (sj + 0.5) * g.h - g.a * ((nu / 3) % 3 - 1),
+                     d2 = tz - (sk + 0.5) * g.h - g.a * (nu % 3 - 1);
+        selfv[nu] = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    __syncthreads();
+    double b = 0.0;
+    for (int m = tid; m < nt; m += 64) b += Wt[m] * w[m];
+    red[tid] = b;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double self = 0.0;
+        for (int nu = 0; nu < 27; ++nu) self += selfv[nu];
+        const double cbox = (6.0 + 8.0 / sqrt(3.0) + 12.0 / sqrt(2.0)) / g.a;
+        const int64_t ts = ((int64_t)ti * n + tj) * n + tk;
+        F[rank * K + k] = -self + cbox + 0.5 * (sigma[ts] + sigma[s]) - red[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_frow_w(Geo g, int p, int64_t s_site, const double *__restrict__ R,
+                                                double *__restrict__ w)
+{
+    frow_w_body(blockIdx.x, g, p, s_site, R, w);
+}
+
+__global__ __launch_bounds__(64) void k_frow_b(Geo g, int p, int64_t rank, int64_t s_site, int K,
+                                               const int32_t *__restrict__ offs, const double *__restrict__ w,
+                                               const double *__restrict__ sigma, double *__restrict__ F)
+{
+    frow_b_body(blockIdx.x, g, p, rank, s_site, K, offs, w, sigma, F);
 }
 
 void launch_sigma(fmmkmc_ctx *c, const Geo &g)
@@ -1394,13 +1403,12 @@ void launch_sigma(fmmkmc_ctx *c, const Geo &g)
                c->far.R, c->far.sigma);
 }
 
-bool launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t site, hipStream_t st)
+void launch_f_row1(fmmkmc_ctx *c, const Geo &g, int K, int64_t rank, int64_t site, hipStream_t st)
 {
-    const size_t shm1 = sizeof(double) * ((size_t)(K + 3) * c->nt + 256 + 27 * (size_t)K);
-    if (shm1 > 64 * 1024) return false;
-    launch_on(c, st, "f_row1", k_f_row1, dim3(1), dim3(256), shm1, g, c->p, rank, site, K, c->d_offsets, c->far.R,
+    launch_on(c, st, "f_row1", k_frow_w, dim3(frow_w_blocks(c->nt)), dim3(256), 0, g, c->p, site, c->far.R,
+              c->frow_w);
+    launch_on(c, st, "f_row1", k_frow_b, dim3(K), dim3(64), 0, g, c->p, rank, site, K, c->d_offsets, c->frow_w,
               c->far.sigma, c->F);
-    return true;
 }
 
 void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, int K, int64_t first)
@@ -1848,14 +1856,26 @@ __global__ __launch_bounds__(256) void k_b_move_dU(const RepDev *__restrict__ re
                  d.R, d.H, acc + (int64_t)r * kMoveParts, d.psi_lv);
 }
 
-// the moved charge's F row, one block per replica (periodic replicas)
-__global__ __launch_bounds__(256) void k_b_frow(const RepDev *__restrict__ reps, const MoveDev *__restrict__ moves)
+// the moved charge's F row (periodic replicas): w blocks per replica, then K
+// one-wave blocks per replica (blocks past a replica's hop count return)
+__global__ __launch_bounds__(256) void k_b_frow_w(const RepDev *__restrict__ reps, const MoveDev *__restrict__ moves,
+                                                  int nblk)
 {
-    const int r = blockIdx.x;
+    const int r = blockIdx.x / nblk;
     const MoveDev &mv = moves[r];
     const RepDev &d = reps[r];
     if (!mv.valid || !d.F) return;
-    f_row1_body(d.g, d.p, mv.rank, mv.new_site, d.K, d.offsets, d.R, d.sigma, d.F);
+    frow_w_body(blockIdx.x % nblk, d.g, d.p, mv.new_site, d.R, d.frow_w);
+}
+
+__global__ __launch_bounds__(64) void k_b_frow_b(const RepDev *__restrict__ reps, const MoveDev *__restrict__ moves,
+                                                 int Kmax)
+{
+    const int r = blockIdx.x / Kmax, k = blockIdx.x % Kmax;
+    const MoveDev &mv = moves[r];
+    const RepDev &d = reps[r];
+    if (!mv.valid || !d.F || k >= d.K) return;
+    frow_b_body(k, d.g, d.p, mv.rank, mv.new_site, d.K, d.offsets, d.frow_w, d.sigma, d.F);
 }
 
 // per-level mode: the coarser levels at every site of every replica.  General
@@ -1956,11 +1976,11 @@ void launch_b_move_dU(Profiler &pr, hipStream_t st, const RepDev *reps, int R, c
                 dim3(256), shm, reps, moves, acc, part0, nparts);
 }
 
-size_t f_row1_shm(int nt, int K) { return sizeof(double) * ((size_t)(K + 3) * nt + 256 + 27 * (size_t)K); }
-
 void launch_b_frow(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves, int nt, int K)
 {
-    launch_prof(pr, st, "b_frow", k_b_frow, dim3((unsigned)R), dim3(256), f_row1_shm(nt, K), reps, moves);
+    const int nblk = frow_w_blocks(nt);
+    launch_prof(pr, st, "b_frow", k_b_frow_w, dim3((unsigned)(R * nblk)), dim3(256), 0, reps, moves, nblk);
+    launch_prof(pr, st, "b_frow", k_b_frow_b, dim3((unsigned)(R * K)), dim3(64), 0, reps, moves, K);
 }
 
 }  // namespace fmmkmc
