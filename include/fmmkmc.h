@@ -182,7 +182,7 @@ int fmmkmc_potential(fmmkmc_ctx *c, int64_t m, const double *xyz, const int64_t 
  * range), ESTATE (not initialised), EHIP. */
 int fmmkmc_multipole(fmmkmc_ctx *c, int level, int64_t cell, double *out);
 
-/* Per-kernel timing: when on,/* Per-kernel timing: when on, every kernel launch is bracketed by HIP events
+/* Per-kernel timing: when on, every kernel launch is bracketed by HIP events
  * on the context's stream.  fmmkmc_kernel_time() returns the accumulated time
  * (ms) and launch count of the named kernel since profiling was switched on. */
 int fmmkmc_set_profiling(fmmkmc_ctx *c, int on);
