@@ -318,14 +318,15 @@ def run_batched(precision, steps, warmup, seed, tune=True, keep=False, per_level
     wall = time.perf_counter() - t0
     # per-phase times over a few more steps as plain launches
     b.set_profiling(True)
-    b.step(rng.random((3, R)))
+    nprof = 3
+    b.step(rng.random((nprof, R)))
     phases = {}
     for name in ["b_coarse", "b_coarse_s2", "b_site", "b_slot", "b_count", "b_select", "b_move_dU", "b_move_dU_side",
                  "b_frow", "b_sweep", "b_levels", "b_path", "b_book", "b_far_refresh", "b_cheb_a", "b_cheb_b",
                  "b_finish"]:
         ms, n = b.kernel_time(name)
         if n:
-            phases[name] = ms / n * 1e3
+            phases[name] = ms / nprof * 1e3  # per step (some phases are several launches)
     b.set_profiling(False)
     moved_frac = float((moved.cpu().numpy() >= 0).mean())
     b.close()

@@ -526,10 +526,12 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
             // charge per site in site order (0 on a vacant site)
             std::vector<double> qs(ns, 0.0);
             std::vector<float> qs32(ns, 0.0f);
+            bool q32exact = true;
             for (int64_t i = 0; i < n; ++i) {
                 const int64_t so = site_order(c, c->hsite[i]);
                 qs[so] = c->hq[i];
                 qs32[so] = (float)c->hq[i];
+                q32exact = q32exact && (double)qs32[so] == c->hq[i];
             }
             // per axis, the first and last lattice plane of every fine cell (the
             // cell of a site is the cell of its position, as for any point):
@@ -564,7 +566,9 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
             c->near_tab_ok = 3 * (span - 1) * (span - 1) < kInvTab ? 1 : 0;
             c->qsite = dalloc<double>(ns);
             upload(c->qsite, qs.data(), ns, s);
-            if (c->prec == FMMKMC_MIXED) {
+            // FP32 site charges: the mixed near field, and the FP64 one of general
+            // lattices when no charge is rounded by FP32
+            if (c->prec == FMMKMC_MIXED || (!c->s2 && q32exact)) {
                 c->qsite32 = dalloc<float>(ns);
                 upload(c->qsite32, qs32.data(), ns, s);
             }
@@ -646,6 +650,7 @@ Geo make_geo(const fmmkmc_ctx *c)
     g.per_level = c->per_level;
     g.L = c->L;
     g.lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
+    g.q32 = c->qsite32 ? 1 : 0;
     for (int k = 0; k < 3; ++k) g.field[k] = c->field[k];
     return g;
 }

@@ -420,11 +420,10 @@ struct fmmkmc_batch {
     double *out_dU = nullptr, *out_dt = nullptr;
     int cap_steps = 0;
     // phases
-    Phase site, slot, count, sweep, path, far, cheb_a, cheb_b, coarse;
+    Phase site, site_lf, site_gen, slot, count, sweep, path, far, cheb_a, cheb_b, coarse;
     std::vector<Phase> coarse_s2;  // per depth below the fine level (2x2x2 replicas)
     int slot_tc = 64, sweep_block = 256;
     bool per_level = false;  // replicas keep their local expansions per level (no sweep)
-    bool all_s2 = false;     // every replica has 2 x 2 x 2 sites per fine cell
     int Lmax = 0;
     int64_t slots_per_step = 0;
     // graph of one step
@@ -484,7 +483,8 @@ void record_step(fmmkmc_batch *b)
         for (int dpt = 0; dpt < (int)b->coarse_s2.size(); ++dpt)
             launch_b_coarse_s2(b->prof, s, b->reps, R, b->coarse_s2[dpt].d, b->coarse_s2[dpt].blocks, b->p, dpt);
     }
-    launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->p, b->mixed, b->all_s2);
+    launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->site_lf.d, b->site_lf.blocks, b->site_gen.d,
+                  b->site_gen.blocks, b->p, b->mixed);
     launch_b_slot(b->prof, s, b->reps, R, b->slot.d, b->slot.blocks, b->slot_tc);
     launch_prof(b->prof, s, "b_count", k_b_count, dim3((unsigned)b->count.blocks), dim3(256), 0, b->reps, R,
                 b->count.d, b->rates, b->wsum);
@@ -585,8 +585,8 @@ void release_batch(fmmkmc_batch *b)
     dfree(b->out_dU);
     dfree(b->out_dt);
     for (Phase &ph : b->coarse_s2) dfree(ph.d);
-    for (Phase *ph : {&b->site, &b->slot, &b->count, &b->sweep, &b->path, &b->far, &b->cheb_a, &b->cheb_b,
-                      &b->coarse})
+    for (Phase *ph : {&b->site, &b->site_lf, &b->site_gen, &b->slot, &b->count, &b->sweep, &b->path, &b->far,
+                      &b->cheb_a, &b->cheb_b, &b->coarse})
         dfree(ph->d);
     for (auto &pd : b->prof.pending) {
         (void)hipEventDestroy(pd.a);
@@ -739,8 +739,6 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
     b->device = ctx[0]->device;
     b->mixed = ctx[0]->prec == FMMKMC_MIXED;
     b->per_level = ctx[0]->per_level != 0;
-    b->all_s2 = true;
-    for (int r = 0; r < n; ++r) b->all_s2 = b->all_s2 && ctx[r]->s2;
     for (int r = 0; r < n; ++r) b->Lmax = std::max(b->Lmax, ctx[r]->L);
     b->stream = (hipStream_t)stream;
     b->ctx.assign(ctx, ctx + n);
@@ -782,12 +780,15 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
         upload(b->U, U.data(), n, s);
         b->step = dalloc<int32_t>(1);
         // phase block tables
-        std::vector<int64_t> nsite(n), ncount(n), npath(n), nfar(n), na(n), nb(n), ncoarse(n);
+        std::vector<int64_t> nsite(n), nsite_lf(n), nsite_gen(n), ncount(n), npath(n), nfar(n), na(n), nb(n),
+            ncoarse(n);
         for (int r = 0; r < n; ++r) {
             const fmmkmc_ctx *c = ctx[r];
             const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
             const int q = c->p + 1;
-            nsite[r] = c->s2 ? (b->all_s2 ? (c->M + 255) / 256 : (c->M + 127) / 128) : general_site_blocks(c->lat_n);
+            nsite[r] = c->s2 ? (c->M + 255) / 256 : 0;
+            nsite_lf[r] = c->s2 ? 0 : (ns + 255) / 256;
+            nsite_gen[r] = c->s2 ? 0 : general_site_blocks(c->lat_n, c->nc);
             ncount[r] = (c->N * K + kSelChunk - 1) / kSelChunk;
             npath[r] = ((int64_t)c->L * (q * (q + 1) / 2) + 255) / 256;
             const bool per = c->bc == FMMKMC_PERIODIC;
@@ -812,6 +813,8 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             }
         }
         set_phase(b->site, nsite, s);
+        set_phase(b->site_lf, nsite_lf, s);
+        set_phase(b->site_gen, nsite_gen, s);
         set_phase(b->count, ncount, s);
         set_phase(b->path, npath, s);
         set_phase(b->far, nfar, s);
@@ -919,7 +922,8 @@ int fmmkmc_batch_tune(fmmkmc_batch *b, int rounds)
         const bool was = b->prof.on;
         b->prof.on = false;
         // slot gather: charges per block (reads the site potentials of the current configuration)
-        launch_b_site(b->prof, s, b->reps, b->R, b->site.d, b->site.blocks, b->p, b->mixed, b->all_s2);
+        launch_b_site(b->prof, s, b->reps, b->R, b->site.d, b->site.blocks, b->site_lf.d, b->site_lf.blocks,
+                      b->site_gen.d, b->site_gen.blocks, b->p, b->mixed);
         float best = 0;
         int best_tc = b->slot_tc;
         for (int tc : {32, 64, 128}) {

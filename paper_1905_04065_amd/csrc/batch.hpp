@@ -75,10 +75,13 @@ __device__ inline int find_rep(const int64_t *__restrict__ base, int R, int64_t 
 }
 
 // launchers of the batched kernels (grids: one block range per replica)
-// all_s2: every replica has 2 x 2 x 2 sites per fine cell (256 cells per block, 512 threads);
-// else 128 cells per block of such replicas and the general body's blocks for the others
-void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
-                   int p, bool mixed, bool all_s2);
+// site potentials: replicas with 2 x 2 x 2 sites per fine cell (256 cells per
+// 512-thread block), then the two passes of the general-lattice replicas (the
+// local expansion, far field and coarse levels per site; the near field), one
+// launch each (a replica has blocks in the s2 table or in the other two)
+void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base_s2,
+                   int64_t blocks_s2, const int64_t *base_lf, int64_t blocks_lf, const int64_t *base_gen,
+                   int64_t blocks_gen, int p, bool mixed);
 void launch_b_slot(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                    int tc);
 // parts [part0, part0 + nparts) of every replica's move dU

@@ -33,6 +33,8 @@ struct Geo {
     int per_level;   // local expansions kept per level (no L2L); evaluation sums the levels
     int L;           // levels (root = 1): the fine level
     int lstart;      // first level with an interaction list (periodic 2, free space 3)
+    int q32;         // lattice: an FP32 copy of the site charges exists (mixed precision, or every
+                     // charge is exactly an FP32 number)
     double field[3];  // uniform external field E: a hop by d adds -q E.d
 };
 

@@ -71,6 +71,54 @@ struct RecTables {
     }
 };
 
+// L2P (the same sum as l2p() in solid.hpp) for the lane's fine cell of
+// coefficient-major expansions (coefficient k of cell c at base[k * M + c]),
+// fully unrolled: every coefficient load is issued up front, each a uniform
+// column start plus the lane's 32-bit cell offset, for kernels that can spend
+// the registers on having them all in flight.
+template <int P, typename T, bool SKIP0 = false>
+__device__ inline T l2p_cell(gptr<const T> base, int64_t M, uint32_t cell, T x, T y, T z)
+{
+    auto L = [&](int k) { return (base + (int64_t)k * M)[cell]; };
+    const T r2 = x * x + y * y + z * z;
+    T acc0 = SKIP0 ? T(0) : L(0);
+    T cm2 = T(1), cm1 = z;
+    if (P >= 1) acc0 += L(slot0(1)) * z;
+#pragma unroll
+    for (int n = 2; n <= P; ++n) {
+        const T c = ((T)(2 * n - 1) * z * cm1 - r2 * cm2) * (T)rinv(n, 0);
+        acc0 += L(slot0(n)) * c;
+        cm2 = cm1;
+        cm1 = c;
+    }
+    T acc1 = T(0);
+    T dr = T(1), di = T(0);
+#pragma unroll
+    for (int m = 1; m <= P; ++m) {
+        const T f = (T)(-0.5 / m);
+        const T ndr = f * (x * dr - y * di), ndi = f * (x * di + y * dr);
+        dr = ndr;
+        di = ndi;
+        T ar = dr, ai = di;
+        acc1 += L(slot_re(m, m)) * ar + L(slot_im(m, m)) * ai;
+        if (m + 1 <= P) {
+            T br = z * ar, bi = z * ai;
+            acc1 += L(slot_re(m + 1, m)) * br + L(slot_im(m + 1, m)) * bi;
+#pragma unroll
+            for (int n = m + 2; n <= P; ++n) {
+                const T w = (T)rinv(n, m);
+                const T cr = ((T)(2 * n - 1) * z * br - r2 * ar) * w, ci = ((T)(2 * n - 1) * z * bi - r2 * ai) * w;
+                acc1 += L(slot_re(n, m)) * cr + L(slot_im(n, m)) * ci;
+                ar = br;
+                ai = bi;
+                br = cr;
+                bi = ci;
+            }
+        }
+    }
+    return acc0 + T(2) * acc1;
+}
+
 // L2P (the same sum as l2p() in solid.hpp) with the orders m >= 1 in a rolled
 // loop: one column's coefficients are live at a time, so the compiler cannot
 // hoist all (p+1)^2 loads at once and the caller keeps a small register

@@ -105,7 +105,7 @@ void launch_slot_lattice(fmmkmc_ctx *c, const Geo &g, int K, double *dU, uint8_t
 // exact self-image option: Fhop[k] = G_self - G(h offsets[k]) for the K hops
 void launch_self_hops(fmmkmc_ctx *c, int K);
 // blocks of the general-geometry site kernel for an n^3 lattice
-int64_t general_site_blocks(int n);
+int64_t general_site_blocks(int n, int nc);
 void launch_sigma(fmmkmc_ctx *c, const Geo &g);
 // F rows of the charges of ranks first..first+count-1
 void launch_f_rows(fmmkmc_ctx *c, const Geo &g, int64_t count, int K, int64_t first);

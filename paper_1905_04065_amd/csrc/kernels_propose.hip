@@ -209,8 +209,21 @@ constexpr int gen_smem_bytes()
     return (int)((2 * kInvTab + gen_tile_q<MIXED>() + kTilePad) * (MIXED ? sizeof(float) : sizeof(double))) + 32;
 }
 
+// Blocks of the general-lattice near field: one fine cell cx along x (the x-planes
+// of that cell) and a chunk of kGenSites (y, z) sites of the plane; a plane of
+// n^2 sites takes ceil(n^2 / kGenSites) chunks, lanes past its end idle.
+// Lane t of chunk ch: the (y, z) site of the plane.
+__device__ inline bool gen_yz(int ch, int n, int t, int &sj, int &sk)
+{
+    const int loc = ch * kGenSites + t;
+    const bool active = loc < n * n;
+    sj = active ? loc / n : 0;
+    sk = active ? loc - (loc / n) * n : 0;
+    return active;
+}
+
 template <int P, bool MIXED>
-__device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi_,
+__device__ __forceinline__ void site_general_boxrows(int si, int ch, Geo g, int64_t M, const double *__restrict__ psi_,
                                                   const float *__restrict__ psi32_, const double *__restrict__ Bz_,
                                                   const double *__restrict__ Tax_, const double *__restrict__ qsite_,
                                                   const float *__restrict__ qsite32_,
@@ -232,9 +245,9 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
     int *sLo = (int *)(sQ + gen_tile_q<MIXED>() + kTilePad), *sHi = sLo + 3, *sNz = sHi + 3;
     const int n = g.n, nc = g.nc;
     const int t = threadIdx.x;
-    const int64_t s = blk * kGenSites + t;
-    const bool active = s < (int64_t)n * n * n;  // lane 0 always is
-    const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
+    int sj, sk;
+    const bool active = gen_yz(ch, n, t, sj, sk);  // lane 0 always is
+    const int64_t s = ((int64_t)si * n + sj) * n + sk;
     for (int e = t; e < kTab; e += blockDim.x) sInv[e] = e < kInvTab ? (Real)IT.v[e] : Real(0);
     if (t < 3) {
         sLo[t] = 0x7fffffff;
@@ -289,13 +302,32 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         }
     }
     __syncthreads();
-    if (gen_tile_q<MIXED>() > 0 && active) {
+    if (gen_tile_q<MIXED>() > 0) {
+        // union of the lanes' boxes: a butterfly over each wave (lane-varying
+        // values into an LDS atomic would be serialised lane by lane), then one
+        // atomic per wave
+        int v[7];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            atomicMin(&sLo[ax], blo[ax]);
-            atomicMax(&sHi[ax], bhi[ax]);
+            v[ax] = active ? blo[ax] : 0x7fffffff;
+            v[3 + ax] = active ? bhi[ax] : -0x7fffffff;
         }
-        atomicMax(sNz, bhi[2] - blo[2] + 1);
+        v[6] = active ? bhi[2] - blo[2] + 1 : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[e] = min(v[e], __shfl_xor(v[e], o, 64));
+#pragma unroll
+            for (int e = 3; e < 7; ++e) v[e] = max(v[e], __shfl_xor(v[e], o, 64));
+        }
+        if ((t & 63) == 0) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                atomicMin(&sLo[ax], v[ax]);
+                atomicMax(&sHi[ax], v[3 + ax]);
+            }
+            atomicMax(sNz, v[6]);
+        }
     }
     __syncthreads();
     const int lox = sLo[0], loy = sLo[1], loz = sLo[2];
@@ -306,15 +338,6 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
     // table unguarded.
     const bool tiled = gen_tile_q<MIXED>() > 0 && g.tab_ok && Lx > 0 && Ly > 0 && Lz > 0 &&
                        (int64_t)Ly * Lz <= gen_tile_q<MIXED>();
-    const int64_t cell = cell_id(nc, cx, cy, cz);
-    double phi = 0.0;
-    if (active) {
-        const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
-        if (MIXED)
-            phi = psi[cell] + (double)l2p_cols<P, float, true>(psi32 + cell, M, (float)ux, (float)uy, (float)uz);
-        else
-            phi = l2p_cols<P, double>((gptr<const double>)psi + cell, M, ux, uy, uz);
-    }
     // The near field is summed per row in the working precision and the row
     // sums in FP64, so FP32 rounding does not grow with the box (mixed).
     // rowof(i, j, shx, shy, shz): the charges of plane row (i, j), indexed by z
@@ -489,17 +512,310 @@ __device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M,
         nearv = near_sum([&](int i, int j, int, int, int) { return Qs + ((int64_t)i * n + j) * n; });
     }
     if (!active) return;
-    phi += nearv / g.h;
-    if (phic_) phi += as_global(phic_)[s];  // per-level mode: the coarser levels
-    if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
+    // phisite holds the local expansion, far-field and coarse-level part (site_lf_body)
+    const double phi = phisite[s] + nearv / g.h;
     const int32_t rk = site_rank[s];
     if (rk >= 0) phi_r[rk] = phi;
     phisite[s] = rk >= 0 ? __builtin_nan("") : phi;
 }
 
-int64_t general_site_blocks(int n)
+// ---- general lattice, block-uniform x-window -----------------------------
+// A block holds the G x-planes of one fine cell cx and a chunk of (y, z)
+// sites, so its lanes share the x-planes of the cells cx-1 .. cx+1: a window
+// of NX consecutive planes (unwrapped), the same for every lane.  The union
+// over the lanes of their (y, z) boxes is staged once as columns of NX
+// charges, [y][z][x] with x fastest, beside a table of 1/sqrt(r + dx^2) for
+// every r = dy^2 + dz^2 up to the block's largest and every x offset dx
+// between the window and the G planes.  Each lane computes the G sites of its
+// (y, z) position in the cell's planes: they have one box, so every column of
+// NX charges is read once and the G sites take the same table row shifted by
+// one entry per plane; that divides the LDS words per (site, box site) by
+// about G.  A table row of zeros (r = RZ) stands for the columns of the
+// block's longest box that lie outside a lane's shorter box, and 1/sqrt(0) is
+// stored as 0, which leaves a site's own occupant out.  Charges are staged in
+// FP32: mixed precision rounds them so, and the FP64 path takes this body
+// only when every charge is exactly an FP32 number.
+constexpr int kG2Tile = 10240;  // staged charges (FP32)
+constexpr int kG2Tab = 1536;    // table entries (working precision)
+constexpr int kG2MaxNX = 12;
+constexpr int kG2MaxG = 4;
+
+template <bool MIXED>
+constexpr int g2_smem_bytes()
 {
-    return ((int64_t)n * n * n + kGenSites - 1) / kGenSites;
+    return kG2Tile * 4 + kG2Tab * (MIXED ? 4 : 8) + 4 * 8 * 4;
+}
+
+template <bool MIXED>
+constexpr int general_smem_bytes()
+{
+    return g2_smem_bytes<MIXED>() > gen_smem_bytes<MIXED>() ? g2_smem_bytes<MIXED>() : gen_smem_bytes<MIXED>();
+}
+
+// near-field sums of one lane's G sites: NY x NZ columns (the block's longest
+// box), of which ny x nz are the lane's own; col0 its first column, (dy0,
+// dz0) the offset of that column from the sites.  Table rows hold TW = NX +
+// G - 1 entries: entry e is dx = e - (G - 1) + (window start - first plane),
+// so plane g reads entries ix + G - 1 - g.
+template <int NX, int G, typename Real>
+__device__ __forceinline__ void g2_near(const float *__restrict__ tile, const Real *__restrict__ tab, int Lz,
+                                        int NY, int NZ, int RZ, int col0, int ny, int nz, int dy0, int dz0,
+                                        double (&acc)[G])
+{
+    constexpr int TW = NX + G - 1;
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) acc[gi] = 0.0;
+    for (int yy = 0; yy < NY; ++yy) {
+        const int dy = dy0 + yy;
+        const int oy = yy < ny ? dy * dy : RZ;
+        // a row past the lane's box weighs nothing; it reads the lane's first
+        // row so that every read stays inside the staged columns
+        const float *col = tile + (col0 + (yy < ny ? yy : 0) * Lz) * NX;
+        int dz2 = dz0 * dz0, st = 2 * dz0 + 1;  // (d + 1)^2 = d^2 + 2d + 1
+        for (int zz = 0; zz < NZ; ++zz) {
+            int r = min(oy + dz2, RZ);
+            r = zz < nz ? r : RZ;
+            // 24-bit multiply (full rate): r * TW < 2^24
+            const Real *w = (const Real *)((const char *)tab + __mul24(r, TW * (int)sizeof(Real)));
+            Real c[NX], wr[TW];
+#pragma unroll
+            for (int ix = 0; ix < NX; ++ix) c[ix] = (Real)col[ix];
+#pragma unroll
+            for (int e = 0; e < TW; ++e) wr[e] = w[e];
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+                Real racc = Real(0);
+#pragma unroll
+                for (int ix = 0; ix < NX; ++ix) racc += c[ix] * wr[ix + G - 1 - gi];
+                acc[gi] += (double)racc;
+            }
+            col += NX;
+            dz2 += st;
+            st += 2;
+        }
+    }
+}
+
+// The body above for block (cell cx, chunk ch); returns false (having written
+// nothing) when the cell has more than kG2MaxG planes, the block's union does
+// not fit the tile or the table, or the charges are not staged in FP32, and
+// the caller falls back to site_general_boxrows plane by plane.
+template <bool MIXED>
+__device__ __forceinline__ bool site_general_g2(int cx, int ch, Geo g, const float *__restrict__ qsite32_,
+                                                const int32_t *__restrict__ cell_rng_,
+                                                const int32_t *__restrict__ site_rank_,
+                                                double *__restrict__ phisite_, double *__restrict__ phi_r_,
+                                                unsigned char *smem)
+{
+    using Real = typename std::conditional<MIXED, float, double>::type;
+    const auto Q = as_global(qsite32_);
+    const auto cell_rng = as_global(cell_rng_), site_rank = as_global(site_rank_);
+    const auto phisite = as_global(phisite_), phi_r = as_global(phi_r_);
+    // the table first: its rows are then addressed by small immediate offsets
+    Real *tab = (Real *)smem;
+    float *tile = (float *)(smem + kG2Tab * sizeof(Real));
+    int *red = (int *)(smem + kG2Tab * sizeof(Real) + kG2Tile * 4);  // [4 waves][8]
+    const int n = g.n, nc = g.nc, t = threadIdx.x;
+    const int x0 = cell_rng[2 * cx], G = cell_rng[2 * cx + 1] - x0 + 1;  // the cell's planes
+    int sj, sk;
+    const bool active = gen_yz(ch, n, t, sj, sk);
+    // per axis, the unwrapped planes [lo, hi] of the cells c-1 .. c+1 around
+    // cell c (a periodic neighbour across a face is shifted by n)
+    auto box_of = [&](int c, int &lo, int &hi) {
+        const int a0 = c - 1 < 0 ? 0 : c - 1, a1 = c + 1 >= nc ? nc - 1 : c + 1;
+        lo = cell_rng[2 * a0];
+        hi = cell_rng[2 * a1 + 1];
+        if (g.periodic && c - 1 < 0) lo = cell_rng[2 * (nc - 1)] - n;
+        else if (g.periodic && c + 1 >= nc) hi = cell_rng[1] + n;
+    };
+    int xlo, xhi, ylo, yhi, zlo, zhi;
+    const int cy = fine_coord((sj + 0.5) * g.h, g.w, nc), cz = fine_coord((sk + 0.5) * g.h, g.w, nc);
+    box_of(cx, xlo, xhi);
+    box_of(cy, ylo, yhi);
+    box_of(cz, zlo, zhi);
+    // block-wide: union of the (y, z) boxes, longest ny and nz, largest |dy|, |dz|
+    int v[8];
+    v[0] = active ? ylo : 0x7fffffff;
+    v[1] = active ? zlo : 0x7fffffff;
+    v[2] = active ? yhi : -0x7fffffff;
+    v[3] = active ? zhi : -0x7fffffff;
+    v[4] = active ? yhi - ylo + 1 : 0;
+    v[5] = active ? zhi - zlo + 1 : 0;
+    v[6] = active ? max(sj - ylo, yhi - sj) : 0;
+    v[7] = active ? max(sk - zlo, zhi - sk) : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) v[e] = min(v[e], __shfl_xor(v[e], o, 64));
+#pragma unroll
+        for (int e = 2; e < 8; ++e) v[e] = max(v[e], __shfl_xor(v[e], o, 64));
+    }
+    if ((t & 63) == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[(t >> 6) * 8 + e] = v[e];
+    }
+    __syncthreads();
+    int u[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) u[e] = red[e];
+    for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) u[e] = min(u[e], red[wv * 8 + e]);
+#pragma unroll
+        for (int e = 2; e < 8; ++e) u[e] = max(u[e], red[wv * 8 + e]);
+    }
+    const int loy = u[0], loz = u[1], Ly = u[2] - loy + 1, Lz = u[3] - loz + 1, NY = u[4], NZ = u[5];
+    const int RZ = u[6] * u[6] + u[7] * u[7] + 1;
+    const int NX = xhi - xlo + 1, TW = NX + G - 1;  // the same on every lane
+    // the staged columns, then NZ columns of zeros: a lane's columns past its
+    // shorter z-box run at most that far past the union's last column
+    const bool fits = g.q32 && G <= kG2MaxG && NX <= kG2MaxNX && (Ly * Lz + NZ) * NX <= kG2Tile &&
+                      (RZ + 1) * TW <= kG2Tab;
+    if (!fits) {
+        __syncthreads();  // every lane has read red before the fallback reuses the LDS
+        return false;
+    }
+    // stage the columns: each thread keeps one z and walks the (x, y) rows
+    auto wrap = [&](int w) {
+        return g.periodic ? (w < 0 ? w + n : (w >= n ? w - n : w)) : (w >= 0 && w < n ? w : -1);
+    };
+    if (Lz <= (int)blockDim.x) {
+        const int rpp = blockDim.x / Lz, zt = t % Lz;
+        int r = t / Lz;
+        if (r < rpp) {
+            const int uz = wrap(loz + zt);
+            int ix = r / Ly, iy = r - (r / Ly) * Ly;
+            for (; r < NX * Ly; r += rpp) {
+                const int ux = wrap(xlo + ix), uy = wrap(loy + iy);
+                float qv = 0.0f;
+                if (ux >= 0 && uy >= 0 && uz >= 0) qv = Q[((int64_t)ux * n + uy) * n + uz];
+                tile[(iy * Lz + zt) * NX + ix] = qv;
+                iy += rpp;
+                while (iy >= Ly) {
+                    iy -= Ly;
+                    ++ix;
+                }
+            }
+        }
+    } else {
+        for (int e = t; e < NX * Ly * Lz; e += blockDim.x) {
+            const int ix = e / (Ly * Lz), iy = (e / Lz) % Ly, iz = e % Lz;
+            const int ux = wrap(xlo + ix), uy = wrap(loy + iy), uz = wrap(loz + iz);
+            float qv = 0.0f;
+            if (ux >= 0 && uy >= 0 && uz >= 0) qv = Q[((int64_t)ux * n + uy) * n + uz];
+            tile[(iy * Lz + iz) * NX + ix] = qv;
+        }
+    }
+    for (int e = t; e < NZ * NX; e += blockDim.x) tile[Ly * Lz * NX + e] = 0.0f;
+    // table: row r, entry e holds 1/sqrt(r + dx^2), dx = xlo - x0 - (G - 1) + e; row RZ is zeros
+    for (int e = t; e < (RZ + 1) * TW; e += blockDim.x) {
+        const int r = e / TW, ix = e - (e / TW) * TW;
+        const int dx = xlo - x0 - (G - 1) + ix;
+        const int d2 = r + dx * dx;
+        tab[e] = (r >= RZ || d2 == 0) ? Real(0) : (Real)(1.0 / sqrt((double)d2));
+    }
+    __syncthreads();
+    if (!active) return true;
+    const int col0 = (ylo - loy) * Lz + (zlo - loz);
+    const int ny = yhi - ylo + 1, nz = zhi - zlo + 1, dy0 = ylo - sj, dz0 = zlo - sk;
+    double acc[kG2MaxG];
+    switch (G * 16 + NX) {
+#define FMMKMC_G2_CASE(gg, k)                                                                                    \
+    case gg * 16 + k: {                                                                                          \
+        double a_[gg];                                                                                           \
+        g2_near<k, gg, Real>(tile, tab, Lz, NY, NZ, RZ, col0, ny, nz, dy0, dz0, a_);                             \
+        for (int gi = 0; gi < gg; ++gi) acc[gi] = a_[gi];                                                        \
+    } break;
+#define FMMKMC_G2_ROW(gg)                                                                                        \
+    FMMKMC_G2_CASE(gg, 1) FMMKMC_G2_CASE(gg, 2) FMMKMC_G2_CASE(gg, 3) FMMKMC_G2_CASE(gg, 4)                       \
+    FMMKMC_G2_CASE(gg, 5) FMMKMC_G2_CASE(gg, 6) FMMKMC_G2_CASE(gg, 7) FMMKMC_G2_CASE(gg, 8)                       \
+    FMMKMC_G2_CASE(gg, 9) FMMKMC_G2_CASE(gg, 10) FMMKMC_G2_CASE(gg, 11) FMMKMC_G2_CASE(gg, 12)
+    FMMKMC_G2_ROW(1) FMMKMC_G2_ROW(2) FMMKMC_G2_ROW(3) FMMKMC_G2_ROW(4)
+#undef FMMKMC_G2_ROW
+#undef FMMKMC_G2_CASE
+    default:
+        for (int gi = 0; gi < kG2MaxG; ++gi) acc[gi] = 0.0;
+        break;
+    }
+    for (int gi = 0; gi < G; ++gi) {
+        const int64_t s = ((int64_t)(x0 + gi) * n + sj) * n + sk;
+        // phisite holds the local expansion, far-field and coarse-level part (site_lf_body)
+        const double phi = phisite[s] + acc[gi] / g.h;
+        const int32_t rk = site_rank[s];
+        if (rk >= 0) phi_r[rk] = phi;
+        phisite[s] = rk >= 0 ? __builtin_nan("") : phi;
+    }
+    return true;
+}
+
+// General lattices, first pass: the part of a site's potential that is not
+// the near field, one lane per site (lattice order): L2P of its fine cell's
+// local expansion, the coarser levels (per-level mode) and the far field.  The
+// near-field pass adds its sum to this value.  Kept apart from the near field,
+// whose LDS tiles limit how many waves a CU holds, so that these global loads
+// run at full occupancy.
+template <int P, bool MIXED>
+__device__ __forceinline__ void site_lf_body(int64_t s, Geo g, int64_t M, const double *__restrict__ psi_,
+                                             const float *__restrict__ psi32_, const double *__restrict__ Bz_,
+                                             const double *__restrict__ Tax_, const double *__restrict__ phic_,
+                                             double *__restrict__ phisite_)
+{
+    const int n = g.n, nc = g.nc;
+    if (s >= (int64_t)n * n * n) return;
+    const auto psi = as_global(psi_), Bz = as_global(Bz_), Tax = as_global(Tax_);
+    const auto psi32 = as_global(psi32_);
+    const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
+    const double px = (si + 0.5) * g.h, py = (sj + 0.5) * g.h, pz = (sk + 0.5) * g.h;
+    const int cx = fine_coord(px, g.w, nc), cy = fine_coord(py, g.w, nc), cz = fine_coord(pz, g.w, nc);
+    const int64_t cell = cell_id(nc, cx, cy, cz);
+    const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
+    double phi;
+    if (MIXED)
+        phi = psi[cell] + (double)l2p_cell<P, float, true>(psi32, M, (uint32_t)cell, (float)ux, (float)uy, (float)uz);
+    else
+        phi = l2p_cell<P, double>(psi, M, (uint32_t)cell, ux, uy, uz);
+    if (phic_) phi += as_global(phic_)[s];  // per-level mode: the coarser levels
+    if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
+    as_global(phisite_)[s] = phi;
+}
+
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_site_lf(Geo g, int64_t M, const double *__restrict__ psi,
+                                                 const float *__restrict__ psi32, const double *__restrict__ Bz,
+                                                 const double *__restrict__ Tax, const double *__restrict__ phic,
+                                                 double *__restrict__ phisite)
+{
+    site_lf_body<P, MIXED>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, g, M, psi, psi32, Bz, Tax, phic,
+                           phisite);
+}
+
+// a general-lattice block (fine cell cx along x, chunk ch of (y, z) sites):
+// the x-window body, else the box-row body for each plane of the cell
+template <int P, bool MIXED>
+__device__ __forceinline__ void site_general_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi,
+                                                  const float *__restrict__ psi32, const double *__restrict__ Bz,
+                                                  const double *__restrict__ Tax, const double *__restrict__ qsite,
+                                                  const float *__restrict__ qsite32,
+                                                  const int32_t *__restrict__ cell_rng,
+                                                  const int32_t *__restrict__ site_rank, double *__restrict__ phisite,
+                                                  double *__restrict__ phi_r, const double *__restrict__ phic,
+                                                  unsigned char *smem)
+{
+    const int bpp = (g.n * g.n + kGenSites - 1) / kGenSites;
+    const int cx = (int)(blk / bpp), ch = (int)(blk - (int64_t)cx * bpp);
+    if (site_general_g2<MIXED>(cx, ch, g, qsite32, cell_rng, site_rank, phisite, phi_r, smem)) return;
+    const int x0 = as_global(cell_rng)[2 * cx], x1 = as_global(cell_rng)[2 * cx + 1];
+    for (int si = x0; si <= x1; ++si) {
+        site_general_boxrows<P, MIXED>(si, ch, g, M, psi, psi32, Bz, Tax, qsite, qsite32, cell_rng, site_rank,
+                                       phisite, phi_r, phic, smem);
+        __syncthreads();  // the next plane restages the LDS
+    }
+}
+
+// blocks of the general-lattice near field: fine cells along x times chunks of a plane
+int64_t general_site_blocks(int n, int nc)
+{
+    return (int64_t)nc * ((n * n + kGenSites - 1) / kGenSites);
 }
 
 template <int P, bool MIXED>
@@ -514,7 +830,7 @@ __global__ __launch_bounds__(256) void k_site_phi_general(Geo g, int64_t M, cons
                                                           double *__restrict__ phisite, double *__restrict__ phi_r,
                                                           const double *__restrict__ phic)
 {
-    __shared__ __align__(16) unsigned char smem[gen_smem_bytes<MIXED>()];
+    __shared__ __align__(16) unsigned char smem[general_smem_bytes<MIXED>()];
     site_general_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, Bz, Tax, qsite, qsite32, cell_rng, site_rank,
                                 phisite, phi_r, phic, smem);
 }
@@ -833,7 +1149,18 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
                                            c->far.Tax, c->phisite, c->phi_r, c->phicoarse));
         }
     } else {
-        dim3 grid((unsigned)general_site_blocks(c->lat_n));
+        const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
+        const dim3 glf((unsigned)((ns + 255) / 256));
+        if (mixed) {
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_lf<P_, true>, glf, dim3(256), g, c->M,
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->phicoarse,
+                                           c->phisite));
+        } else {
+            FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_lf<P_, false>, glf, dim3(256), g, c->M,
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->phicoarse,
+                                           c->phisite));
+        }
+        dim3 grid((unsigned)general_site_blocks(c->lat_n, c->nc));
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_phi_general<P_, true>, grid, dim3(256), g, c->M,
                                            c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->qsite, c->qsite32,
@@ -1815,22 +2142,28 @@ void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int n
 // ---- batched replicas: one launch per phase over every replica ----------------
 // base[r] .. base[r+1] are replica r's blocks; all replicas share p and precision.
 
+// first pass of the general-lattice replicas (site_lf_body), blocks of 256 sites
 template <int P, bool MIXED>
-__global__ __launch_bounds__(256) void k_b_site(const RepDev *__restrict__ reps, int R,
-                                                const int64_t *__restrict__ base)
+__global__ __launch_bounds__(256) void k_b_site_lf(const RepDev *__restrict__ reps, int R,
+                                                   const int64_t *__restrict__ base)
 {
-    // one LDS buffer serves whichever body the replica takes
-    constexpr int kS2 = s2_smem_bytes<MIXED, 4>(), kGen = gen_smem_bytes<MIXED>();
-    __shared__ __align__(16) unsigned char smem[kS2 > kGen ? kS2 : kGen];
     const int r = find_rep(base, R, blockIdx.x);
     const RepDev &d = reps[r];
-    const int64_t blk = blockIdx.x - base[r];
-    if (d.s2)
-        site_s2_body<P, MIXED, 4>(blk, d.g, d.M, d.psi, d.psi32, d.qsite, d.qsite32, d.site_rank, d.Bz, d.Tax,
-                                  d.phisite, d.phi_r, d.phicoarse, smem);
-    else
-        site_general_body<P, MIXED>(blk, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.qsite, d.qsite32, d.cell_rng,
-                                    d.site_rank, d.phisite, d.phi_r, d.phicoarse, smem);
+    site_lf_body<P, MIXED>((int64_t)(blockIdx.x - base[r]) * 256 + threadIdx.x, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax,
+                           d.phicoarse, d.phisite);
+}
+
+// general-lattice replicas (2x2x2 replicas take k_b_site_s2 in a launch of
+// their own, so neither body's registers limit the other's occupancy)
+template <int P, bool MIXED>
+__global__ __launch_bounds__(256) void k_b_site_gen(const RepDev *__restrict__ reps, int R,
+                                                    const int64_t *__restrict__ base)
+{
+    __shared__ __align__(16) unsigned char smem[general_smem_bytes<MIXED>()];
+    const int r = find_rep(base, R, blockIdx.x);
+    const RepDev &d = reps[r];
+    site_general_body<P, MIXED>(blockIdx.x - base[r], d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.qsite, d.qsite32,
+                                d.cell_rng, d.site_rank, d.phisite, d.phi_r, d.phicoarse, smem);
 }
 
 template <int TC>
@@ -1935,25 +2268,36 @@ __global__ __launch_bounds__(512) void k_b_site_s2(const RepDev *__restrict__ re
                               d.Tax, d.phisite, d.phi_r, d.phicoarse, smem);
 }
 
-void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
-                   int p, bool mixed, bool all_s2)
+void launch_b_site(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base_s2,
+                   int64_t blocks_s2, const int64_t *base_lf, int64_t blocks_lf, const int64_t *base_gen,
+                   int64_t blocks_gen, int p, bool mixed)
 {
-    if (all_s2) {
+    if (blocks_lf > 0) {
         if (mixed) {
-            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_s2<P_, true>, dim3((unsigned)blocks),
-                                             dim3(512), 0, reps, R, base));
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_lf<P_, true>, dim3((unsigned)blocks_lf),
+                                             dim3(256), 0, reps, R, base_lf));
         } else {
-            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_s2<P_, false>, dim3((unsigned)blocks),
-                                             dim3(512), 0, reps, R, base));
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_lf<P_, false>, dim3((unsigned)blocks_lf),
+                                             dim3(256), 0, reps, R, base_lf));
         }
-        return;
     }
-    if (mixed) {
-        FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site<P_, true>, dim3((unsigned)blocks), dim3(256), 0,
-                                       reps, R, base));
-    } else {
-        FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site<P_, false>, dim3((unsigned)blocks), dim3(256), 0,
-                                       reps, R, base));
+    if (blocks_s2 > 0) {
+        if (mixed) {
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_s2<P_, true>, dim3((unsigned)blocks_s2),
+                                             dim3(512), 0, reps, R, base_s2));
+        } else {
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_s2<P_, false>, dim3((unsigned)blocks_s2),
+                                             dim3(512), 0, reps, R, base_s2));
+        }
+    }
+    if (blocks_gen > 0) {
+        if (mixed) {
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_gen<P_, true>, dim3((unsigned)blocks_gen),
+                                             dim3(256), 0, reps, R, base_gen));
+        } else {
+            FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_site", k_b_site_gen<P_, false>, dim3((unsigned)blocks_gen),
+                                             dim3(256), 0, reps, R, base_gen));
+        }
     }
 }
 

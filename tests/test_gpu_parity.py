@@ -103,6 +103,30 @@ def test_lattice_proposals_match_oracle(n, N, L, p, bc):
     ctx.close()
 
 
+@pytest.mark.parametrize("bc", ["periodic", "free"])
+def test_general_lattice_charges_not_exact_in_fp32(bc):
+    """FP64 on a general lattice (2.5 sites per cell edge) with charges +-0.3,
+    which FP32 rounds: the site kernel cannot stage them in FP32 and takes its
+    box-row body for every block.  Every valid slot against O-fmm."""
+    import torch
+    periodic = bc == "periodic"
+    n, N, L, p = 20, 500, 4, 7
+    sites, xyz, q, idx, tgt, valid = lattice_case(n, N, 4242, periodic)
+    q = 0.3 * q
+    print(f"charges +-0.3: n={n} N={N} L={L} p={p} {bc}", flush=True)
+    ctx = make_ctx(xyz, q, n, L, p, bc)
+    ctx.initialise()
+    dU, mask = ctx.propose_lattice(W.HOPS6)
+    torch.cuda.synchronize()
+    dU = dU.cpu().numpy().reshape(-1)
+    assert np.array_equal(mask.cpu().numpy().reshape(-1).astype(bool), valid)
+    d_ref = O.FmmKmc(xyz, q, n, L, p, bc).propose(idx[valid], tgt[valid])
+    err = guarded_err(dU[valid], d_ref)
+    print(f"  max guarded rel err {err:.3e}", flush=True)
+    assert err < 1e-10
+    ctx.close()
+
+
 @pytest.mark.parametrize("bc,L", [("free", 3), ("periodic", 3)])
 def test_generic_proposals_match_oracle(bc, L):
     """propose(P) with arbitrary (off-lattice) targets."""
