@@ -1883,29 +1883,28 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nt; k += blockDim.x) part += qi * Wt[k] * H[k];
-        // eight independent loads of R in flight per lane (the quadratic term is
-        // part of the exact self-image change when that option is on)
-        const int nn = g.self_exact ? 0 : nt * nt;
-        double acc8[8] = {};
-        int e = threadIdx.x;
-        for (; e + 7 * 256 < nn; e += 8 * 256) {
-            double r8[8];
+        // dW^T R dK: lane (k, group) runs down column k of R over the rows m of
+        // its group, so consecutive lanes read consecutive words and no lane
+        // divides per element; four independent loads in flight per lane (the
+        // quadratic term is part of the exact self-image change when that
+        // option is on)
+        if (!g.self_exact) {
+            const int ng = (int)blockDim.x >= 2 * nt ? (int)blockDim.x / nt : 1;  // row groups
+            for (int task = threadIdx.x; task < ng * nt; task += blockDim.x) {
+                const int grp = task / nt, k = task - grp * nt;
+                double a4[4] = {};
+                int m = grp;
+                for (; m + 3 * ng < nt; m += 4 * ng) {
+                    double r4[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) r8[u] = R[e + u * 256];
+                    for (int u = 0; u < 4; ++u) r4[u] = R[(int64_t)(m + u * ng) * nt + k];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int ee = e + u * 256, m = ee / nt, k = ee - m * nt;
-                acc8[u] += Wt[k] * r8[u] * Kt[m];
+                    for (int u = 0; u < 4; ++u) a4[u] += r4[u] * Kt[m + u * ng];
+                }
+                for (; m < nt; m += ng) a4[0] += R[(int64_t)m * nt + k] * Kt[m];
+                part += 0.5 * qi * Wt[k] * ((a4[0] + a4[1]) + (a4[2] + a4[3]));
             }
         }
-        for (; e < nn; e += 256) {
-            const int m = e / nt, k = e - m * nt;
-            acc8[0] += Wt[k] * R[e] * Kt[m];
-        }
-        double bil = 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) bil += acc8[u];
-        part += 0.5 * qi * bil;
     }
     const double tot = block_sum(part, red);
     if (threadIdx.x == 0) out[part_id] = tot;
