@@ -787,7 +787,7 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
             const int q = c->p + 1;
             nsite[r] = c->s2 ? (c->M + 255) / 256 : 0;
-            nsite_lf[r] = c->s2 ? 0 : (ns + 255) / 256;
+            nsite_lf[r] = c->s2 ? 0 : general_site_blocks(c->lat_n, c->nc);
             nsite_gen[r] = c->s2 ? 0 : general_site_blocks(c->lat_n, c->nc);
             ncount[r] = (c->N * K + kSelChunk - 1) / kSelChunk;
             npath[r] = ((int64_t)c->L * (q * (q + 1) / 2) + 255) / 256;

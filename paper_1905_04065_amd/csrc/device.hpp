@@ -71,15 +71,11 @@ struct RecTables {
     }
 };
 
-// L2P (the same sum as l2p() in solid.hpp) for the lane's fine cell of
-// coefficient-major expansions (coefficient k of cell c at base[k * M + c]),
-// fully unrolled: every coefficient load is issued up front, each a uniform
-// column start plus the lane's 32-bit cell offset, for kernels that can spend
-// the registers on having them all in flight.
-template <int P, typename T, bool SKIP0 = false>
-__device__ inline T l2p_cell(gptr<const T> base, int64_t M, uint32_t cell, T x, T y, T z)
+// L2P (the same sum as l2p() in solid.hpp), fully unrolled, with coefficient
+// k read as L(k): every load can be issued up front.
+template <int P, typename T, bool SKIP0 = false, class LF>
+__device__ inline T l2p_fn(LF L, T x, T y, T z)
 {
-    auto L = [&](int k) { return (base + (int64_t)k * M)[cell]; };
     const T r2 = x * x + y * y + z * z;
     T acc0 = SKIP0 ? T(0) : L(0);
     T cm2 = T(1), cm1 = z;
@@ -117,6 +113,94 @@ __device__ inline T l2p_cell(gptr<const T> base, int64_t M, uint32_t cell, T x, 
         }
     }
     return acc0 + T(2) * acc1;
+}
+
+// l2p_fn at G points that share one expansion and their y and z offsets (the
+// same site of G consecutive x-planes of a cell): each coefficient is read
+// once and used G times.
+template <int P, typename T, int G, bool SKIP0 = false, class LF>
+__device__ inline void l2p_fn_x(LF L, const T (&x)[G], T y, T z, T (&out)[G])
+{
+    T r2[G], acc0[G], acc1[G], cm2[G], cm1[G], dr[G], di[G];
+    const T l0 = SKIP0 ? T(0) : L(0);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        r2[q] = x[q] * x[q] + y * y + z * z;
+        acc0[q] = l0;
+        acc1[q] = T(0);
+        cm2[q] = T(1);
+        cm1[q] = z;
+        dr[q] = T(1);
+        di[q] = T(0);
+    }
+    if (P >= 1) {
+        const T l = L(slot0(1));
+#pragma unroll
+        for (int q = 0; q < G; ++q) acc0[q] += l * z;
+    }
+#pragma unroll
+    for (int n = 2; n <= P; ++n) {
+        const T l = L(slot0(n));
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const T c = ((T)(2 * n - 1) * z * cm1[q] - r2[q] * cm2[q]) * (T)rinv(n, 0);
+            acc0[q] += l * c;
+            cm2[q] = cm1[q];
+            cm1[q] = c;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m <= P; ++m) {
+        const T f = (T)(-0.5 / m);
+        T ar[G], ai[G], br[G], bi[G];
+        {
+            const T lr = L(slot_re(m, m)), li = L(slot_im(m, m));
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const T ndr = f * (x[q] * dr[q] - y * di[q]), ndi = f * (x[q] * di[q] + y * dr[q]);
+                dr[q] = ndr;
+                di[q] = ndi;
+                ar[q] = dr[q];
+                ai[q] = di[q];
+                acc1[q] += lr * ar[q] + li * ai[q];
+            }
+        }
+        if (m + 1 <= P) {
+            const T lr = L(slot_re(m + 1, m)), li = L(slot_im(m + 1, m));
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                br[q] = z * ar[q];
+                bi[q] = z * ai[q];
+                acc1[q] += lr * br[q] + li * bi[q];
+            }
+#pragma unroll
+            for (int n = m + 2; n <= P; ++n) {
+                const T w = (T)rinv(n, m);
+                const T lr2 = L(slot_re(n, m)), li2 = L(slot_im(n, m));
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const T cr = ((T)(2 * n - 1) * z * br[q] - r2[q] * ar[q]) * w;
+                    const T ci = ((T)(2 * n - 1) * z * bi[q] - r2[q] * ai[q]) * w;
+                    acc1[q] += lr2 * cr + li2 * ci;
+                    ar[q] = br[q];
+                    ai[q] = bi[q];
+                    br[q] = cr;
+                    bi[q] = ci;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) out[q] = acc0[q] + T(2) * acc1[q];
+}
+
+// l2p_fn for the lane's fine cell of coefficient-major expansions (coefficient
+// k of cell c at base[k * M + c]): each load a uniform column start plus the
+// lane's 32-bit cell offset.
+template <int P, typename T, bool SKIP0 = false>
+__device__ inline T l2p_cell(gptr<const T> base, int64_t M, uint32_t cell, T x, T y, T z)
+{
+    return l2p_fn<P, T, SKIP0>([&](int k) { return (base + (int64_t)k * M)[cell]; }, x, y, z);
 }
 
 // L2P (the same sum as l2p() in solid.hpp) with the orders m >= 1 in a rolled

@@ -680,21 +680,33 @@ __device__ __forceinline__ bool site_general_g2(int cx, int ch, Geo g, const flo
         return g.periodic ? (w < 0 ? w + n : (w >= n ? w - n : w)) : (w >= 0 && w < n ? w : -1);
     };
     if (Lz <= (int)blockDim.x) {
+        // each thread keeps one z and walks the (x, y) rows, eight loads in
+        // flight before their stores
         const int rpp = blockDim.x / Lz, zt = t % Lz;
         int r = t / Lz;
         if (r < rpp) {
             const int uz = wrap(loz + zt);
             int ix = r / Ly, iy = r - (r / Ly) * Ly;
-            for (; r < NX * Ly; r += rpp) {
-                const int ux = wrap(xlo + ix), uy = wrap(loy + iy);
-                float qv = 0.0f;
-                if (ux >= 0 && uy >= 0 && uz >= 0) qv = Q[((int64_t)ux * n + uy) * n + uz];
-                tile[(iy * Lz + zt) * NX + ix] = qv;
-                iy += rpp;
-                while (iy >= Ly) {
-                    iy -= Ly;
-                    ++ix;
+            while (r < NX * Ly) {
+                float qv[8];
+                int at[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool in_r = r < NX * Ly;
+                    const int ux = wrap(xlo + ix), uy = wrap(loy + iy);
+                    const bool ok = in_r && ux >= 0 && uy >= 0 && uz >= 0;
+                    qv[u] = ok ? Q[((int64_t)ux * n + uy) * n + uz] : 0.0f;
+                    at[u] = in_r ? (iy * Lz + zt) * NX + ix : -1;
+                    r += rpp;
+                    iy += rpp;
+                    while (iy >= Ly) {
+                        iy -= Ly;
+                        ++ix;
+                    }
                 }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (at[u] >= 0) tile[at[u]] = qv[u];
             }
         }
     } else {
@@ -749,44 +761,86 @@ __device__ __forceinline__ bool site_general_g2(int cx, int ch, Geo g, const flo
 }
 
 // General lattices, first pass: the part of a site's potential that is not
-// the near field, one lane per site (lattice order): L2P of its fine cell's
-// local expansion, the coarser levels (per-level mode) and the far field.  The
-// near-field pass adds its sum to this value.  Kept apart from the near field,
-// whose LDS tiles limit how many waves a CU holds, so that these global loads
-// run at full occupancy.
-template <int P, bool MIXED>
-__device__ __forceinline__ void site_lf_body(int64_t s, Geo g, int64_t M, const double *__restrict__ psi_,
-                                             const float *__restrict__ psi32_, const double *__restrict__ Bz_,
-                                             const double *__restrict__ Tax_, const double *__restrict__ phic_,
-                                             double *__restrict__ phisite_)
+// the near field: L2P of its fine cell's local expansion, the coarser levels
+// (per-level mode) and the far field.  The near-field pass adds its sum to
+// this value.  Blocks as in the near-field pass: one fine cell cx along x and
+// a chunk of (y, z) sites; a lane takes the cell's G planes at its (y, z), one
+// fine cell, so in mixed precision it reads each coefficient once for G sites.
+template <int P, typename Real, int G>
+__device__ __forceinline__ void lf_planes(const Geo &g, gptr<const Real> src, int64_t M, int64_t cell, int x0,
+                                          double cxw, Real uy, Real uz, double (&out)[G])
 {
-    const int n = g.n, nc = g.nc;
-    if (s >= (int64_t)n * n * n) return;
+    Real ux[G], v[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) ux[q] = (Real)((x0 + q + 0.5) * g.h - cxw);
+    auto L = [&](int k) { return (src + (int64_t)k * M)[(uint32_t)cell]; };
+    l2p_fn_x<P, Real, G, std::is_same<Real, float>::value>(L, ux, uy, uz, v);
+#pragma unroll
+    for (int q = 0; q < G; ++q) out[q] = (double)v[q];
+}
+
+template <int P, bool MIXED>
+__device__ __forceinline__ void site_lf_body(int64_t blk, Geo g, int64_t M, const double *__restrict__ psi_,
+                                             const float *__restrict__ psi32_, const double *__restrict__ Bz_,
+                                             const double *__restrict__ Tax_, const int32_t *__restrict__ cell_rng_,
+                                             const double *__restrict__ phic_, double *__restrict__ phisite_)
+{
+    using Real = typename std::conditional<MIXED, float, double>::type;
+    const int n = g.n, nc = g.nc, t = threadIdx.x;
+    const int bpp = (n * n + kGenSites - 1) / kGenSites;
+    const int cx = (int)(blk / bpp), ch = (int)(blk - (int64_t)cx * bpp);
+    int sj, sk;
+    if (!gen_yz(ch, n, t, sj, sk)) return;
+    const auto cell_rng = as_global(cell_rng_);
+    const int x0 = cell_rng[2 * cx], G = cell_rng[2 * cx + 1] - x0 + 1;  // the cell's planes
     const auto psi = as_global(psi_), Bz = as_global(Bz_), Tax = as_global(Tax_);
-    const auto psi32 = as_global(psi32_);
-    const int si = (int)(s / ((int64_t)n * n)), sj = (int)((s / n) % n), sk = (int)(s % n);
-    const double px = (si + 0.5) * g.h, py = (sj + 0.5) * g.h, pz = (sk + 0.5) * g.h;
-    const int cx = fine_coord(px, g.w, nc), cy = fine_coord(py, g.w, nc), cz = fine_coord(pz, g.w, nc);
+    const gptr<const Real> src = MIXED ? (gptr<const Real>)as_global(psi32_) : (gptr<const Real>)as_global(psi_);
+    const double py = (sj + 0.5) * g.h, pz = (sk + 0.5) * g.h;
+    const int cy = fine_coord(py, g.w, nc), cz = fine_coord(pz, g.w, nc);
     const int64_t cell = cell_id(nc, cx, cy, cz);
-    const double ux = px - (cx + 0.5) * g.w, uy = py - (cy + 0.5) * g.w, uz = pz - (cz + 0.5) * g.w;
-    double phi;
-    if (MIXED)
-        phi = psi[cell] + (double)l2p_cell<P, float, true>(psi32, M, (uint32_t)cell, (float)ux, (float)uy, (float)uz);
-    else
-        phi = l2p_cell<P, double>(psi, M, (uint32_t)cell, ux, uy, uz);
-    if (phic_) phi += as_global(phic_)[s];  // per-level mode: the coarser levels
-    if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
-    as_global(phisite_)[s] = phi;
+    const double cxw = (cx + 0.5) * g.w;
+    const Real uy = (Real)(py - (cy + 0.5) * g.w), uz = (Real)(pz - (cz + 0.5) * g.w);
+    const double c0 = MIXED ? psi[cell] : 0.0;  // mixed: the constant term in FP64
+    auto finish = [&](int q, double l) {
+        const int si = x0 + q;
+        const int64_t s = ((int64_t)si * n + sj) * n + sk;
+        double phi = c0 + l;
+        if (phic_) phi += as_global(phic_)[s];  // per-level mode: the coarser levels
+        if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
+        as_global(phisite_)[s] = phi;
+    };
+    auto run = [&](auto gc) {
+        constexpr int GG = decltype(gc)::value;
+        double o[GG];
+        lf_planes<P, Real, GG>(g, src, M, cell, x0, cxw, uy, uz, o);
+#pragma unroll
+        for (int q = 0; q < GG; ++q) finish(q, o[q]);
+    };
+    using std::integral_constant;
+    // FP64: one site at a time (the shared form's registers cost more occupancy than its loads save)
+    switch (MIXED ? G : 0) {
+    case 1: run(integral_constant<int, 1>{}); break;
+    case 2: run(integral_constant<int, 2>{}); break;
+    case 3: run(integral_constant<int, 3>{}); break;
+    case 4: run(integral_constant<int, 4>{}); break;
+    default:
+        // one site at a time
+        for (int q = 0; q < G; ++q) {
+            double o[1];
+            lf_planes<P, Real, 1>(g, src, M, cell, x0 + q, cxw, uy, uz, o);
+            finish(q, o[0]);
+        }
+        break;
+    }
 }
 
 template <int P, bool MIXED>
 __global__ __launch_bounds__(256) void k_site_lf(Geo g, int64_t M, const double *__restrict__ psi,
                                                  const float *__restrict__ psi32, const double *__restrict__ Bz,
-                                                 const double *__restrict__ Tax, const double *__restrict__ phic,
-                                                 double *__restrict__ phisite)
+                                                 const double *__restrict__ Tax, const int32_t *__restrict__ cell_rng,
+                                                 const double *__restrict__ phic, double *__restrict__ phisite)
 {
-    site_lf_body<P, MIXED>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, g, M, psi, psi32, Bz, Tax, phic,
-                           phisite);
+    site_lf_body<P, MIXED>(blockIdx.x, g, M, psi, psi32, Bz, Tax, cell_rng, phic, phisite);
 }
 
 // a general-lattice block (fine cell cx along x, chunk ch of (y, z) sites):
@@ -1149,16 +1203,15 @@ void launch_site_phi(fmmkmc_ctx *c, const Geo &g)
                                            c->far.Tax, c->phisite, c->phi_r, c->phicoarse));
         }
     } else {
-        const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
-        const dim3 glf((unsigned)((ns + 255) / 256));
+        const dim3 glf((unsigned)general_site_blocks(c->lat_n, c->nc));
         if (mixed) {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_lf<P_, true>, glf, dim3(256), g, c->M,
-                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->phicoarse,
-                                           c->phisite));
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->cell_rng,
+                                           c->phicoarse, c->phisite));
         } else {
             FMMKMC_DISPATCH_P(c->p, launch(c, "site_phi", k_site_lf<P_, false>, glf, dim3(256), g, c->M,
-                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->phicoarse,
-                                           c->phisite));
+                                           c->psi_lv[c->L], c->psi32, c->far.Bz, c->far.Tax, c->cell_rng,
+                                           c->phicoarse, c->phisite));
         }
         dim3 grid((unsigned)general_site_blocks(c->lat_n, c->nc));
         if (mixed) {
@@ -2141,15 +2194,15 @@ void launch_dats_select(fmmkmc_ctx *c, int64_t N, int K, const int32_t *C, int n
 // ---- batched replicas: one launch per phase over every replica ----------------
 // base[r] .. base[r+1] are replica r's blocks; all replicas share p and precision.
 
-// first pass of the general-lattice replicas (site_lf_body), blocks of 256 sites
+// first pass of the general-lattice replicas (site_lf_body)
 template <int P, bool MIXED>
 __global__ __launch_bounds__(256) void k_b_site_lf(const RepDev *__restrict__ reps, int R,
                                                    const int64_t *__restrict__ base)
 {
     const int r = find_rep(base, R, blockIdx.x);
     const RepDev &d = reps[r];
-    site_lf_body<P, MIXED>((int64_t)(blockIdx.x - base[r]) * 256 + threadIdx.x, d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax,
-                           d.phicoarse, d.phisite);
+    site_lf_body<P, MIXED>(blockIdx.x - base[r], d.g, d.M, d.psi, d.psi32, d.Bz, d.Tax, d.cell_rng, d.phicoarse,
+                           d.phisite);
 }
 
 // general-lattice replicas (2x2x2 replicas take k_b_site_s2 in a launch of
