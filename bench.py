@@ -701,6 +701,48 @@ def run_slab(steps, warmup, seed, precision="fp64", n=128, N=500000, L=7, p=12, 
             "valid_slots": valid, "propose_us": propose_us, "commit_us": commit_us, "setup_s": setup_s}
 
 
+def batched_rooflines(run, precision, p=10, count=256):
+    """work of the batched step's site and sweep phases over all replicas:
+    the site phase against HBM (algorithmic bytes: the fine-level expansions
+    once, the site tables, the potentials out) with the near-field box entries
+    per second beside it (the general-lattice bodies are bound by LDS and
+    VALU, not HBM); the sweep against FP64 peak"""
+    Ns, ns, Ls = W.replica_sizes(count)
+    nt = (p + 1) ** 2
+    mixed = precision == "mixed"
+    nbytes = flop = entries = 0
+    for N, n, L in zip(Ns, ns, Ls):
+        N, n, L = int(N), int(n), int(L)
+        nc = 2 ** (L - 1)
+        M = nc ** 3
+        sites = n ** 3
+        nbytes += M * nt * (4 if mixed else 8) + (M * 8 if mixed else 0) + sites * ((4 if mixed else 8) + 4 + 8) \
+            + N * 8 + n * n * (p + 1) * 8
+        flop += M * 54 * P2L_FLOP * nt / 169.0
+        # near-field box entries: per axis the planes of the three cells around each site's cell
+        w = n / nc
+        cell = np.minimum(np.floor((np.arange(n) + 0.5) / w).astype(int), nc - 1)
+        per = np.bincount(cell, minlength=nc)
+        ext = per[(cell - 1) % nc] + per[cell] + per[(cell + 1) % nc]
+        entries += int(ext.sum()) ** 3
+    ph = run["phase_us"]
+    out = {}
+    if "b_site" in ph:
+        us = ph["b_site"]
+        ach = nbytes / (us * 1e-6) / 1e9
+        out["b_site"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": nbytes, "avg_us": us,
+                         "near_field_box_entries": entries, "box_entries_per_s": entries / (us * 1e-6),
+                         "note": "all three site launches per step (2x2x2 body; the general lattices' local "
+                                 "expansion pass and near-field pass); the near field is LDS- and VALU-bound"}
+    if "b_sweep" in ph:
+        us = ph["b_sweep"]
+        ach = flop / (us * 1e-6) / 1e12
+        out["b_sweep"] = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": ach / FP64_PEAK_TFLOPS, "algorithmic_flop": flop, "avg_us": us}
+    return out
+
+
 def batched_summary(args):
     """256 replicas, p = 10, 6 hops, periodic: mixed and FP64 batched (graph
     steps) against the plain FP64 path (one replica at a time, host selection)"""
@@ -719,7 +761,9 @@ def batched_summary(args):
     log("[batch] mixed, per-level expansions and exact self-image term")
     mixed_levels = run_batched("mixed", steps, args.warmup, seed, per_level=True, self_image="exact")
     slots = mixed["slots_per_step"]
+    rooflines = {pr: batched_rooflines(r, pr) for pr, r in (("mixed", mixed), ("fp64", fp64))}
     return {
+        "rooflines": rooflines,
         "workload": f"{mixed['replicas']} periodic replicas, N_r log-uniform in [1000, 65536] (sum {slots // 6}), "
                     "50 % lattice occupancy, 6 hops, p=10, one accepted move per replica per step",
         "slots_per_step": slots,
