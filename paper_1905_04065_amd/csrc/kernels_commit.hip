@@ -24,15 +24,19 @@ namespace fmmkmc {
 
 
 // Columns m of the local expansion are split into groups whose coefficients
-// fit in registers (at most kSweepBudget doubles); one lane per (cell, group).
-// The per-source work (offset, 1/r, the near test) is shared by a group's
-// columns, and the irregular diagonal I_m^m is carried across them.
-constexpr int kSweepBudget = 56;
+// fit in registers (at most sweep_budget(P) doubles); one lane per (cell,
+// group).  The per-source work (offset, 1/r, the near test) is shared by a
+// group's columns, and the irregular diagonal I_m^m is carried across them, so
+// fewer groups repeat that work less often; 59 doubles give three groups at
+// p = 12 (four at 56) within 168 VGPRs, i.e. three waves per SIMD, which the
+// sweep needs to hide its FP64 dependency chains (two groups at p = 10 would
+// need 65 and spill).
+__host__ __device__ constexpr int sweep_budget(int) { return 59; }
 __host__ __device__ constexpr int col_cost(int P, int m) { return m == 0 ? P + 1 : 2 * (P - m + 1); }
 __host__ __device__ constexpr int group_end(int P, int m0)
 {
     int acc = col_cost(P, m0), m = m0;
-    while (m + 1 <= P && acc + col_cost(P, m + 1) <= kSweepBudget) acc += col_cost(P, ++m);
+    while (m + 1 <= P && acc + col_cost(P, m + 1) <= sweep_budget(P)) acc += col_cost(P, ++m);
     return m;
 }
 __host__ __device__ constexpr int n_groups(int P)
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(256) void k_levels(Geo g, Move mv, double *const *_
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_sweep(Geo g, int64_t M, Move mv, double *__restrict__ psi,
+__global__ __launch_bounds__(256, 3) void k_sweep(Geo g, int64_t M, Move mv, double *__restrict__ psi,
                                                float *__restrict__ psi32)
 {
     __shared__ SweepSources S;
@@ -528,7 +532,7 @@ void launch_commit(fmmkmc_ctx *c, const Geo &g, const CommitArgs &a, hipStream_t
 // ---- batched replicas ---------------------------------------------------------
 
 template <int P>
-__global__ __launch_bounds__(256) void k_b_sweep(const RepDev *__restrict__ reps, int R,
+__global__ __launch_bounds__(256, 3) void k_b_sweep(const RepDev *__restrict__ reps, int R,
                                                  const int64_t *__restrict__ base, const MoveDev *__restrict__ moves)
 {
     const int r = find_rep(base, R, blockIdx.x);
