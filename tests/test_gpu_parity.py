@@ -43,6 +43,9 @@ CASES = [
     (16, 300, 3, 8, "periodic"),   # general site kernel, periodic
     (16, 400, 4, 8, "periodic"),   # 2x2x2 kernel, periodic
     (20, 500, 4, 7, "periodic"),   # non-integer cell width (2.5 sites), ties at cell faces
+    (13, 300, 4, 6, "periodic"),   # 1.625 sites per cell edge: cells of one and of two planes
+    (6, 40, 4, 5, "periodic"),     # 0.75 sites per cell edge: cells with no plane at all
+    (10, 100, 4, 6, "free"),       # 1.25 sites per cell edge, clamped boxes at the faces
     (16, 200, 2, 6, "free"),       # 8 sites per cell axis: boxes beyond the 1/sqrt table (computed 1/|d|)
 ]
 
