@@ -962,6 +962,29 @@ __host__ __device__ constexpr int s2_d2(int u, int nb, int v)
     return dx * dx + dy * dy + dz * dz;
 }
 
+// near-field terms of neighbour cell NB at the 8 sites of a cell: compile-time
+// 1/|d| (unit spacing), so no lane reads a weight from memory
+template <int NB, typename Real>
+__device__ __forceinline__ void s2_near_cell(const Real (&qv)[8], double (&near_)[8])
+{
+    constexpr InvSqrt IS{};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        Real part = Real(0);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) part += (Real)IS.v[s2_d2(u, NB, v)] * qv[v];
+        near_[u] += (double)part;
+    }
+}
+
+// neighbour nb (uniform over the wave): one branch to its compile-time weights
+template <typename Real, int... NBs>
+__device__ __forceinline__ void s2_near_switch(int nb, const Real (&qv)[8], double (&near_)[8],
+                                               std::integer_sequence<int, NBs...>)
+{
+    (void)((nb == NBs ? (s2_near_cell<NBs, Real>(qv, near_), true) : false) || ...);
+}
+
 // The two halves of the work have different shapes: the class sums stream
 // (p+1)^2 coefficients per cell from HBM, the near field walks 27 neighbour
 // cells through L2.  Fused in one lane they need the registers of both and run
@@ -976,11 +999,11 @@ __host__ __device__ constexpr int s2_d2(int u, int nb, int v)
 template <int NW>
 constexpr int s2_cells() { return 32 * NW; }  // cells per block
 
-// LDS of the 2x2x2 body: the near-field 1/|d| table, the two per-site results
+// LDS of the 2x2x2 body: the two per-site results
 template <bool MIXED, int NW>
 constexpr int s2_smem_bytes()
 {
-    return (int)(27 * 64 * (MIXED ? sizeof(float) : sizeof(double))) + 2 * s2_cells<NW>() * 9 * 8;
+    return 2 * s2_cells<NW>() * 9 * 8;
 }
 
 template <int P, bool MIXED, int NW>
@@ -998,18 +1021,9 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
     const auto site_rank = as_global(site_rank_);
     const auto phisite = as_global(phisite_), phi_r = as_global(phi_r_);
     constexpr S2Weights<P> W{};
-    constexpr InvSqrt IS{};
     // per cell and site: local-expansion part, near + far-field part (row of 9: no bank conflicts)
     constexpr int CELLS = s2_cells<NW>();
     double *sFar = (double *)smem, *sNear = sFar + CELLS * 9;
-    // 1/|d| between the 8 sites of a cell and the 8 sites of each of its 27
-    // neighbours, [nb][u][v], unit spacing
-    Real *sT = (Real *)(sNear + CELLS * 9);
-    for (int e = threadIdx.x; e < 27 * 64; e += blockDim.x) {
-        const int nb = e / 64, u = (e / 8) % 8, v = e % 8;
-        sT[e] = (Real)IS.v[s2_d2(u, nb, v)];
-    }
-    __syncthreads();
     // per-level mode: this thread's sites' coarse-level sums, loaded now so that
     // their latency hides behind the work below
     constexpr int PER = CELLS * 8 / (64 * NW);
@@ -1126,14 +1140,7 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
                 const int64_t b1 = cell_base(nb + 1, ok);
                 load8(b1, ok, qn);
             }
-            const Real *tb = sT + nb * 64;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                Real part = Real(0);
-#pragma unroll
-                for (int v = 0; v < 8; ++v) part += tb[u * 8 + v] * qv[v];
-                near_[u] += (double)part;
-            }
+            s2_near_switch<Real>(nb, qv, near_, std::make_integer_sequence<int, 27>{});
         }
         // far field of V_inf at the 8 sites: the 4 (i, j) rows of Bz against the two Tax rows 2cz, 2cz+1
         double fs[8] = {};
