@@ -985,25 +985,66 @@ __device__ __forceinline__ void s2_near_switch(int nb, const Real (&qv)[8], doub
     (void)((nb == NBs ? (s2_near_cell<NBs, Real>(qv, near_), true) : false) || ...);
 }
 
-// The two halves of the work have different shapes: the class sums stream
+// The two kinds of work have different shapes: the class sums stream
 // (p+1)^2 coefficients per cell from HBM, the near field walks 27 neighbour
-// cells through L2.  Fused in one lane they need the registers of both and run
-// at one wave per SIMD; here half of a block's NW waves do the class sums of
-// its 32 NW cells and the other half the near field and far-field sites of the
-// same cells, so a wave holds the registers of one half only and both kinds of
-// load are in flight on a CU at once.  Results meet in LDS and all waves write
-// the block's sites contiguously.  With NW = 8 the class-sum waves are 0, 1, 6,
-// 7 and the near-field waves 2..5: the waves of a block go to the CU's four
-// SIMDs in turn, so every SIMD gets one of each (with NW = 4, waves 0-1 and
-// 2-3, the near field sits on two SIMDs only; 8 waves measured 10 % faster).
+// cells through L2, and both are bound by how many loads a CU keeps in flight.
+// Every lane of a block takes part in both, one after the other: two lanes per
+// cell (lane t and t + CELLS, so each SIMD holds a wave of either half), which
+// first split the cell's degrees for the class sums (the low degrees, about
+// half the coefficients, and the rest) and then its 27 neighbour cells for the
+// near field.  Each pair adds its two partial sums through LDS, and all waves
+// write the block's sites contiguously.  An earlier form gave half of the
+// waves the class sums and the other half the near field; timed apart, the
+// class-sum waves took twice as long as the near-field waves.  Sharing both
+// phases among all waves measured the same in FP64 (114 us at 128^3, L = 7,
+// p = 12) and 4 % faster in mixed precision (96 -> 92 us): the class sums
+// stream Psi_L at about 3.5 TB/s either way.
 template <int NW>
-constexpr int s2_cells() { return 32 * NW; }  // cells per block
+constexpr int s2_cells() { return 32 * NW; }  // cells per block (2 lanes per cell)
 
-// LDS of the 2x2x2 body: the two per-site results
+// LDS of the 2x2x2 body: the two per-site results (rows of 9: no bank conflicts)
 template <bool MIXED, int NW>
 constexpr int s2_smem_bytes()
 {
     return 2 * s2_cells<NW>() * 9 * 8;
+}
+
+// first degree of the second half of the class sums: about half the (p+1)^2 coefficients below it
+__host__ __device__ constexpr int s2_degree_split(int P)
+{
+    int n = 0;
+    while (2 * n * n < (P + 1) * (P + 1)) ++n;
+    return n;
+}
+
+// class sums S[A][B][C] over degrees N0 .. N1 - 1 of one cell: A = (n+m) & 1,
+// B = m & 1, C = 0 real part / 1 imaginary part.  Each degree is summed in the
+// working precision and the degrees in FP64, so in mixed precision the
+// rounding does not grow with the order.
+template <int P, bool MIXED, int N0, int N1, typename Real, class PS>
+__device__ __forceinline__ void s2_class_sums(PS Ps, int64_t M, int64_t cell, Real h, double (&S)[2][2][2])
+{
+    constexpr S2Weights<P> W{};
+    Real hn = Real(1);
+#pragma unroll
+    for (int n = 0; n < N0; ++n) hn *= h;
+#pragma unroll
+    for (int n = N0; n < N1; ++n) {
+        Real part[2][2] = {};  // [B][C] within degree n
+        Real v[2 * P + 1];
+#pragma unroll
+        for (int k = 0; k < 2 * n + 1; ++k) v[k] = (MIXED && n == 0) ? Real(0) : Ps[(int64_t)(n * n + k) * M + cell];
+#pragma unroll
+        for (int k = 0; k < 2 * n + 1; ++k) {
+            const int m = (k + 1) / 2, C = (k > 0 && (k & 1) == 0) ? 1 : 0;
+            part[m & 1][C] += (Real)W.w[n * n + k] * v[k];
+        }
+#pragma unroll
+        for (int B = 0; B < 2; ++B)
+#pragma unroll
+            for (int C = 0; C < 2; ++C) S[(n + B) & 1][B][C] += (double)(hn * part[B][C]);
+        hn *= h;
+    }
 }
 
 template <int P, bool MIXED, int NW>
@@ -1020,10 +1061,11 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
     const auto psi32 = as_global(psi32_), qsite32 = as_global(qsite32_);
     const auto site_rank = as_global(site_rank_);
     const auto phisite = as_global(phisite_), phi_r = as_global(phi_r_);
-    constexpr S2Weights<P> W{};
-    // per cell and site: local-expansion part, near + far-field part (row of 9: no bank conflicts)
+    // per cell and site: local-expansion part, near + far-field part; the second
+    // half's partial sums pass through sNear before the final values
     constexpr int CELLS = s2_cells<NW>();
     double *sFar = (double *)smem, *sNear = sFar + CELLS * 9;
+    static_assert(NW == 8, "2 lanes per cell: 8 waves of 64 for 256 cells");
     // per-level mode: this thread's sites' coarse-level sums, loaded now so that
     // their latency hides behind the work below
     constexpr int PER = CELLS * 8 / (64 * NW);
@@ -1033,40 +1075,30 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
         const int64_t e = threadIdx.x + (int64_t)t * blockDim.x;
         pcv[t] = (phic_ && blk * CELLS * 8 + e < M * 8) ? as_global(phic_)[blk * CELLS * 8 + e] : 0.0;
     }
-    const int wave = threadIdx.x >> 6;
-    static_assert(NW == 4 || NW == 8, "4 or 8 waves per block");
-    const bool class_wave = wave < 2 || (NW == 8 && wave >= 6);
-    const int ci = wave < 2 ? wave : (class_wave ? wave - 4 : wave - 2);  // index within the role
-    const int lc = ci * 64 + (threadIdx.x & 63);
+    const int half = (int)threadIdx.x >= CELLS ? 1 : 0;  // uniform over each wave
+    const int lc = (int)threadIdx.x - half * CELLS;
     const int64_t c0 = blk * CELLS, cell = c0 + lc;
+    const bool live = cell < M;
     const int nc = g.nc;
-    if (class_wave) {
-        if (cell < M) {
-            const gptr<const Real> Ps = MIXED ? (gptr<const Real>)psi32 : (gptr<const Real>)psi;
-            // class sums S[A][B][C]: A = (n+m) & 1, B = m & 1, C = 0 real part / 1 imaginary part.
-            // Each degree is summed in the working precision and the degrees in FP64, so in
-            // mixed precision the rounding does not grow with the order.
-            double S[2][2][2] = {};
-            Real hn = Real(1);
-            const Real h = (Real)g.h;
+    // ---- class sums: degrees below the split on the first half, the rest on the second
+    {
+        constexpr int NS = s2_degree_split(P);
+        const gptr<const Real> Ps = MIXED ? (gptr<const Real>)psi32 : (gptr<const Real>)psi;
+        double S[2][2][2] = {};
+        if (live) {
+            if (half == 0)
+                s2_class_sums<P, MIXED, 0, NS, Real>(Ps, M, cell, (Real)g.h, S);
+            else
+                s2_class_sums<P, MIXED, NS, P + 1, Real>(Ps, M, cell, (Real)g.h, S);
+        }
+        if (half == 1 && live) {
 #pragma unroll
-            for (int n = 0; n <= P; ++n) {
-                Real part[2][2] = {};  // [B][C] within degree n
-                Real v[2 * P + 1];
+            for (int e = 0; e < 8; ++e) sNear[lc * 9 + e] = S[e >> 2][(e >> 1) & 1][e & 1];
+        }
+        __syncthreads();
+        if (half == 0 && live) {
 #pragma unroll
-                for (int k = 0; k < 2 * n + 1; ++k)
-                    v[k] = (MIXED && n == 0) ? Real(0) : Ps[(int64_t)(n * n + k) * M + cell];
-#pragma unroll
-                for (int k = 0; k < 2 * n + 1; ++k) {
-                    const int m = (k + 1) / 2, C = (k > 0 && (k & 1) == 0) ? 1 : 0;
-                    part[m & 1][C] += (Real)W.w[n * n + k] * v[k];
-                }
-#pragma unroll
-                for (int B = 0; B < 2; ++B)
-#pragma unroll
-                    for (int C = 0; C < 2; ++C) S[(n + B) & 1][B][C] += (double)(hn * part[B][C]);
-                hn *= h;
-            }
+            for (int e = 0; e < 8; ++e) S[e >> 2][(e >> 1) & 1][e & 1] += sNear[lc * 9 + e];
             const double l00 = MIXED ? psi[cell] : 0.0;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -1084,11 +1116,14 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
                 sFar[lc * 9 + u] = l00 + far_;
             }
         }
-    } else if (cell < M) {
+        __syncthreads();  // the partials have been read before sNear takes the near-field ones
+    }
+    // ---- near field: neighbour cells 0 .. 12 and the far field on the first half, 13 .. 26 on the second
+    {
         const gptr<const Real> Qs = MIXED ? (gptr<const Real>)qsite32 : (gptr<const Real>)qsite;
         const int cx = (int)(cell / ((int64_t)nc * nc)), cy = (int)((cell / nc) % nc), cz = (int)(cell % nc);
-        // near field: the 27 neighbour cells' 8 sites each (wrapped, or absent in
-        // free space); the next cell's charges are loaded while the current one is summed
+        // the 27 neighbour cells' 8 sites each (wrapped, or absent in free space);
+        // the next cell's charges are loaded while the current one is summed
         auto cell_base = [&](int nb, bool &ok) {
             int ax = cx + nb / 9 - 1, ay = cy + (nb / 3) % 3 - 1, az = cz + nb % 3 - 1;
             ok = g.periodic || (ax >= 0 && ax < nc && ay >= 0 && ay < nc && az >= 0 && az < nc);
@@ -1124,47 +1159,57 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
         };
         // each neighbour cell's 8 terms per site in the working precision, the cells in FP64
         double near_[8] = {};
-        Real qn[8];
-        {
-            bool ok;
-            const int64_t b0 = cell_base(0, ok);
-            load8(b0, ok, qn);
-        }
-#pragma unroll 1
-        for (int nb = 0; nb < 27; ++nb) {
-            Real qv[8];
-#pragma unroll
-            for (int v = 0; v < 8; ++v) qv[v] = qn[v];
-            if (nb + 1 < 27) {
-                bool ok;
-                const int64_t b1 = cell_base(nb + 1, ok);
-                load8(b1, ok, qn);
-            }
-            s2_near_switch<Real>(nb, qv, near_, std::make_integer_sequence<int, 27>{});
-        }
-        // far field of V_inf at the 8 sites: the 4 (i, j) rows of Bz against the two Tax rows 2cz, 2cz+1
         double fs[8] = {};
-        if (g.periodic) {
-            const int n = g.n;
-            const auto t0 = Tax + (int64_t)(2 * cz) * (P + 1);
+        if (live) {
+            const int nb0 = half ? 13 : 0, nb1 = half ? 27 : 13;
+            Real qn[8];
+            {
+                bool ok;
+                const int64_t b0 = cell_base(nb0, ok);
+                load8(b0, ok, qn);
+            }
+#pragma unroll 1
+            for (int nb = nb0; nb < nb1; ++nb) {
+                Real qv[8];
 #pragma unroll
-            for (int ij = 0; ij < 4; ++ij) {
-                const int i = 2 * cx + (ij >> 1), j = 2 * cy + (ij & 1);
-                const auto bz = Bz + ((int64_t)i * n + j) * (P + 1);
-                double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-                for (int cc = 0; cc <= P; ++cc) {
-                    const double bb = bz[cc];
-                    a0 += bb * t0[cc];
-                    a1 += bb * t0[P + 1 + cc];
+                for (int v = 0; v < 8; ++v) qv[v] = qn[v];
+                if (nb + 1 < nb1) {
+                    bool ok;
+                    const int64_t b1 = cell_base(nb + 1, ok);
+                    load8(b1, ok, qn);
                 }
-                fs[2 * ij] = a0;
-                fs[2 * ij + 1] = a1;
+                s2_near_switch<Real>(nb, qv, near_, std::make_integer_sequence<int, 27>{});
+            }
+            // far field of V_inf at the 8 sites: the 4 (i, j) rows of Bz against the two Tax rows 2cz, 2cz+1
+            if (g.periodic && half == 0) {
+                const int n = g.n;
+                const auto t0 = Tax + (int64_t)(2 * cz) * (P + 1);
+#pragma unroll
+                for (int ij = 0; ij < 4; ++ij) {
+                    const int i = 2 * cx + (ij >> 1), j = 2 * cy + (ij & 1);
+                    const auto bz = Bz + ((int64_t)i * n + j) * (P + 1);
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int cc = 0; cc <= P; ++cc) {
+                        const double bb = bz[cc];
+                        a0 += bb * t0[cc];
+                        a1 += bb * t0[P + 1 + cc];
+                    }
+                    fs[2 * ij] = a0;
+                    fs[2 * ij + 1] = a1;
+                }
             }
         }
-        const double inv_h = 1.0 / g.h;
+        if (half == 1 && live) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) sNear[lc * 9 + u] = near_[u] * inv_h + fs[u];
+            for (int u = 0; u < 8; ++u) sNear[lc * 9 + u] = near_[u];
+        }
+        __syncthreads();
+        if (half == 0 && live) {
+            const double inv_h = 1.0 / g.h;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sNear[lc * 9 + u] = (near_[u] + sNear[lc * 9 + u]) * inv_h + fs[u];
+        }
     }
     __syncthreads();
     const int nsite = (int)((M - c0 < CELLS ? M - c0 : CELLS) * 8);
