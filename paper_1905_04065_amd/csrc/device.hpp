@@ -258,11 +258,12 @@ __device__ inline T l2p_cols(PT L, long stride, T x, T y, T z)
 // chain is at most p steps long instead of the (p+1)^2 of a single lane.
 __device__ inline void harmonics_column(int p, int m, double x, double y, double z, double *Km, double *Wt)
 {
-    constexpr RecTables T{};
+    // the recurrence factors are computed, not looked up: a table indexed by the
+    // lane's column is a dependent global load per step
     const double r2 = x * x + y * y + z * z;
     double ar = 1.0, ai = 0.0;
     for (int k = 1; k <= m; ++k) {
-        const double f = -T.half_inv[k];
+        const double f = -0.5 / (double)k;
         const double nr = f * (x * ar - y * ai), ni = f * (x * ai + y * ar);
         ar = nr;
         ai = ni;
@@ -279,7 +280,7 @@ __device__ inline void harmonics_column(int p, int m, double x, double y, double
             br = cr;
             bi = ci;
         } else {
-            const double w = T.rinv[n][m];
+            const double w = 1.0 / (double)((n + m) * (n - m));
             cr = ((2 * n - 1) * z * br - r2 * ar) * w;
             ci = ((2 * n - 1) * z * bi - r2 * ai) * w;
             ar = br;

@@ -1763,8 +1763,20 @@ __device__ __forceinline__ void frow_w_body(int blk, Geo g, int p, int64_t s_sit
     __syncthreads();
     const int lr = tid & 15, ls = tid >> 4, row = blk * kFrowRows + lr;
     double acc = 0.0;
-    if (row < nt)
-        for (int m = ls; m < nt; m += 16) acc += R[(int64_t)m * nt + row] * K1[m];
+    if (row < nt) {
+        // four independent loads in flight
+        double a4[4] = {};
+        int m = ls;
+        for (; m + 48 < nt; m += 64) {
+            double r4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r4[u] = R[(int64_t)(m + 16 * u) * nt + row];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a4[u] += r4[u] * K1[m + 16 * u];
+        }
+        for (; m < nt; m += 16) a4[0] += R[(int64_t)m * nt + row] * K1[m];
+        acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    }
     red[tid] = acc;
     __syncthreads();
     if (ls == 0 && row < nt) {
