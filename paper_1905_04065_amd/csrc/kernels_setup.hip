@@ -105,39 +105,79 @@ void launch_p2m(fmmkmc_ctx *c, const Geo &g)
 }
 
 // ---- matrix-vector translation kernels ------------------------------------
-// out[k][cell] = sum_n mat[n][k] * in[n][cell'] with the matrix uniform over a
-// wavefront (scalar loads) and in/out rows coalesced over consecutive cells.
-// Outputs are produced KB at a time.
+// out[k][cell] = sum_n mat[n][k] * in[n][cell'] with in/out rows coalesced over
+// consecutive cells.
 
-constexpr int KB = 16;
+// matrix entries a thread loads at once before using them (the sums still run
+// in order of n)
+constexpr int kPre = 16;
 
-// M2M: parent cell per lane; 8 children with level-specific matrices.
+// M2M: one thread per (parent cell, output coefficient k).  The threads of a
+// wave share the parent (each parent takes nt rounded up to a multiple of 64
+// threads), so they read the same child coefficients and consecutive matrix
+// entries; the sum runs over the 8 children, then n.
 __global__ __launch_bounds__(256) void k_m2m(int nt, int ncp, const double *__restrict__ mats,
                                              const double *__restrict__ child, double *__restrict__ parent)
 {
     const int64_t Mp = (int64_t)ncp * ncp * ncp, Mc = Mp * 8;
     const int ncc = 2 * ncp;
-    const int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pc >= Mp) return;
+    const int KP = (nt + 63) & ~63;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pc = gt / KP;
+    const int k = (int)(gt - pc * KP);
+    if (pc >= Mp || k >= nt) return;
     const int px = (int)(pc / ((int64_t)ncp * ncp)), py = (int)((pc / ncp) % ncp), pz = (int)(pc % ncp);
-    for (int k0 = 0; k0 < nt; k0 += KB) {
-        double acc[KB];
+    double acc = 0.0;
+    for (int ch = 0; ch < 8; ++ch) {
+        const int64_t cc = cell_id(ncc, 2 * px + (ch >> 2), 2 * py + ((ch >> 1) & 1), 2 * pz + (ch & 1));
+        const double *col = mats + (int64_t)ch * nt * nt + k;
+        const double *cv = child + cc;
+        int n = 0;
+        for (; n + kPre <= nt; n += kPre) {
+            double mv[kPre], xv[kPre];
 #pragma unroll
-        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-        for (int ch = 0; ch < 8; ++ch) {
-            const int64_t cc = cell_id(ncc, 2 * px + (ch >> 2), 2 * py + ((ch >> 1) & 1), 2 * pz + (ch & 1));
-            const double *mat = mats + (int64_t)ch * nt * nt;
-            for (int n = 0; n < nt; ++n) {
-                const double v = child[(int64_t)n * Mc + cc];
-                const double *row = mat + (int64_t)n * nt + k0;
-#pragma unroll
-                for (int t = 0; t < KB; ++t)
-                    if (k0 + t < nt) acc[t] += row[t] * v;
+            for (int j = 0; j < kPre; ++j) {
+                mv[j] = col[(int64_t)(n + j) * nt];
+                xv[j] = cv[(int64_t)(n + j) * Mc];
             }
-        }
 #pragma unroll
-        for (int t = 0; t < KB; ++t)
-            if (k0 + t < nt) parent[(int64_t)(k0 + t) * Mp + pc] = acc[t];
+            for (int j = 0; j < kPre; ++j) acc += mv[j] * xv[j];
+        }
+        for (; n < nt; ++n) acc += col[(int64_t)n * nt] * cv[(int64_t)n * Mc];
+    }
+    parent[(int64_t)k * Mp + pc] = acc;
+}
+
+int64_t m2m_blocks(int nt, int ncp)
+{
+    const int64_t threads = (int64_t)ncp * ncp * ncp * ((nt + 63) & ~63);
+    return (threads + 255) / 256;
+}
+
+// acc[c] += sum_n mat[n][k] * stage[n][c] over n in order, the column entries
+// loaded kPre at a time
+template <int C>
+__device__ __forceinline__ void column_times_stage(double (&acc)[C], const double *__restrict__ mat, int k, int nt,
+                                                   const double *stage)
+{
+    const double *col = mat + k;
+    int n = 0;
+    for (; n + kPre <= nt; n += kPre) {
+        double tv[kPre];
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) tv[j] = col[(int64_t)(n + j) * nt];
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) {
+            const double *sr = stage + (n + j) * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += tv[j] * sr[c];
+        }
+    }
+    for (; n < nt; ++n) {
+        const double tv = col[(int64_t)n * nt];
+        const double *sr = stage + n * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += tv * sr[c];
     }
 }
 
@@ -196,14 +236,7 @@ __global__ __launch_bounds__(256) void k_m2l(int nt, int nc, int periodic, int w
 #pragma unroll
                 for (int u = 0; u < KPT; ++u) {
                     const int k = threadIdx.x + u * 256;
-                    if (k < nt) {
-                        for (int n = 0; n < nt; ++n) {
-                            const double tv = mat[(int64_t)n * nt + k];
-                            const double *sr = stage + n * C;
-#pragma unroll
-                            for (int c = 0; c < C; ++c) acc[u][c] += tv * sr[c];
-                        }
-                    }
+                    if (k < nt) column_times_stage<C>(acc[u], mat, k, nt, stage);
                 }
                 __syncthreads();
             }
@@ -226,14 +259,7 @@ __global__ __launch_bounds__(256) void k_m2l(int nt, int nc, int periodic, int w
 #pragma unroll
         for (int u = 0; u < KPT; ++u) {
             const int k = threadIdx.x + u * 256;
-            if (k < nt) {
-                for (int n = 0; n < nt; ++n) {
-                    const double tv = mat[(int64_t)n * nt + k];
-                    const double *sr = stage + n * C;
-#pragma unroll
-                    for (int c = 0; c < C; ++c) acc[u][c] += tv * sr[c];
-                }
-            }
+            if (k < nt) column_times_stage<C>(acc[u], mat, k, nt, stage);
         }
         __syncthreads();
     }
@@ -259,7 +285,7 @@ void launch_upward(fmmkmc_ctx *c)
     for (int l = c->L - 1; l >= 1; --l) {
         const int ncp = 1 << (l - 1);
         const int64_t Mp = (int64_t)ncp * ncp * ncp;
-        launch(c, "m2m", k_m2m, dim3((unsigned)((Mp + 255) / 256)), dim3(256), c->nt, ncp, c->m2m[l],
+        launch(c, "m2m", k_m2m, dim3((unsigned)m2m_blocks(c->nt, ncp)), dim3(256), c->nt, ncp, c->m2m[l],
                c->phi_lv[l + 1], c->phi_lv[l]);
     }
 }
@@ -275,7 +301,12 @@ void launch_downward(fmmkmc_ctx *c)
         const bool from_parent = l > start && !c->per_level;
         const double *par = from_parent ? c->psi_lv[l - 1] : nullptr;
         const int wp = from_parent ? 1 : 0, per = c->bc == FMMKMC_PERIODIC ? 1 : 0;
-        if (c->nt <= 196) {  // p <= 13: 32 cells per block, <= 50 KB of LDS
+        if (c->nt <= 196 && Mh <= 2048) {  // small levels: 8 cells per block, for more blocks
+            constexpr int C = 8;
+            launch_shm(c, "m2l", k_m2l<C, 1>, dim3((unsigned)((Mh + C - 1) / C), 8), dim3(256),
+                       sizeof(double) * c->nt * C, c->nt, nc, per, wp, c->m2l, c->m2l_index, sin_, sout,
+                       c->l2l[l], c->phi_lv[l], par, c->psi_lv[l]);
+        } else if (c->nt <= 196) {  // p <= 13: 32 cells per block, <= 50 KB of LDS
             constexpr int C = 32;
             launch_shm(c, "m2l", k_m2l<C, 1>, dim3((unsigned)((Mh + C - 1) / C), 8), dim3(256),
                        sizeof(double) * c->nt * C, c->nt, nc, per, wp, c->m2l, c->m2l_index, sin_, sout,
