@@ -119,14 +119,20 @@ struct ScaledIrregular {
 // its copies nu in V_box (periodic; 2 x 27) or alone (free space; 2).  Every
 // lane of a block reads the same source at the same time, so the block builds
 // this table once in LDS: the copy's position, its charge and its fine-cell
-// coordinates (unwrapped, for the near-field test).
+// coordinates (unwrapped, for the near-field test).  mnear: whether the copy
+// can lie in the near field of any of the block's cells (its cell within one
+// of the bounding box of the block's cells); for all other copies the lanes
+// skip their own near-field test.
 struct SweepSources {
     double x[54], y[54], z[54], q[54];
     int gx[54], gy[54], gz[54];
+    int mnear[54];
 };
 
-// by the first 2 x 27 (2) threads of the block; a barrier must follow
-__device__ inline void sweep_sources(const Geo &g, const Move &mv, SweepSources &S)
+// by the first 2 x 27 (2) threads of the block; a barrier must follow.  The
+// block's fine cells are c0 .. c1 (cell order); c1 < c0: unknown (every copy
+// is marked as possibly near).
+__device__ inline void sweep_sources(const Geo &g, const Move &mv, SweepSources &S, int64_t c0 = 0, int64_t c1 = -1)
 {
     const int nimg = g.periodic ? 27 : 1;
     const int t = threadIdx.x;
@@ -142,6 +148,19 @@ __device__ inline void sweep_sources(const Geo &g, const Move &mv, SweepSources 
         S.y[t] = (e ? mv.ny : mv.oy) + g.a * j;
         S.z[t] = (e ? mv.nz : mv.oz) + g.a * k;
         S.q[t] = e ? mv.q : -mv.q;
+        int mn = 1;
+        if (c1 >= c0) {
+            // bounding box of the cells c0 .. c1: consecutive cell ids share x
+            // (then y) only if the first and the last one do
+            const int nc = g.nc;
+            const int x0 = (int)(c0 / ((int64_t)nc * nc)), y0 = (int)((c0 / nc) % nc), z0 = (int)(c0 % nc);
+            const int x1 = (int)(c1 / ((int64_t)nc * nc)), y1 = (int)((c1 / nc) % nc), z1 = (int)(c1 % nc);
+            const bool sx = x0 == x1, sxy = sx && y0 == y1;
+            const int by0 = sx ? y0 : 0, by1 = sx ? y1 : nc - 1, bz0 = sxy ? z0 : 0, bz1 = sxy ? z1 : nc - 1;
+            mn = S.gx[t] >= x0 - 1 && S.gx[t] <= x1 + 1 && S.gy[t] >= by0 - 1 && S.gy[t] <= by1 + 1 &&
+                 S.gz[t] >= bz0 - 1 && S.gz[t] <= bz1 + 1;
+        }
+        S.mnear[t] = mn;
     }
 }
 
@@ -151,7 +170,8 @@ __device__ inline void sweep_sources(const Geo &g, const Move &mv, SweepSources 
 // from the interaction list (the per-level rule); else every copy outside the
 // near field contributes.
 template <int P, int M0, int M1, bool LEVEL, class PD, class PF>
-__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSources &S, PD psi, PF psi32, int sh)
+__device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSources &S, uint64_t mmask, PD psi,
+                           PF psi32, int sh)
 {
     constexpr ScaledIrregular<P> SI{};
     constexpr int NACC = col_offset(P, M0, M1 + 1);
@@ -167,21 +187,27 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
     const int nsrc = g.periodic ? 54 : 2;
 #pragma unroll 1
     for (int t = 0; t < nsrc; ++t) {
-        int sx = S.gx[t], sy = S.gy[t], sz = S.gz[t];
-        if (LEVEL) {  // arithmetic shifts: floor division of the unwrapped coordinates
-            sx >>= sh;
-            sy >>= sh;
-            sz >>= sh;
-        }
-        bool near = ((unsigned)(sx - bx + 1) <= 2u) & ((unsigned)(sy - by + 1) <= 2u) & ((unsigned)(sz - bz + 1) <= 2u);
-        if (LEVEL) {
-            const bool parent_near = ((unsigned)((sx >> 1) - (bx >> 1) + 1) <= 2u) &
-                                     ((unsigned)((sy >> 1) - (by >> 1) + 1) <= 2u) &
-                                     ((unsigned)((sz >> 1) - (bz >> 1) + 1) <= 2u);
-            near = near | !parent_near;  // outside the interaction list: no contribution
-            // most copies lie in no target's interaction list on the finer levels:
-            // skip a copy that no lane of the wave takes (a wave-uniform branch)
-            if (!__any(!near)) continue;
+        // a copy that no cell of the block has in its near field skips the
+        // per-lane test (a block-uniform branch; the sums are the same)
+        const bool mn = LEVEL || ((mmask >> t) & 1);
+        bool near = false;
+        if (mn) {
+            int sx = S.gx[t], sy = S.gy[t], sz = S.gz[t];
+            if (LEVEL) {  // arithmetic shifts: floor division of the unwrapped coordinates
+                sx >>= sh;
+                sy >>= sh;
+                sz >>= sh;
+            }
+            near = ((unsigned)(sx - bx + 1) <= 2u) & ((unsigned)(sy - by + 1) <= 2u) & ((unsigned)(sz - bz + 1) <= 2u);
+            if (LEVEL) {
+                const bool parent_near = ((unsigned)((sx >> 1) - (bx >> 1) + 1) <= 2u) &
+                                         ((unsigned)((sy >> 1) - (by >> 1) + 1) <= 2u) &
+                                         ((unsigned)((sz >> 1) - (bz >> 1) + 1) <= 2u);
+                near = near | !parent_near;  // outside the interaction list: no contribution
+                // most copies lie in no target's interaction list on the finer levels:
+                // skip a copy that no lane of the wave takes (a wave-uniform branch)
+                if (!__any(!near)) continue;
+            }
         }
         // for a near copy the weights are exactly zero; 1/|d| is taken as 1 so
         // that every factor stays finite (|d| may be 0), and the zero weights
@@ -202,9 +228,14 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
 #pragma unroll
             for (int b = 0; (1 << b) <= M0; ++b) {
                 if ((M0 >> b) & 1) {
-                    const double ndr = dr * br - di * bi, ndi = dr * bi + di * br;
-                    dr = ndr;
-                    di = ndi;
+                    if ((M0 & ((1 << b) - 1)) == 0) {  // the lowest set bit: z^(2^b) itself
+                        dr = br;
+                        di = bi;
+                    } else {
+                        const double ndr = dr * br - di * bi, ndi = dr * bi + di * br;
+                        dr = ndr;
+                        di = ndi;
+                    }
                 }
                 if ((2 << b) <= M0) {
                     const double nbr = br * br - bi * bi, nbi = 2.0 * br * bi;
@@ -272,16 +303,27 @@ __device__ void sweep_cols(const Geo g, int64_t M, int64_t cell, const SweepSour
     }
 }
 
+// mmask: bit t set if source copy t may lie in the near field of a cell of the
+// block (sweep_near_mask); LEVEL ignores it
 template <int P, bool LEVEL = false, int G = 0, class PD, class PF>
-__device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const SweepSources &S, PD psi,
-                               PF psi32, int sh = 0)
+__device__ void sweep_dispatch(int grp, const Geo g, int64_t M, int64_t cell, const SweepSources &S, uint64_t mmask,
+                               PD psi, PF psi32, int sh = 0)
 {
     if constexpr (G < n_groups(P)) {
         if (grp == G)
-            sweep_cols<P, group_m0(P, G), group_end(P, group_m0(P, G)), LEVEL>(g, M, cell, S, psi, psi32, sh);
+            sweep_cols<P, group_m0(P, G), group_end(P, group_m0(P, G)), LEVEL>(g, M, cell, S, mmask, psi, psi32,
+                                                                             sh);
         else
-            sweep_dispatch<P, LEVEL, G + 1>(grp, g, M, cell, S, psi, psi32, sh);
+            sweep_dispatch<P, LEVEL, G + 1>(grp, g, M, cell, S, mmask, psi, psi32, sh);
     }
+}
+
+// the copies' mnear flags as a wave-uniform bit mask; every lane of the wave
+// must take part (before any lane leaves)
+__device__ inline uint64_t sweep_near_mask(const Geo &g, const SweepSources &S)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    return __ballot(lane < (g.periodic ? 54 : 2) && S.mnear[lane] != 0);
 }
 
 // Target t of a per-level commit: level lstart + t / (2 * 343), then the 7^3
@@ -338,7 +380,7 @@ __device__ inline void levels_body(int grp, const Geo &gf, const Move &mv, const
     g.nc = 1 << (level - 1);
     g.w = gf.a / g.nc;
     const int64_t Ml = (int64_t)g.nc * g.nc * g.nc;
-    sweep_dispatch<P, true>(grp, g, Ml, cell, S, psi_lv[level], level == gf.L ? psi32 : (PF) nullptr,
+    sweep_dispatch<P, true>(grp, g, Ml, cell, S, ~0ull, psi_lv[level], level == gf.L ? psi32 : (PF) nullptr,
                             gf.L - level);
 }
 
@@ -357,11 +399,13 @@ __global__ __launch_bounds__(256, 3) void k_sweep(Geo g, int64_t M, Move mv, dou
                                                float *__restrict__ psi32)
 {
     __shared__ SweepSources S;
-    sweep_sources(g, mv, S);
+    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x;
+    sweep_sources(g, mv, S, c0, (c0 + blockDim.x < M ? c0 + blockDim.x : M) - 1);
     __syncthreads();
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t mmask = sweep_near_mask(g, S);
+    const int64_t cell = c0 + threadIdx.x;
     if (cell >= M) return;
-    sweep_dispatch<P>(blockIdx.y, g, M, cell, S, psi, psi32);
+    sweep_dispatch<P>(blockIdx.y, g, M, cell, S, mmask, psi, psi32);
 }
 
 // P2M of -q at the old and +q at the new position into the cells containing
@@ -540,16 +584,18 @@ __global__ __launch_bounds__(256, 3) void k_b_sweep(const RepDev *__restrict__ r
     if (!mv.valid) return;  // uniform over the block
     const RepDev &d = reps[r];
     __shared__ SweepSources S;
-    sweep_sources(d.g, mv.mv, S);
+    const int64_t c0 = (blockIdx.x - base[r]) * blockDim.x;
+    sweep_sources(d.g, mv.mv, S, c0, (c0 + blockDim.x < d.M ? c0 + blockDim.x : d.M) - 1);
     __syncthreads();
-    const int64_t cell = (blockIdx.x - base[r]) * blockDim.x + threadIdx.x;
+    const uint64_t mmask = sweep_near_mask(d.g, S);
+    const int64_t cell = c0 + threadIdx.x;
     if (cell >= d.M) return;
     // The expansions' pointers come from the replica table, so the compiler
     // cannot tell they address global memory and would use flat loads and
     // stores for the write-back; global-space pointers keep it global.
     using GD = __attribute__((address_space(1))) double;
     using GF = __attribute__((address_space(1))) float;
-    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, S, (GD *)d.psi, (GF *)d.psi32);
+    sweep_dispatch<P>(blockIdx.y, d.g, d.M, cell, S, mmask, (GD *)d.psi, (GF *)d.psi32);
 }
 
 // per-level commit of every replica: nb blocks per replica
