@@ -521,7 +521,7 @@ int create_impl(const fmmkmc_params *prm, int64_t n, const double *xyz, const do
         // per-level mode: the coarser levels' potential per site (none when only the fine level has an
         // interaction list)
         const int lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
-        if (c->per_level && c->L - 1 >= lstart) c->phicoarse = dalloc<double>(ns);
+        if (c->per_level && c->L - 1 >= lstart) c->phicoarse = dalloc<double>(ns * (c->s2 ? c->L - lstart : 1));
         {
             // charge per site in site order (0 on a vacant site)
             std::vector<double> qs(ns, 0.0);
@@ -651,6 +651,7 @@ Geo make_geo(const fmmkmc_ctx *c)
     g.L = c->L;
     g.lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
     g.q32 = c->qsite32 ? 1 : 0;
+    g.ncoarse = c->phicoarse ? (c->s2 ? c->L - g.lstart : 1) : 0;
     for (int k = 0; k < 3; ++k) g.field[k] = c->field[k];
     return g;
 }

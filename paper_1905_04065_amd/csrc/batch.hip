@@ -421,7 +421,7 @@ struct fmmkmc_batch {
     int cap_steps = 0;
     // phases
     Phase site, site_lf, site_gen, slot, count, sweep, path, far, cheb_a, cheb_b, coarse;
-    std::vector<Phase> coarse_s2;  // per depth below the fine level (2x2x2 replicas)
+    Phase coarse_s2;  // every coarse level of the 2x2x2 replicas (per-level mode)
     int slot_tc = 64, sweep_block = 256;
     bool per_level = false;  // replicas keep their local expansions per level (no sweep)
     int Lmax = 0;
@@ -480,8 +480,8 @@ void record_step(fmmkmc_batch *b)
     const int R = b->R;
     if (b->per_level) {
         launch_b_coarse(b->prof, s, b->reps, R, b->coarse.d, b->coarse.blocks, b->p);
-        for (int dpt = 0; dpt < (int)b->coarse_s2.size(); ++dpt)
-            launch_b_coarse_s2(b->prof, s, b->reps, R, b->coarse_s2[dpt].d, b->coarse_s2[dpt].blocks, b->p, dpt);
+        if (b->coarse_s2.blocks)
+            launch_b_coarse_s2(b->prof, s, b->reps, R, b->coarse_s2.d, b->coarse_s2.blocks, b->p);
     }
     launch_b_site(b->prof, s, b->reps, R, b->site.d, b->site.blocks, b->site_lf.d, b->site_lf.blocks, b->site_gen.d,
                   b->site_gen.blocks, b->p, b->mixed);
@@ -584,9 +584,8 @@ void release_batch(fmmkmc_batch *b)
     dfree(b->out_site);
     dfree(b->out_dU);
     dfree(b->out_dt);
-    for (Phase &ph : b->coarse_s2) dfree(ph.d);
     for (Phase *ph : {&b->site, &b->site_lf, &b->site_gen, &b->slot, &b->count, &b->sweep, &b->path, &b->far,
-                      &b->cheb_a, &b->cheb_b, &b->coarse})
+                      &b->cheb_a, &b->cheb_b, &b->coarse, &b->coarse_s2})
         dfree(ph->d);
     for (auto &pd : b->prof.pending) {
         (void)hipEventDestroy(pd.a);
@@ -798,19 +797,15 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
             ncoarse[r] = (c->phicoarse && !c->s2) ? (ns + 255) / 256 : 0;
         }
         set_phase(b->coarse, ncoarse, s);
-        if (b->per_level) {
-            // 2x2x2 replicas: levels L_r - 1 down to 2, one phase per depth
-            const int depths = b->Lmax - 1 - 2 + 1;
-            b->coarse_s2.assign(std::max(depths, 0), Phase{});
-            for (int dpt = 0; dpt < (int)b->coarse_s2.size(); ++dpt) {
-                std::vector<int64_t> nc2(n, 0);
-                for (int r = 0; r < n; ++r) {
-                    const fmmkmc_ctx *c = ctx[r];
-                    const int level = c->L - 1 - dpt, lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
-                    if (c->phicoarse && c->s2 && level >= lstart) nc2[r] = coarse_s2_level_blocks(c->L, level);
-                }
-                set_phase(b->coarse_s2[dpt], nc2, s);
+        {
+            // 2x2x2 replicas: every coarse level in one launch
+            std::vector<int64_t> nc2(n, 0);
+            for (int r = 0; r < n; ++r) {
+                const fmmkmc_ctx *c = ctx[r];
+                const int lstart = c->bc == FMMKMC_PERIODIC ? 2 : 3;
+                if (c->phicoarse && c->s2) nc2[r] = coarse_s2_replica_blocks(c->L, lstart);
             }
+            set_phase(b->coarse_s2, nc2, s);
         }
         set_phase(b->site, nsite, s);
         set_phase(b->site_lf, nsite_lf, s);

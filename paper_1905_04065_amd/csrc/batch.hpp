@@ -100,11 +100,11 @@ void launch_b_levels(Profiler &pr, hipStream_t st, const RepDev *reps, int R, in
 // per-level mode: the coarse levels' potential at every site of every replica
 void launch_b_coarse(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
                      int p);
-// ... on 2x2x2 lattices, the orbit kernel for level L_r - 1 - depth of every replica
+// ... on 2x2x2 lattices, the orbit kernel for every coarse level of every replica (one launch)
 void launch_b_coarse_s2(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
-                        int p, int depth);
-// blocks of the orbit kernel for one level of a 2x2x2 lattice with L levels
-int64_t coarse_s2_level_blocks(int L, int level);
+                        int p);
+// blocks of that kernel for one 2x2x2 replica with L levels, coarse levels lstart .. L-1
+int64_t coarse_s2_replica_blocks(int L, int lstart);
 void launch_b_book(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const MoveDev *moves);
 void launch_b_far(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base_far,
                   int64_t blocks_far, const int64_t *base_a, int64_t blocks_a, const int64_t *base_b,

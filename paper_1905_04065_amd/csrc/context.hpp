@@ -35,6 +35,9 @@ struct Geo {
     int lstart;      // first level with an interaction list (periodic 2, free space 3)
     int q32;         // lattice: an FP32 copy of the site charges exists (mixed precision, or every
                      // charge is exactly an FP32 number)
+    int ncoarse;     // per-level mode, lattice: per-site arrays of the coarse levels' potential (0: none;
+                     // 2x2x2 lattices one per level, array a holding level L-1-a; other lattices one
+                     // array of all levels)
     double field[3];  // uniform external field E: a hop by d adds -q E.d
 };
 

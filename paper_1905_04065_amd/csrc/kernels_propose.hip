@@ -222,6 +222,15 @@ __device__ inline bool gen_yz(int ch, int n, int t, int &sj, int &sk)
     return active;
 }
 
+// per-level mode: the coarse levels' potential at site s (site order), from
+// g.ncoarse per-site arrays of ns entries added in array order
+__device__ __forceinline__ double coarse_at(const Geo &g, gptr<const double> phic, int64_t ns, int64_t s)
+{
+    double v = 0.0;
+    for (int a = 0; a < g.ncoarse; ++a) v += phic[(int64_t)a * ns + s];
+    return v;
+}
+
 template <int P, bool MIXED>
 __device__ __forceinline__ void site_general_boxrows(int si, int ch, Geo g, int64_t M, const double *__restrict__ psi_,
                                                   const float *__restrict__ psi32_, const double *__restrict__ Bz_,
@@ -805,7 +814,7 @@ __device__ __forceinline__ void site_lf_body(int64_t blk, Geo g, int64_t M, cons
         const int si = x0 + q;
         const int64_t s = ((int64_t)si * n + sj) * n + sk;
         double phi = c0 + l;
-        if (phic_) phi += as_global(phic_)[s];  // per-level mode: the coarser levels
+        if (phic_) phi += coarse_at(g, as_global(phic_), (int64_t)n * n * n, s);  // per-level mode: the coarser levels
         if (g.periodic) phi += far_site<P>(n, si, sj, sk, Bz, Tax);
         as_global(phisite_)[s] = phi;
     };
@@ -1073,7 +1082,8 @@ __device__ __forceinline__ void site_s2_body(int64_t blk, Geo g, int64_t M, cons
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
         const int64_t e = threadIdx.x + (int64_t)t * blockDim.x;
-        pcv[t] = (phic_ && blk * CELLS * 8 + e < M * 8) ? as_global(phic_)[blk * CELLS * 8 + e] : 0.0;
+        pcv[t] = (phic_ && blk * CELLS * 8 + e < M * 8) ? coarse_at(g, as_global(phic_), M * 8, blk * CELLS * 8 + e)
+                                                        : 0.0;
     }
     const int half = (int)threadIdx.x >= CELLS ? 1 : 0;  // uniform over each wave
     const int lc = (int)threadIdx.x - half * CELLS;
@@ -1313,8 +1323,8 @@ __global__ __launch_bounds__(256) void k_coarse_sites(Geo g, double *const *__re
 // One lane per (level-l cell, orbit); the orbit's base offset is
 // ((bx + 1/2) h, (by + 1/2) h, (bz + 1/2) h), bx, by, bz in [0, W/2).  A block
 // covers whole cells (or a part of one cell's orbits) and first stages their
-// coefficients in LDS with coalesced loads.  The first level launched writes,
-// the others add.
+// coefficients in LDS with coalesced loads.  Every coarse level is one launch,
+// each level writing its own per-site array (the site kernels add them).
 // 128 lanes per block: one cell's orbits in chunks of 128, or 128 / orbits whole
 // cells (their staged coefficients then take at most 16 x (p+1)^2 doubles)
 constexpr int kCoarseThreads = 128;
@@ -1358,7 +1368,7 @@ struct ScaledRegular {
 };
 
 template <int P>
-__device__ inline void coarse_s2_body(const Geo &g, int level, const double *__restrict__ psi, int first,
+__device__ inline void coarse_s2_body(const Geo &g, int level, const double *__restrict__ psi,
                                       double *__restrict__ phic, int64_t blk, double *sL)
 {
     constexpr int NT = (P + 1) * (P + 1);
@@ -1395,18 +1405,15 @@ __device__ inline void coarse_s2_body(const Geo &g, int level, const double *__r
     const double x = (bx + 0.5) * g.h, y = (by + 0.5) * g.h, z = (bz + 0.5) * g.h;
     const double nr2 = -(x * x + y * y + z * z);
     const double *L = sL + cl * NT;
-    // the orbit's eight sites, and (after the first level) their running sums,
-    // loaded before the arithmetic so the loads overlap it
+    // the orbit's eight sites
     const int W = 2 * Hh;
     int64_t at[8];
-    double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int fx = (u >> 2) & 1, fy = (u >> 1) & 1, fz = u & 1;  // 1: the reflected side
         const int i = cx * W + Hh + (fx ? -1 - bx : bx), j = cy * W + Hh + (fy ? -1 - by : by),
                   k = cz * W + Hh + (fz ? -1 - bz : bz);
         at[u] = s2_site(g.nc, i, j, k);
-        v[u] = first ? 0.0 : phic[at[u]];
     }
     // class sums S[A][B][C]: A = (n + m) & 1, B = m & 1, C = 0 real / 1 imaginary part
     double S[2][2][2] = {};
@@ -1464,7 +1471,7 @@ __device__ inline void coarse_s2_body(const Geo &g, int level, const double *__r
                 const double sim = sz * ((fx && !B) ? -1.0 : 1.0) * (fy ? -1.0 : 1.0);
                 acc += sre * S[A][B][0] + sim * S[A][B][1];
             }
-        phic[at[u]] = v[u] + acc;
+        phic[at[u]] = acc;
     }
 }
 
@@ -1477,12 +1484,40 @@ __host__ __device__ inline int64_t coarse_s2_blocks(int L, int level)
     return C > 1 ? (Ml + C - 1) / C : Ml * (orbits / kCoarseThreads);
 }
 
+// blocks of the orbit kernel for all coarse levels lstart .. L-1 of a 2x2x2
+// lattice in one launch, level L-1 first
+__host__ __device__ inline int64_t coarse_s2_all_blocks(int L, int lstart)
+{
+    int64_t b = 0;
+    for (int l = L - 1; l >= lstart; --l) b += coarse_s2_blocks(L, l);
+    return b;
+}
+
+// block blk of that launch: its level, and blk becomes the block within the level
+__device__ inline int coarse_s2_level_of(int L, int lstart, int64_t &blk)
+{
+    int l = L - 1;
+    for (; l > lstart; --l) {
+        const int64_t nb = coarse_s2_blocks(L, l);
+        if (blk < nb) break;
+        blk -= nb;
+    }
+    return l;
+}
+
+// LDS of an orbit-kernel block: the most cells per block any level has (its finest, 8 orbits per cell)
+inline size_t coarse_s2_shm(int p) { return sizeof(double) * (p + 1) * (p + 1) * coarse_cells_per_block(8); }
+
+// every coarse level in one launch, level l into per-site array L-1-l
 template <int P>
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_s2(Geo g, int level, const double *__restrict__ psi, int first,
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_s2(Geo g, double *const *__restrict__ psi_lv,
                                                    double *__restrict__ phic)
 {
     extern __shared__ double sL[];
-    coarse_s2_body<P>(g, level, psi, first, phic, blockIdx.x, sL);
+    int64_t blk = blockIdx.x;
+    const int level = coarse_s2_level_of(g.L, g.lstart, blk);
+    const int64_t ns = (int64_t)g.n * g.n * g.n;
+    coarse_s2_body<P>(g, level, psi_lv[level], phic + (int64_t)(g.L - 1 - level) * ns, blk, sL);
 }
 
 void launch_coarse_sites(fmmkmc_ctx *c, const Geo &g)
@@ -1490,14 +1525,9 @@ void launch_coarse_sites(fmmkmc_ctx *c, const Geo &g)
     if (!c->per_level || !c->phicoarse) return;  // no coarser level with an interaction list
     const int lstart = g.lstart;
     if (c->s2) {
-        for (int l = g.L - 1; l >= lstart; --l) {
-            const int64_t orbits = (int64_t)1 << (3 * (g.L - l));
-            const size_t shm = sizeof(double) * c->nt * coarse_cells_per_block(orbits);
-            const std::string name = "coarse_s2_l" + std::to_string(l);  // per level in the kernel timings
-            FMMKMC_DISPATCH_P(c->p, launch_shm(c, name.c_str(), k_coarse_s2<P_>,
-                                               dim3((unsigned)coarse_s2_blocks(g.L, l)), dim3(kCoarseThreads), shm, g, l,
-                                               (const double *)c->psi_lv[l], l == g.L - 1 ? 1 : 0, c->phicoarse));
-        }
+        FMMKMC_DISPATCH_P(c->p, launch_shm(c, "coarse_s2", k_coarse_s2<P_>,
+                                           dim3((unsigned)coarse_s2_all_blocks(g.L, lstart)), dim3(kCoarseThreads),
+                                           coarse_s2_shm(c->p), g, (double *const *)c->d_psi_ptrs, c->phicoarse));
     } else {
         const int64_t ns = (int64_t)c->lat_n * c->lat_n * c->lat_n;
         FMMKMC_DISPATCH_P(c->p, launch(c, "coarse_sites", k_coarse_sites<P_>, dim3((unsigned)((ns + 255) / 256)),
@@ -2343,13 +2373,15 @@ __global__ __launch_bounds__(256) void k_b_coarse(const RepDev *__restrict__ rep
 
 template <int P>
 __global__ __launch_bounds__(kCoarseThreads) void k_b_coarse_s2(const RepDev *__restrict__ reps, int R,
-                                                     const int64_t *__restrict__ base, int depth)
+                                                     const int64_t *__restrict__ base)
 {
     extern __shared__ double sL[];
     const int r = find_rep(base, R, blockIdx.x);
     const RepDev &d = reps[r];
-    const int level = d.g.L - 1 - depth;
-    coarse_s2_body<P>(d.g, level, d.psi_lv[level], depth == 0 ? 1 : 0, d.phicoarse, blockIdx.x - base[r], sL);
+    int64_t blk = blockIdx.x - base[r];
+    const int level = coarse_s2_level_of(d.g.L, d.g.lstart, blk);
+    const int64_t ns = (int64_t)d.g.n * d.g.n * d.g.n;
+    coarse_s2_body<P>(d.g, level, d.psi_lv[level], d.phicoarse + (int64_t)(d.g.L - 1 - level) * ns, blk, sL);
 }
 
 void launch_b_coarse(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
@@ -2360,16 +2392,13 @@ void launch_b_coarse(Profiler &pr, hipStream_t st, const RepDev *reps, int R, co
 }
 
 void launch_b_coarse_s2(Profiler &pr, hipStream_t st, const RepDev *reps, int R, const int64_t *base, int64_t blocks,
-                        int p, int depth)
+                        int p)
 {
-    const int64_t orbits = (int64_t)1 << (3 * (1 + depth));
-    const size_t shm = sizeof(double) * (p + 1) * (p + 1) * coarse_cells_per_block(orbits);
     FMMKMC_DISPATCH_P(p, launch_prof(pr, st, "b_coarse_s2", k_b_coarse_s2<P_>, dim3((unsigned)blocks),
-                                     dim3(kCoarseThreads), shm,
-                                     reps, R, base, depth));
+                                     dim3(kCoarseThreads), coarse_s2_shm(p), reps, R, base));
 }
 
-int64_t coarse_s2_level_blocks(int L, int level) { return coarse_s2_blocks(L, level); }
+int64_t coarse_s2_replica_blocks(int L, int lstart) { return coarse_s2_all_blocks(L, lstart); }
 
 // every replica with 2 x 2 x 2 sites per fine cell: the 8-wave form of that
 // body (256 cells per block), as the single-context kernel runs it
