@@ -424,6 +424,7 @@ struct fmmkmc_batch {
     Phase coarse_s2;  // every coarse level of the 2x2x2 replicas (per-level mode)
     int slot_tc = 64, sweep_block = 256;
     bool per_level = false;  // replicas keep their local expansions per level (no sweep)
+    bool frow = false;       // some replica keeps a per-charge hop table F (periodic, expansion self terms)
     int Lmax = 0;
     int64_t slots_per_step = 0;
     // graph of one step
@@ -500,7 +501,7 @@ void record_step(fmmkmc_batch *b)
     HIPCHK(hipEventRecord(b->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
     launch_b_move_dU(b->prof, b->aux, b->reps, R, b->moves, b->acc, b->nt, 1, kMoveParts - 1, 1);
-    launch_b_frow(b->prof, b->aux, b->reps, R, b->moves, b->nt, b->K);
+    if (b->frow) launch_b_frow(b->prof, b->aux, b->reps, R, b->moves, b->nt, b->K);  // no-ops without an F table
     launch_b_path(b->prof, b->aux, b->reps, R, b->path.d, b->path.blocks, b->moves);
     launch_b_book(b->prof, b->aux, b->reps, R, b->moves);
     launch_b_far(b->prof, b->aux, b->reps, R, b->far.d, b->far.blocks, b->cheb_a.d, b->cheb_a.blocks, b->cheb_b.d,
@@ -738,7 +739,10 @@ int fmmkmc_batch_create(int n, fmmkmc_ctx *const *ctx, int K, const int32_t *off
     b->device = ctx[0]->device;
     b->mixed = ctx[0]->prec == FMMKMC_MIXED;
     b->per_level = ctx[0]->per_level != 0;
-    for (int r = 0; r < n; ++r) b->Lmax = std::max(b->Lmax, ctx[r]->L);
+    for (int r = 0; r < n; ++r) {
+        b->Lmax = std::max(b->Lmax, ctx[r]->L);
+        if (ctx[r]->bc == FMMKMC_PERIODIC && !ctx[r]->self_exact) b->frow = true;
+    }
     b->stream = (hipStream_t)stream;
     b->ctx.assign(ctx, ctx + n);
     b->offsets.assign(offsets, offsets + 3 * K);

@@ -2359,8 +2359,7 @@ __global__ __launch_bounds__(64) void k_b_frow_b(const RepDev *__restrict__ reps
 
 // per-level mode: the coarser levels at every site of every replica.  General
 // lattices: one lane per site (blocks only for such replicas); 2x2x2 lattices:
-// the orbit kernel, one launch per depth below the fine level (level L_r - 1 -
-// depth of replica r; the cells per block depend on the depth only).
+// the orbit kernel, every coarse level of every replica in one launch.
 template <int P>
 __global__ __launch_bounds__(256) void k_b_coarse(const RepDev *__restrict__ reps, int R,
                                                   const int64_t *__restrict__ base)
