@@ -1939,6 +1939,17 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
         // then the dot products over the block (every level's loads independent).
         const int l0 = g.per_level ? g.lstart : g.L, nlev = g.L - l0 + 1;
         double *Wl = sm + 256;  // [level][endpoint][nt]
+        // per level: its expansions, cell count and the cells holding t and r
+        // (the level pointers read once, beside the harmonics below)
+        __shared__ const double *s_pl[kMaxLevels + 1];
+        __shared__ int64_t s_ml[kMaxLevels + 1], s_tc[kMaxLevels + 1], s_rc[kMaxLevels + 1];
+        if ((int)threadIdx.x < nlev) {
+            const int li = threadIdx.x, l = l0 + li, side = 1 << (l - 1), sh = g.L - l;
+            s_pl[li] = l == g.L ? psi : psi_lv[l];
+            s_ml[li] = (int64_t)side * side * side;
+            s_tc[li] = cell_id(side, tcx >> sh, tcy >> sh, tcz >> sh);
+            s_rc[li] = cell_id(side, rcx >> sh, rcy >> sh, rcz >> sh);
+        }
         for (int task = threadIdx.x; task < nlev * 2 * (p + 1); task += blockDim.x) {
             const int li = task / (2 * (p + 1)), e = (task / (p + 1)) & 1, m = task % (p + 1);
             const int l = l0 + li, side = 1 << (l - 1), sh = g.L - l;
@@ -1948,15 +1959,26 @@ __device__ __forceinline__ void move_dU_body(int part_id, Geo g, int p, int64_t 
                              (e ? rz : tz) - (cz + 0.5) * w, nullptr, Wl + (int64_t)(2 * li + e) * nt);
         }
         __syncthreads();
-        for (int li = 0; li < nlev; ++li) {
-            const int l = l0 + li, side = 1 << (l - 1), sh = g.L - l;
-            const int64_t Ml = (int64_t)side * side * side;
-            const int64_t tc = cell_id(side, tcx >> sh, tcy >> sh, tcz >> sh),
-                          rc = cell_id(side, rcx >> sh, rcy >> sh, rcz >> sh);
-            const double *pl = l == g.L ? psi : psi_lv[l];
-            const double *Wt = Wl + (int64_t)(2 * li) * nt, *Wr = Wt + nt;
-            for (int k = threadIdx.x; k < nt; k += blockDim.x)
-                part += qi * (pl[(int64_t)k * Ml + tc] * Wt[k] - pl[(int64_t)k * Ml + rc] * Wr[k]);
+        // (level, coefficient) pairs over the block, four per thread in flight
+        const int ne = nlev * nt;
+        for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+            double tv[4], rv[4], wt[4], wr[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * (int)blockDim.x;
+                tv[u] = rv[u] = wt[u] = wr[u] = 0.0;
+                if (e < ne) {
+                    const int li = e / nt, k = e - li * nt;
+                    const double *pl = s_pl[li] + (int64_t)k * s_ml[li];
+                    tv[u] = pl[s_tc[li]];
+                    rv[u] = pl[s_rc[li]];
+                    wt[u] = Wl[(int64_t)(2 * li) * nt + k];
+                    wr[u] = Wl[(int64_t)(2 * li + 1) * nt + k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e0 + u * (int)blockDim.x < ne) part += qi * (tv[u] * wt[u] - rv[u] * wr[u]);
         }
         if (threadIdx.x == 0) part += qi * field_work(g, tx - rx, ty - ry, tz - rz);  // uniform field
         // self terms: one copy nu of the old position per lane, or the exact
